@@ -1,0 +1,345 @@
+"""Pins of the CPU oracle (and of the seeded inputs) against what the paper and
+the mathematics fix: closed forms, invariants, limits, exact identities, brute
+force and library routines on tiny inputs.  No GPU needed."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import rom as R
+from oracle.grid import FullOrder, Grid
+from tests import _cases
+
+
+# ----------------------------------------------------------------- grid
+def test_oracle_and_input_operators_agree():
+    """Two independent constructions of K, x (index formulas vs lookup tables)."""
+    c = _cases.magnetic10()
+    fo = c.oracle_fo()
+    assert (abs(fo.K - c.ops.K)).max() < 1e-14 * abs(fo.K).max()
+    assert np.abs(fo.x - c.ops.x).max() == 0.0
+
+
+def test_curl_of_gradient_vanishes_and_stokes():
+    g = Grid(7)
+    C = g.curl()
+    n = g.n
+    # node gradient on interior nodes
+    nid = -np.ones((n + 1,) * 3, int)
+    nodes = np.argwhere(np.ones((n - 1,) * 3, bool)) + 1
+    nid[tuple(nodes.T)] = np.arange(len(nodes))
+    rows, cols, vals = [], [], []
+    for a in range(3):
+        st = g.edge_start[a]
+        e0 = g.table[a][tuple(st.T)]
+        for nd, s in ((st + np.eye(3, dtype=int)[a], 1.0), (st, -1.0)):
+            ii = nid[tuple(nd.T)]
+            k = ii >= 0
+            rows.append(e0[k]); cols.append(ii[k]); vals.append(np.full(k.sum(), s))
+    G = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(g.N, len(nodes)))
+    assert abs(C @ G).max() == 0.0
+    # Stokes: circulation of e_i x xi round an interior face is 2 h^2 (e_i . n_f)
+    x = g.source_dofs()
+    Cx = C @ x
+    ax = g.face_normal_axis()
+    interior = np.ones(C.shape[0], bool)
+    f0 = 0
+    for a, fs in enumerate(g.face_start):
+        b, cc = (a + 1) % 3, (a + 2) % 3
+        ok = (fs[:, b] >= 1) & (fs[:, b] <= n - 2) & (fs[:, cc] >= 1) & (fs[:, cc] <= n - 2)
+        interior[f0:f0 + len(fs)] = ok
+        f0 += len(fs)
+    for i in range(3):
+        expect = 2 * g.h ** 2 * (ax == i)
+        assert np.allclose(Cx[interior, i], expect[interior], atol=1e-13)
+
+
+def test_K_symmetric_psd_and_sparsity():
+    c = _cases.ellipsoid16()
+    K = c.ops.K
+    assert abs(K - K.T).max() == 0.0
+    assert np.diff(K.indptr).max() <= 13
+    v = np.random.default_rng(0).standard_normal((K.shape[0], 4))
+    assert np.all(np.einsum("ij,ij->j", v, K @ v) >= 0)
+
+
+# ------------------------------------------------------------ snapshots
+@pytest.mark.parametrize("case", ["ellipsoid16", "magnetic10"])
+def test_snapshot_residual_and_reciprocity(case):
+    c = getattr(_cases, case)()
+    fo = c.oracle_fo()
+    K = c.snap.size
+    for k, om in enumerate(c.snap):
+        q = c.D[:, [k, K + k, 2 * K + k]]
+        r = fo.rhs(om, c.w)
+        res = r - fo.A(om) @ q
+        assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(r)
+        # complex symmetry of A: w_i^T C q_j = w_j^T C q_i
+        Mx = c.w.T @ (fo.c[:, None] * q)
+        assert np.abs(Mx - Mx.T).max() <= 1e-9 * np.abs(Mx).max()
+
+
+def test_snapshot_tensors_match_sparse_direct():
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    om = c.snap[5]
+    q_ref = fo.full_solve(om, c.w)
+    K = c.snap.size
+    q = c.D[:, [5, K + 5, 2 * K + 5]]
+    R1, I1 = R.tensors_fmm(fo, q, om, c.w, np.zeros((3, 3)))
+    R2, I2 = R.tensors_fmm(fo, q_ref, om, c.w, np.zeros((3, 3)))
+    assert np.abs(R1 - R2).max() <= 1e-9 * np.abs(R2).max()
+    assert np.abs(I1 - I2).max() <= 1e-9 * np.abs(I2).max()
+
+
+def test_theta0_magnetostatic_residual():
+    c = _cases.magnetic10()
+    fo = c.oracle_fo()
+    b = -((fo.K - fo.K1) @ c.ops.x)
+    res = b - fo.X @ c.o
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ POD
+def test_truncation_rule_examples():
+    s = np.array([1.0, 0.5, 1e-3, 1e-3 * (1 - 1e-12), 1e-7, 1e-9])
+    assert R.truncation_rank(s, 1e-6, 10) == 4  # s_5 = 1e-7 < 1e-6 dropped
+    assert R.truncation_rank(s, 1e-8, 10) == 5
+    assert R.truncation_rank(s, 1e-2, 10) == 2
+    assert R.truncation_rank(s, 1e-8, 3) == 2  # cap 3 would split the 1e-3 pair
+    assert R.truncation_rank(s, 1e-8, 4) == 4
+    assert R.truncation_rank(s, 1e-10, 99) == 6
+
+
+def test_pod_basis_reconstructs_and_is_orthonormal():
+    c = _cases.ellipsoid16()
+    U, s, M = R.pod_basis(c.D, 1e-6, 99)
+    assert np.abs(U.conj().T @ U - np.eye(M)).max() < 1e-13
+    proj = c.D - U @ (U.conj().T @ c.D)
+    assert np.linalg.norm(proj, 2) <= 1.01 * s[M] if M < s.size else True
+    # singular values squared are the eigenvalues of the Gram matrix (leading part)
+    ev = np.sort(np.linalg.eigvalsh(c.D.conj().T @ c.D))[::-1]
+    assert np.allclose(ev[:4], s[:4] ** 2, rtol=1e-10)
+
+
+# ------------------------------------------------------- sweep / tensors
+def _rom(c, M, fo=None):
+    fo = fo or c.oracle_fo()
+    U, s, _ = np.linalg.svd(c.D, full_matrices=False)
+    U = U[:, :M]
+    rom = R.project(fo.K, fo.c, fo.eps_h, c.w, U)
+    rom["N0"] = R.static_tensor_mesh(fo, c.o)
+    return fo, U, rom
+
+
+def test_mm_equals_mesh_sums():
+    """IM, FMM and MM agree up to rounding."""
+    c = _cases.ellipsoid16()
+    fo, U, rom = _rom(c, 10)
+    om = np.logspace(1, 6, 7)
+    a = R.reduced_solve(rom, om)
+    Rt, I = R.tensors_mesh(fo, U, a, om, c.w, rom["N0"])
+    Rm, Im = R.tensors_mm(rom, a, om, rom["N0"], fo.alpha)
+    for k in range(om.size):
+        Rf, If = R.tensors_fmm(fo, U @ a[k], om[k], c.w, rom["N0"])
+        assert np.abs(Rf - Rt[k]).max() <= 1e-12 * np.abs(Rt[k]).max()
+        scale_I = max(np.abs(I[k]).max(), 0.25 * fo.alpha ** 3 * om[k] * np.abs(rom["E"]).max())
+        assert np.abs(If - I[k]).max() <= 1e-12 * scale_I
+    assert np.abs(Rm - Rt).max() <= 1e-12 * np.abs(Rt).max()
+    for k in range(om.size):
+        scale_I = max(np.abs(I[k]).max(), 0.25 * fo.alpha ** 3 * om[k] * np.abs(rom["E"]).max())
+        assert np.abs(Im[k] - I[k]).max() <= 1e-12 * scale_I
+
+
+def test_untruncated_pod_reproduces_full_order_at_snapshots():
+    c = _cases.ellipsoid16()
+    fo, U, rom = _rom(c, 3 * c.snap.size)
+    a = R.reduced_solve(rom, c.snap)
+    Rt, I = R.tensors_mesh(fo, U, a, c.snap, c.w, rom["N0"])
+    K = c.snap.size
+    for k in range(K):
+        q = c.D[:, [k, K + k, 2 * K + k]]
+        Rf, If = R.tensors_fmm(fo, q, c.snap[k], c.w, rom["N0"])
+        assert np.abs(Rf - Rt[k]).max() <= 1e-10 * np.abs(Rf).max()
+        assert np.abs(If - I[k]).max() <= 1e-10 * np.abs(If).max()
+
+
+def test_sphere_tensor_is_isotropic():
+    p = _cases.sphere12()
+    fo = FullOrder(p.ops.grid.n, p.ops.sigma_e, p.ops.mu_f, p.ops.alpha, p.ops.eps)
+    U, s, M = R.pod_basis(p.D, p.wl.tol_sigma, p.M_cap)
+    rom = R.project(fo.K, fo.c, fo.eps_h, p.w, U)
+    rom["N0"] = R.static_tensor_mesh(fo, p.o)
+    om = p.omega[::25]
+    a = R.reduced_solve(rom, om)
+    Rt, I = R.tensors_mesh(fo, U, a, om, p.w, rom["N0"])
+    for T in (Rt, I):
+        sc = np.abs(T).max()
+        off = T - np.einsum("kii->ki", T)[:, :, None] * np.eye(3)
+        assert np.abs(off).max() <= 1e-12 * sc
+        d = np.einsum("kii->ki", T)
+        assert np.abs(d - d[:, :1]).max() <= 1e-12 * sc
+
+
+def test_probe_values_sphere12():
+    """Full-order values of the tiny sphere at 1e1 rad/s, from an independent
+    FEM-free computation of the same stand-in (R~11, I11)."""
+    p = _cases.sphere12()
+    fo = FullOrder(p.ops.grid.n, p.ops.sigma_e, p.ops.mu_f, p.ops.alpha, p.ops.eps)
+    q = fo.full_solve(10.0, p.w)
+    Rf, If = R.tensors_fmm(fo, q, 10.0, p.w, np.zeros((3, 3)))
+    assert abs(Rf[0, 0] - (-7.6801807e-10)) <= 1e-7 * 7.68e-10
+    assert abs(If[0, 0] - 5.85715825e-08) <= 1e-8 * 5.857e-8
+
+
+def test_definiteness_and_limits():
+    """I is PSD, R = R~ - N0 is NSD; R ~ w^2 and I ~ w at low w; I ~ 1/w at high w."""
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    N0 = R.static_tensor_mesh(fo, c.o)
+
+    def tens(om):
+        q = fo.full_solve(om, c.w)
+        return R.tensors_fmm(fo, q, om, c.w, N0)
+
+    for om in (1e2, 1e4):
+        Rt, I = tens(om)
+        assert np.linalg.eigvalsh(I).min() >= -1e-12 * np.abs(I).max()
+        assert np.linalg.eigvalsh(Rt - N0).max() <= 1e-12 * np.abs(Rt - N0).max()
+    R1, I1 = tens(1e-3)
+    R2, I2 = tens(2e-3)
+    assert np.allclose(np.diag(R2 - N0) / np.diag(R1 - N0), 4.0, rtol=1e-4)
+    assert np.allclose(np.diag(I2) / np.diag(I1), 2.0, rtol=1e-4)
+    R3, I3 = tens(1e10)
+    R4, I4 = tens(2e10)
+    d = np.diag(I4) / np.diag(I3)
+    assert np.all(np.abs(d - 0.5) < 0.02)
+
+
+def test_scaling_law_and_omega_sigma_dependence():
+    """Remark 6.2: M[s alpha B, w] = s^3 M[alpha B, s^2 w] on the same grid."""
+    c = _cases.cube10_mu()
+    o = c.ops
+    s = 1.7
+    fo1 = FullOrder(c.grid.n, o.sigma_e, o.mu_f, o.alpha, o.eps)
+    fo2 = FullOrder(c.grid.n, o.sigma_e, o.mu_f, s * o.alpha, o.eps)
+    fo3 = FullOrder(c.grid.n, 2.0 * o.sigma_e, o.mu_f, o.alpha, o.eps)
+    w = c.w  # theta0 does not depend on alpha or sigma
+    om = 3e3
+    N0a = R.static_tensor_mesh(fo1, c.o)
+    N0b = R.static_tensor_mesh(fo2, c.o)
+    Ra, Ia = R.tensors_fmm(fo1, fo1.full_solve(s * s * om, w), s * s * om, w, N0a)
+    Rb, Ib = R.tensors_fmm(fo2, fo2.full_solve(om, w), om, w, N0b)
+    assert np.abs(Rb - s ** 3 * Ra).max() <= 1e-9 * np.abs(Rb).max()
+    assert np.abs(Ib - s ** 3 * Ia).max() <= 1e-9 * np.abs(Ib).max()
+    Rc, Ic = R.tensors_fmm(fo3, fo3.full_solve(om, w), om, w, N0a)
+    Rd, Id = R.tensors_fmm(fo1, fo1.full_solve(2 * om, w), 2 * om, w, N0a)
+    assert np.abs(Rc - Rd).max() <= 1e-9 * np.abs(Rc).max()
+    assert np.abs(Ic - Id).max() <= 1e-9 * np.abs(Ic).max()
+
+
+def test_static_tensor_two_forms_and_sphere_symmetry():
+    c = _cases.magnetic10()
+    fo = c.oracle_fo()
+    N0 = R.static_tensor_mesh(fo, c.o)
+    a3 = fo.alpha ** 3
+    N0x = 0.25 * a3 * (c.ops.x.T @ ((fo.K1 - fo.K) @ c.ops.x) + c.o.T @ (fo.K @ c.o))
+    assert np.abs(N0 - N0x).max() <= 1e-12 * np.abs(N0).max()
+    assert np.abs(N0 - N0[0, 0] * np.eye(3)).max() <= 1e-10 * abs(N0[0, 0])
+    assert N0[0, 0] > 0
+    # magnetic ball of radius r_in: 3 V (mu-1)/(mu+2) alpha^3 within staircase error
+    V = 4.0 / 3.0 * np.pi * 1.0 ** 3
+    assert 0.5 < N0[0, 0] / (a3 * 3 * V * 49.0 / 52.0) < 1.5
+
+
+# --------------------------------------------------------- certificates
+def test_residual_gram_schur_equals_direct():
+    c = _cases.ellipsoid16()
+    fo, U, rom = _rom(c, 8)
+    Gd = R.residual_gram_direct(fo, U, c.w)
+    Gs = R.residual_gram_schur(c.S, c.ops.cond_idx, fo.c, c.w, U, rom["KM"], rom["UhU"], fo.eps_h)
+    # X = K + eps h I has cond ~ |K|/(eps h) ~ 1e12: two backward-stable inverses
+    # (DCT/DST here, SuperLU in the oracle) agree to eps * cond; a wrong block,
+    # sign or scale would differ at O(1).
+    assert np.abs(Gd - Gs).max() <= 1e-5 * np.abs(Gd).max()
+    assert np.abs(Gs - Gs.conj().T).max() <= 1e-14 * np.abs(Gs).max()
+
+
+def test_certificate_gform_equals_direct_residual():
+    """Lemma 4.1 evaluated from G equals the plain residual dual norm where the
+    reduced model is inaccurate enough to sit above the rounding floor."""
+    c = _cases.ellipsoid16()
+    fo, U, rom = _rom(c, 4)
+    om = np.array([3e1, 1e3, 3e4])
+    a = R.reduced_solve(rom, om)
+    Gs = R.residual_gram_schur(c.S, c.ops.cond_idx, fo.c, c.w, U, rom["KM"], rom["UhU"], fo.eps_h)
+    Dg = R.certificate_gform(Gs, a, om, fo.alpha)
+    Dd = R.certificate_direct(fo, U, a, om, c.w)
+    assert np.all(np.abs(Dg - Dd) <= 1e-4 * np.abs(Dd) + 1e-12 * np.abs(Dd).max())
+    assert np.all(Dd >= 0)
+
+
+# ------------------------------------------------------------ selection
+def test_select_snapshots_worked_example():
+    om = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 10.0])
+    snaps = np.array([1.0, 4.0, 7.0, 10.0])
+    d = np.zeros((10, 6))
+    d[1, 2] = 5.0  # interval 0 ([1,4)): max 5 at omega 2
+    d[2, 0] = 5.0  # tie inside interval 0 -> smaller omega (2) wins
+    d[4, 3] = 7.0  # interval 1 ([4,7)): 7 at omega 5
+    d[9, 5] = 6.0  # interval 2 ([7,10], closed): 6 at omega 10
+    new, lam, lam_n = R.select_snapshots(om, d, snaps, 2)
+    assert list(new) == [5.0, 10.0] and lam == 7.0
+    assert list(lam_n) == [5.0, 7.0, 6.0]
+    new1, _, _ = R.select_snapshots(om, d, snaps, 3)
+    assert list(new1) == [5.0, 10.0, 2.0]
+
+
+def test_select_snapshots_brute_force():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        om = np.sort(rng.uniform(1, 100, 50))
+        snaps = np.sort(rng.choice(om, 6, replace=False))
+        d = rng.integers(0, 4, (50, 6)).astype(float)
+        new, lam, lam_n = R.select_snapshots(om, d, snaps, 2)
+        cands = []
+        for n in range(5):
+            lo, hi = snaps[n], snaps[n + 1]
+            best = None
+            for k in range(50):
+                inside = lo <= om[k] < hi or (n == 4 and om[k] == hi)
+                if inside and (best is None or d[k].max() > d[best].max()):
+                    best = k
+            if best is not None:
+                cands.append((-d[best].max(), n, om[best]))
+        cands.sort()
+        assert list(new) == [c[2] for c in cands[:2]]
+
+
+# ---------------------------------------------------------- sensitivities
+def test_forward_sensitivity_matches_central_differences():
+    c = _cases.ellipsoid16()
+    fo, U, rom = _rom(c, 10)
+    om = np.array([50.0, 800.0, 2e4])
+    rng = np.random.default_rng(1)
+    wR = rng.standard_normal((3, 6)) * 1e6
+    wI = rng.standard_normal((3, 6)) * 1e6
+
+    def L(omega, scale=1.0):
+        r2 = dict(rom)
+        r2["CM"] = scale * rom["CM"]
+        r2["g"] = scale * rom["g"]
+        r2["E"] = scale * rom["E"]
+        a = R.reduced_solve(r2, omega)
+        Rt, I = R.tensors_mm(r2, a, omega, rom["N0"], fo.alpha)
+        return np.sum(wR * R.pack(Rt) + wI * R.pack(I))
+
+    dw, ds = R.forward_sensitivity(rom, om, fo.alpha, wR, wI)
+    for k in range(3):
+        h = 1e-6 * om[k]
+        e = np.zeros(3); e[k] = h
+        fd = (L(om + e) - L(om - e)) / (2 * h)
+        assert abs(fd - dw[k]) <= 1e-6 * abs(dw[k]) + 1e-12
+    fd_s = (L(om, 1 + 1e-6) - L(om, 1 - 1e-6)) / 2e-6
+    assert abs(fd_s - ds) <= 1e-6 * abs(ds)
+    assert abs(ds - np.sum(om * dw)) <= 1e-10 * abs(ds)
