@@ -1,0 +1,213 @@
+/*
+ * mpt.h - C ABI of libmpt: the data-parallel hot path of the adaptive POD
+ * method for magnetic polarizability tensor (MPT) spectral signatures
+ * (Elgy & Ledger, arXiv 2307.05590), built for AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every call
+ *   - All numeric arrays are device pointers owned by the caller; the library
+ *     never frees caller memory.  Scratch memory is caller-provided through
+ *     (ws, ws_bytes) arguments whose minimum size is returned by the matching
+ *     *_ws_size query (host call, no device work).
+ *   - Complex numbers are FP64 pairs (re, im) laid out like double2 /
+ *     std::complex<double>; every matrix is row-major with the stated leading
+ *     dimension.  "Hermitian" outputs are stored in full.
+ *   - Work is enqueued on the handle's HIP stream and is asynchronous unless a
+ *     call says it synchronises.  Calls on one handle must not overlap.
+ *   - Every call returns an mpt_status; on failure mpt_last_error() returns a
+ *     message that stays valid until the next call on the handle.  Argument
+ *     errors are detected on the host before any launch.
+ *
+ * Notation (the paper's): snapshot matrix D = [D_1 D_2 D_3] (Section 4.1,
+ * eq. (D)), POD basis U (eqs. (SVD), (truncSVD)), reduced system
+ * A^M(w) p = r^M(w) (eq. (ReducedA)) with A^M = A0 - i w C_M and
+ * r_i^M = i w g_i, tensors R~ = N0 + R and I (eqs. (podprealmpt),
+ * (podpimagmpt)), certificate Delta (Lemma 4.1), adaptive selection
+ * (Algorithm 1).  The regularised full-order operator is
+ * A(w) = K + eps h I - i w C_sigma (eq. (Linear)); X = K + eps h I.
+ */
+#ifndef MPT_H
+#define MPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPT_OK = 0,
+  MPT_E_ARG = 1,         /* invalid argument (shape, pointer, size) */
+  MPT_E_HIP = 2,         /* HIP runtime error */
+  MPT_E_NOMEM = 3,       /* workspace too small */
+  MPT_E_SINGULAR = 4,    /* zero or non-finite pivot in a reduced solve */
+  MPT_E_NOTPD = 5,       /* eigen-solver failed to converge */
+  MPT_E_UNSUPPORTED = 6  /* size outside what the kernels support */
+} mpt_status;
+
+typedef struct mpt_handle_s* mpt_handle;
+
+/* One handle per HIP stream (hip_stream may be NULL for the null stream). */
+mpt_status mpt_create(int device, void* hip_stream, mpt_handle* out);
+mpt_status mpt_destroy(mpt_handle h);
+mpt_status mpt_set_stream(mpt_handle h, void* hip_stream);
+const char* mpt_last_error(mpt_handle h);
+/* Largest reduced dimension M accepted by the sweep kernels. */
+int mpt_max_reduced_dim(void);
+
+/* Real sparse matrix in CSR form (sorted column indices, 0-based). */
+typedef struct {
+  int64_t n;              /* rows = columns */
+  int64_t nnz;
+  const int32_t* rowptr;  /* n + 1 */
+  const int32_t* colind;  /* nnz */
+  const double* val;      /* nnz */
+} mpt_csr;
+
+/*
+ * Reduced model of one object (all device pointers, row-major):
+ *   KM  M x M     K_M = U^H K U                      (eq. (podprealmpt))
+ *   A0  M x M     K_M + eps h U^H U                  (A^M at w = 0)
+ *   CM  M x M     C_M = U^H C_sigma U                (eq. (podpimagmpt))
+ *   g   3 x M     row i = U^H C_sigma w_i, w_i = x_i + o_i (source, r = i w g)
+ *   G   (2M+3)^2  residual Gram Z^H X^{-1} Z with
+ *                 Z = [C_sigma w_1..3 | X U | C_sigma U]     (Lemma 4.1)
+ *   E   3 x 3     w_i^T C_sigma w_j                   (the omega-independent
+ *                 I terms of (I_tensor_coeffs) under Remark 3.1)
+ *   N0  3 x 3     static tensor (eq. (NRI), first line)
+ * alpha is the object size (m); alpha_lb the stability bound of Lemma 4.1.
+ */
+typedef struct {
+  int32_t M;
+  int32_t pad_;
+  const double* KM;
+  const double* A0;
+  const double* CM;
+  const double* g;
+  const double* G;
+  const double* E;
+  const double* N0;
+  double alpha;
+  double alpha_lb;
+} mpt_rom;
+
+/* ----------------------------------------------------------------------
+ * a1  POD basis (Section 4.1, eqs. (SVD), (truncSVD); Algorithm 1 steps
+ *     "Form D_i" / "obtain the TSVDs").
+ * D: N x ncol complex (ldD >= ncol), the joint snapshot matrix
+ *    [q_1(w_1..K) | q_2(...) | q_3(...)].
+ * Thin SVD by two passes of Gram / Hermitian Jacobi eigen-decomposition /
+ * rotation (FP64 MFMA Gram), then truncation: M = #{s_m/s_1 >= tol_sigma},
+ * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
+ * a cluster).  Writes U (N x M_cap, ldU >= M_cap; columns >= M are zero),
+ * sigma (ncol, descending).  *M_out is a HOST pointer: the call synchronises
+ * the stream to return M.  ncol <= 192.
+ */
+size_t mpt_pod_basis_ws_size(int64_t N, int ncol);
+mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N, int ncol,
+                         double tol_sigma, int M_cap, double* U, int64_t ldU,
+                         double* sigma, int* M_out, void* ws, size_t ws_bytes);
+
+/* ----------------------------------------------------------------------
+ * a2  Galerkin projection (eq. (ReducedA); eqs. (podprealmpt),
+ *     (podpimagmpt); residual Gram of Lemma 4.1).
+ * K: the full-order curl-curl matrix (N x N).  c: diagonal of C_sigma (N).
+ * w: N x 3 real (x_i + o_i).  o: N x 3 real theta~^(0) DOFs or NULL (mu_r=1).
+ * vol: 3 values h^3 sum_{faces normal to e_i} (1 - 1/mu_f).
+ * U: N x M complex basis (ldU).
+ * Conductor data for the certificate: cond (n_c sorted edge indices with
+ * c > 0) and S (n_c x n_c real, row-major) = P^T X^{-1} P, the conductor
+ * block of the inverse of X = K + eps h I.
+ * Outputs (device, row-major): KM, A0, CM (M x M), g (3 x M), G
+ * ((2M+3)^2), E (3x3), N0 (3x3; alpha^3 vol_i delta_ij + alpha^3/4 o^T K o).
+ * Y (N x M complex) receives K U when non-NULL (else it lives in ws).
+ */
+size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c);
+mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                       const double* w, const double* o, const double* vol, double alpha,
+                       const double* U, int64_t ldU, int M,
+                       const int32_t* cond, int64_t n_c, const double* S,
+                       double* KM, double* A0, double* CM, double* g, double* G,
+                       double* E, double* N0, double* Y, void* ws, size_t ws_bytes);
+
+/* Sparse x tall-skinny product Y = K U (K real CSR, U complex N x M,
+ * ldU / ldY >= M).  The bandwidth-bound kernel of the projection. */
+mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU, int M,
+                    double* Y, int64_t ldY);
+
+/* ----------------------------------------------------------------------
+ * a3+a4  Online sweep (eq. (ReducedA) per frequency; eqs. (podprealmpt),
+ *     (podpimagmpt); Lemma 4.1 with ||r_i||^2 = w^(i)H G w^(i)).
+ * For each omega[k]: LU with partial pivoting of A0 - i w CM, the three
+ * solves a_i for r_i = i w g_i, then out[k*18 + p]:
+ *   p = 0..5   R~ (11,12,13,22,23,33)
+ *   p = 6..11  I  (same order)
+ *   p = 12..17 Delta (same order), w^(i) = [i w e_i ; -a_i ; i w a_i].
+ * a_out (n_omega x 3 x M complex) receives a_i when non-NULL.
+ * status[k] = 0, or MPT_E_SINGULAR when a pivot was zero / non-finite (the
+ * call then also returns MPT_E_SINGULAR after synchronising).  rom is a
+ * HOST struct holding device pointers.  1 <= M <= mpt_max_reduced_dim().
+ */
+mpt_status mpt_sweep(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n_omega,
+                     double* out, double* a_out, int32_t* status);
+
+/* ----------------------------------------------------------------------
+ * a5  Snapshot selection (Algorithm 1 selection step).
+ * omega (n, ascending), out (n x 18 from mpt_sweep; the Delta columns are
+ * used), snap (n_snap ascending).  Intervals [snap_j, snap_{j+1}), the last
+ * one closed; Lambda_j = max Delta over the interval; the n_star intervals
+ * with the largest Lambda_j (ties: lower j) each give one new frequency at
+ * their argmax (ties: smaller omega).  Device outputs: new_omega (n_star,
+ * rank order; NaN when fewer intervals hold frequencies), lambda (n_snap-1;
+ * -inf for empty intervals), Lambda_max (1).
+ */
+mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n, const double* out,
+                                const double* snap, int n_snap, int n_star,
+                                double* new_omega, double* lambda, double* Lambda_max);
+
+/* ----------------------------------------------------------------------
+ * a6  Batched dictionary sweep: one persistent launch (captured in a HIP
+ * graph when use_graph != 0) over many objects with their own M, omega
+ * count and materials.  roms: DEVICE array of n_obj mpt_rom.  omega_off
+ * (n_obj + 1, host) indexes omega / out / status: object o owns rows
+ * omega_off[o] .. omega_off[o+1]-1.  Results equal mpt_sweep object by
+ * object.  tune: NULL for the tuned defaults.
+ */
+typedef struct {
+  int32_t omegas_per_item;   /* frequencies per work item (>= 1) */
+  int32_t waves_per_group;   /* 1, 2 or 4 */
+  int32_t groups_per_cu;     /* persistent groups per compute unit */
+  int32_t reserved;
+} mpt_tuning;
+
+mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host, const mpt_rom* roms_dev,
+                             int n_obj, const int64_t* omega_off, const double* omega,
+                             double* out, int32_t* status, const mpt_tuning* tune,
+                             int use_graph);
+
+/* ----------------------------------------------------------------------
+ * a7  Adjoint of the sweep (differentiated signature).
+ * Given upstream gradients dout (n x 18; the Delta columns are ignored) of a
+ * scalar L with respect to the sweep outputs, computes dL/domega[k] by an
+ * adjoint reduced solve A^H lambda_i = dL/d(conj a_i) re-using the LU of
+ * A (recomputed here; nothing is kept between calls), and
+ * sig_dsig = sigma_* dL/dsigma_* (one value) for a single conductivity
+ * that scales C_sigma, g and E with the basis frozen.
+ * Same sizes and rom rules as mpt_sweep.
+ */
+mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n,
+                             const double* dout, double* dL_domega, double* sig_dsig,
+                             int32_t* status);
+
+/* Batched adjoint over a dictionary (same layout as mpt_sweep_batched);
+ * sig_dsig has one value per object. */
+mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
+                                     const mpt_rom* roms_dev, int n_obj,
+                                     const int64_t* omega_off, const double* omega,
+                                     const double* dout, double* dL_domega, double* sig_dsig,
+                                     int32_t* status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPT_H */

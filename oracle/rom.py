@@ -134,7 +134,8 @@ def tensors_mm(rom, a, omega, N0, alpha):
 def residual_gram_direct(fo, U, w):
     """G = Z^H X^{-1} Z with Z = [C w_1, C w_2, C w_3, X U, C U] (SuperLU for X^{-1})."""
     Z = np.concatenate([fo.c[:, None] * w, fo.X @ U, fo.c[:, None] * U], 1).astype(np.complex128)
-    return Z.conj().T @ fo.X_solve(Z)
+    G = Z.conj().T @ fo.X_solve(Z)
+    return 0.5 * (G + G.conj().T)  # Hermitian by definition
 
 
 def residual_gram_schur(S, cond_idx, c, w, U, KM, UhU, eps_h):
@@ -149,7 +150,8 @@ def residual_gram_schur(S, cond_idx, c, w, U, KM, UhU, eps_h):
     G = np.zeros((2 * M + 3, 2 * M + 3), np.complex128)
     wc = np.r_[0:3, 3 + M:3 + 2 * M]  # positions of the conductor-supported columns
     xs = np.arange(3, 3 + M)
-    G[np.ix_(wc, wc)] = Zc.conj().T @ (S @ Zc)
+    Gc = Zc.conj().T @ (S @ Zc)
+    G[np.ix_(wc, wc)] = 0.5 * (Gc + Gc.conj().T)  # Hermitian by definition
     ZU = Zc.conj().T @ U[cond_idx]
     G[np.ix_(wc, xs)] = ZU
     G[np.ix_(xs, wc)] = ZU.conj().T

@@ -1,0 +1,672 @@
+// C ABI of libmpt: handles, argument validation, and the orchestration of the
+// POD basis (a1), Galerkin projection (a2), sweep (a3+a4), selection (a5),
+// batched persistent sweep in a HIP graph (a6) and adjoint sweep (a7).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_util.h"
+#include "kernels.h"
+
+struct mpt_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_cu = 256;
+  // library-owned buffers for the batched path (work items, counters, offsets)
+  void* buf = nullptr;      // batched work items / counters (referenced by the graph)
+  size_t buf_bytes = 0;
+  void* scr = nullptr;      // scratch of the single-object calls
+  size_t scr_bytes = 0;
+  int* host_M = nullptr;  // pinned
+  // cached graph of the last batched launch
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;
+  hipStream_t cap = nullptr;  // private stream used only to record graphs
+};
+
+namespace {
+
+mpt_status fail(mpt_handle h, mpt_status s, const std::string& m) {
+  if (h) h->err = m;
+  return s;
+}
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(h, MPT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define ARG(cond, msg)                                  \
+  do {                                                  \
+    if (!(cond)) return fail(h, MPT_E_ARG, (msg));      \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+mpt_status ensure_buf(mpt_handle h, size_t bytes) {
+  if (h->buf_bytes >= bytes) return MPT_OK;
+  if (h->buf) {
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipFree(h->buf));
+    h->buf = nullptr;
+    h->buf_bytes = 0;
+  }
+  if (h->gexec) {  // the cached graph points into the old buffer
+    HIP_OK(hipGraphExecDestroy(h->gexec));
+    h->gexec = nullptr;
+    h->gkey.clear();
+  }
+  HIP_OK(hipMalloc(&h->buf, bytes));
+  h->buf_bytes = bytes;
+  return MPT_OK;
+}
+
+mpt_status ensure_scr(mpt_handle h, size_t bytes) {
+  if (h->scr_bytes >= bytes) return MPT_OK;
+  if (h->scr) {
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipFree(h->scr));
+    h->scr = nullptr;
+    h->scr_bytes = 0;
+  }
+  HIP_OK(hipMalloc(&h->scr, bytes));
+  h->scr_bytes = bytes;
+  return MPT_OK;
+}
+
+mpt_status check_rom(mpt_handle h, const mpt_rom* R) {
+  ARG(R != nullptr, "rom is NULL");
+  ARG(R->M >= 1 && R->M <= 64, "rom M must be in [1, 64]");
+  ARG(R->KM && R->A0 && R->CM && R->g && R->G && R->E && R->N0, "rom has a NULL matrix");
+  ARG(R->alpha > 0.0 && R->alpha_lb > 0.0, "rom alpha and alpha_lb must be positive");
+  return MPT_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- small kernels
+namespace mpt {
+
+// sort eigenvalues (descending), singular values, truncation rank and the
+// scaled rotation W (m x Mcap): W[:, j] = V[:, idx_j] / sigma_j for j < M
+__global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __restrict__ V, int m,
+                               double tol, int Mcap, double* __restrict__ sigma,
+                               double2* __restrict__ W, int* __restrict__ Mout) {
+  __shared__ int idx[192];
+  __shared__ double sv[192];
+  __shared__ int Msh;
+  const int t = threadIdx.x;
+  if (t < m) {
+    const double li = lam[t];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = lam[j];
+      if (lj > li || (lj == li && j < t)) ++rank;
+    }
+    idx[rank] = t;
+    sv[rank] = sqrt(fmax(li, 0.0));
+  }
+  __syncthreads();
+  if (t == 0) {
+    int M = 0;
+    const double s1 = sv[0];
+    if (s1 > 0.0)
+      for (int j = 0; j < m; ++j)
+        if (sv[j] / s1 >= tol) ++M;
+    M = min(M, min(Mcap, m));
+    while (M > 0 && M < m && sv[M] / sv[M - 1] > 1.0 - 1e-8) --M;
+    Msh = M;
+    *Mout = M;
+  }
+  __syncthreads();
+  if (t < m) sigma[t] = sv[t];
+  for (int e = t; e < m * Mcap; e += blockDim.x) {
+    const int r = e / Mcap, j = e % Mcap;
+    double2 v = make_double2(0.0, 0.0);
+    if (j < Msh) {
+      const double2 x = V[r * m + idx[j]];
+      const double inv = 1.0 / sv[j];
+      v = make_double2(x.x * inv, x.y * inv);
+    }
+    W[r * Mcap + j] = v;
+  }
+}
+
+// Zc = [c w (3) | c U (M)] and Uc = U[cond] (n_c rows); also wc (real w, 3)
+__global__ void k_gather_cond(const int32_t* __restrict__ cond, int64_t nc,
+                              const double* __restrict__ c, const double* __restrict__ w,
+                              const double2* __restrict__ U, int64_t ldU, int M,
+                              double2* __restrict__ Zc, double2* __restrict__ Uc,
+                              double2* __restrict__ Wc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = nc * (M + 3);
+  if (e >= tot) return;
+  const int64_t r = e / (M + 3);
+  const int j = (int)(e % (M + 3));
+  const int64_t row = cond[r];
+  const double cc = c[row];
+  if (j < 3) {
+    const double wv = w[row * 3 + j];
+    Zc[r * (M + 3) + j] = make_double2(cc * wv, 0.0);
+    Wc[r * 3 + j] = make_double2(wv, 0.0);
+  } else {
+    const double2 u = U[row * ldU + (j - 3)];
+    Zc[r * (M + 3) + j] = make_double2(cc * u.x, cc * u.y);
+    Uc[r * M + (j - 3)] = u;
+  }
+}
+
+// real N x 3 -> complex N x 3
+__global__ void k_real_to_complex(const double* __restrict__ x, int64_t cnt,
+                                  double2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) y[i] = make_double2(x[i], 0.0);
+}
+
+// assemble A0, CM, g, G, E, N0 from the small contractions
+//   KM (M x M), UhU (M x M), Gc ((M+3)^2 = Zc^H S Zc), P (M x (M+3) = Uc^H Zc),
+//   Ew (3 x 3 complex = Wc^H (c w)), No (3 x 3 complex = o^H K o or NULL)
+__global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KM,
+                           const double2* __restrict__ UhU, const double2* __restrict__ Gc,
+                           const double2* __restrict__ P, const double2* __restrict__ Ew,
+                           const double2* __restrict__ No, const double* __restrict__ vol,
+                           double alpha, double2* __restrict__ A0, double2* __restrict__ CM,
+                           double2* __restrict__ g, double2* __restrict__ G,
+                           double* __restrict__ E, double* __restrict__ N0) {
+  const int L = 2 * M + 3;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nthreads = gridDim.x * blockDim.x;
+  // position maps: G index -> (block, local)
+  for (int e = tid; e < L * L; e += nthreads) {
+    const int a = e / L, b = e % L;
+    // classify: w (0..2), x (3..3+M), c (3+M..)
+    auto cls = [&](int i, int& loc) {
+      if (i < 3) { loc = i; return 0; }
+      if (i < 3 + M) { loc = i - 3; return 1; }
+      loc = i - 3 - M; return 2;
+    };
+    int la, lb;
+    const int ca = cls(a, la), cb = cls(b, lb);
+    double2 v;
+    const int LG = M + 3;  // Gc / Zc column index: w -> 0..2, c -> 3..
+    if (ca != 1 && cb != 1) {
+      // Z^H X^{-1} Z is Hermitian: average the two computed triangles
+      const int ia = ca == 0 ? la : 3 + la, ib = cb == 0 ? lb : 3 + lb;
+      const double2 u = Gc[ia * LG + ib], t = Gc[ib * LG + ia];
+      v = make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
+    } else if (ca == 1 && cb == 1) {
+      const double2 k = KM[la * M + lb], u = UhU[la * M + lb];
+      v = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
+    } else if (ca == 1) {  // x row, w/c column: (X U)^H X^{-1} Z = U^H Z = P
+      const int ib = cb == 0 ? lb : 3 + lb;
+      v = P[la * LG + ib];
+    } else {  // w/c row, x column: conj(P)^T
+      const int ia = ca == 0 ? la : 3 + la;
+      v = cconj(P[lb * LG + ia]);
+    }
+    G[e] = v;
+  }
+  for (int e = tid; e < M * M; e += nthreads) {
+    const int i = e / M, j = e % M;
+    const double2 k = KM[e], u = UhU[e];
+    A0[e] = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
+    CM[e] = P[i * (M + 3) + 3 + j];
+  }
+  for (int e = tid; e < 3 * M; e += nthreads) {
+    const int i = e / M, m = e % M;
+    g[e] = P[m * (M + 3) + i];  // g_i[m] = (Uc^H c w_i)[m]
+  }
+  if (tid < 9) {
+    const int i = tid / 3, j = tid % 3;
+    E[tid] = Ew[tid].x;
+    const double a3 = alpha * alpha * alpha;
+    double n0 = (i == j) ? a3 * vol[i] : 0.0;
+    if (No) n0 += 0.25 * a3 * No[tid].x;
+    N0[tid] = n0;
+  }
+}
+
+}  // namespace mpt
+
+using namespace mpt;
+
+// ------------------------------------------------------------------- handle
+extern "C" mpt_status mpt_create(int device, void* hip_stream, mpt_handle* out) {
+  mpt_handle h = nullptr;
+  if (!out) return MPT_E_ARG;
+  h = new mpt_handle_s();
+  h->device = device;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete h;
+    return MPT_E_HIP;
+  }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      ncu > 0)
+    h->n_cu = ncu;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->host_M), sizeof(int), 0) != hipSuccess) {
+    delete h;
+    return MPT_E_HIP;
+  }
+  *out = h;
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_destroy(mpt_handle h) {
+  if (!h) return MPT_E_ARG;
+  hipSetDevice(h->device);
+  if (h->stream) hipStreamSynchronize(h->stream);
+  else hipDeviceSynchronize();
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->cap) hipStreamDestroy(h->cap);
+  if (h->buf) hipFree(h->buf);
+  if (h->scr) hipFree(h->scr);
+  if (h->host_M) hipHostFree(h->host_M);
+  delete h;
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_set_stream(mpt_handle h, void* hip_stream) {
+  if (!h) return MPT_E_ARG;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return MPT_OK;
+}
+
+extern "C" const char* mpt_last_error(mpt_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+extern "C" int mpt_max_reduced_dim(void) { return 64; }
+
+// ------------------------------------------------------------------ a1 POD
+static void pod_layout(int64_t N, int m, size_t* off) {
+  // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 end
+  size_t o = 0;
+  off[0] = o; o = align256(o + (size_t)m * m * 16);
+  off[1] = o; o = align256(o + (size_t)m * m * 16);
+  off[2] = o; o = align256(o + (size_t)m * 8);
+  off[3] = o; o = align256(o + (size_t)N * m * 16);
+  off[4] = o; o = align256(o + gram_ws_size(N, m, m));
+  off[5] = o; o = align256(o + (size_t)m * 192 * 16);
+  off[6] = o; o = align256(o + 64);
+  off[7] = o; o = align256(o + 64);
+  off[8] = o;
+}
+
+extern "C" size_t mpt_pod_basis_ws_size(int64_t N, int ncol) {
+  if (N <= 0 || ncol <= 0) return 0;
+  size_t off[9];
+  pod_layout(N, ncol, off);
+  return off[8];
+}
+
+extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N,
+                                    int ncol, double tol_sigma, int M_cap, double* U, int64_t ldU,
+                                    double* sigma, int* M_out, void* ws, size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(D && U && sigma && M_out && ws, "NULL pointer");
+  ARG(N > 0 && ncol >= 1 && ncol <= 192, "need N > 0 and 1 <= ncol <= 192");
+  ARG(ldD >= ncol && ldU >= M_cap && M_cap >= 1, "bad leading dimension or M_cap");
+  ARG(tol_sigma >= 0.0 && tol_sigma < 1.0, "tol_sigma must be in [0, 1)");
+  ARG(ws_bytes >= mpt_pod_basis_ws_size(N, ncol), "workspace too small");
+  HIP_OK(hipSetDevice(h->device));
+  const int m = ncol;
+  const int Mc = std::min(M_cap, m);
+  size_t off[9];
+  pod_layout(N, m, off);
+  char* w = reinterpret_cast<char*>(ws);
+  double* G0 = reinterpret_cast<double*>(w + off[0]);
+  double* V0 = reinterpret_cast<double*>(w + off[1]);
+  double* lam = reinterpret_cast<double*>(w + off[2]);
+  double* Q1 = reinterpret_cast<double*>(w + off[3]);
+  void* gws = w + off[4];
+  double* W = reinterpret_cast<double*>(w + off[5]);
+  int* info = reinterpret_cast<int*>(w + off[6]);
+  int* Mdev = reinterpret_cast<int*>(w + off[7]);
+  hipStream_t st = h->stream;
+  // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
+  HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info, st));
+  HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
+  // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
+  HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, st));
+  hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
+                     reinterpret_cast<const double2*>(V0), m, tol_sigma, Mc, sigma,
+                     reinterpret_cast<double2*>(W), Mdev);
+  HIP_OK(hipGetLastError());
+  // U = Q1 W (columns >= M are zero); remaining columns up to M_cap cleared
+  HIP_OK(rotate_launch(Q1, m, N, m, W, Mc, Mc, U, ldU, st));
+  if (M_cap > Mc) HIP_OK(hipMemset2DAsync(reinterpret_cast<char*>(U) + (size_t)Mc * 16, ldU * 16, 0,
+                                          (size_t)(M_cap - Mc) * 16, N, st));
+  HIP_OK(hipMemcpyAsync(h->host_M, Mdev, sizeof(int), hipMemcpyDeviceToHost, st));
+  int hinfo[2] = {0, 0};
+  HIP_OK(hipMemcpyAsync(hinfo, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *M_out = *h->host_M;
+  if (hinfo[0] < 0 || hinfo[1] < 0) return fail(h, MPT_E_NOTPD, "Jacobi did not converge");
+  return MPT_OK;
+}
+
+// ---------------------------------------------------------- a2 projection
+static void proj_layout(int64_t N, int M, int64_t nc, size_t* off) {
+  const int L = M + 3;
+  const int64_t gN = std::max<int64_t>(N, nc);
+  size_t o = 0;
+  off[0] = o; o = align256(o + (size_t)N * M * 16);         // Y (when not given)
+  off[1] = o; o = align256(o + (size_t)M * M * 16);         // UhU
+  off[2] = o; o = align256(o + (size_t)nc * L * 16);        // Zc
+  off[3] = o; o = align256(o + (size_t)nc * M * 16);        // Uc
+  off[4] = o; o = align256(o + (size_t)nc * L * 16);        // T = S Zc
+  off[5] = o; o = align256(o + (size_t)L * L * 16);         // Gc
+  off[6] = o; o = align256(o + (size_t)M * L * 16);         // P
+  off[7] = o; o = align256(o + (size_t)nc * 3 * 16);        // Wc
+  off[8] = o; o = align256(o + 9 * 16);                     // Ew
+  off[9] = o; o = align256(o + (size_t)N * 3 * 16);         // Oc (o as complex)
+  off[10] = o; o = align256(o + (size_t)N * 3 * 16);        // KO
+  off[11] = o; o = align256(o + 9 * 16);                    // No
+  off[12] = o;
+  o = align256(o + std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)));
+  off[13] = o;
+}
+
+extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c) {
+  if (N <= 0 || M <= 0) return 0;
+  size_t off[14];
+  proj_layout(N, M, n_c, off);
+  return off[13];
+}
+
+extern "C" mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU,
+                               int M, double* Y, int64_t ldY) {
+  if (!h) return MPT_E_ARG;
+  ARG(K && K->rowptr && K->colind && K->val && U && Y, "NULL pointer");
+  ARG(K->n > 0 && K->nnz >= 0 && K->nnz < (int64_t)1 << 31, "bad CSR sizes");
+  ARG(M >= 1 && ldU >= M && ldY >= M, "bad M or leading dimensions");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(spmm_launch(*K, U, ldU, M, Y, ldY, h->stream));
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                                  const double* w, const double* o, const double* vol,
+                                  double alpha, const double* U, int64_t ldU, int M,
+                                  const int32_t* cond, int64_t n_c, const double* S, double* KM,
+                                  double* A0, double* CM, double* g, double* G, double* E,
+                                  double* N0, double* Y, void* ws, size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && S, "NULL input");
+  ARG(KM && A0 && CM && g && G && E && N0 && ws, "NULL output");
+  ARG(K->n > 0 && M >= 1 && ldU >= M && n_c >= 1 && n_c <= K->n, "bad sizes");
+  ARG(eps_h >= 0.0 && alpha > 0.0, "bad eps_h or alpha");
+  ARG(ws_bytes >= mpt_project_ws_size(K->n, M, n_c), "workspace too small");
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const int64_t N = K->n;
+  const int L = M + 3;
+  size_t off[14];
+  proj_layout(N, M, n_c, off);
+  char* wsb = reinterpret_cast<char*>(ws);
+  double* Yb = Y ? Y : reinterpret_cast<double*>(wsb + off[0]);
+  const int64_t ldY = M;
+  double* UhU = reinterpret_cast<double*>(wsb + off[1]);
+  double* Zc = reinterpret_cast<double*>(wsb + off[2]);
+  double* Uc = reinterpret_cast<double*>(wsb + off[3]);
+  double* T = reinterpret_cast<double*>(wsb + off[4]);
+  double* Gc = reinterpret_cast<double*>(wsb + off[5]);
+  double* P = reinterpret_cast<double*>(wsb + off[6]);
+  double* Wc = reinterpret_cast<double*>(wsb + off[7]);
+  double* Ew = reinterpret_cast<double*>(wsb + off[8]);
+  double* Oc = reinterpret_cast<double*>(wsb + off[9]);
+  double* KO = reinterpret_cast<double*>(wsb + off[10]);
+  double* No = reinterpret_cast<double*>(wsb + off[11]);
+  void* gws = wsb + off[12];
+
+  // Y = K U; K_M = U^H Y; U^H U
+  HIP_OK(spmm_launch(*K, U, ldU, M, Yb, ldY, st));
+  HIP_OK(gram_launch(U, ldU, Yb, ldY, N, M, M, KM, M, gws, st));
+  HIP_OK(gram_launch(U, ldU, U, ldU, N, M, M, UhU, M, gws, st));
+  // conductor block: Zc = [c w | c U], T = S Zc, Gc = Zc^H T, P = Uc^H Zc
+  {
+    const int64_t tot = n_c * L;
+    hipLaunchKernelGGL(k_gather_cond, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, cond,
+                       n_c, c, w, reinterpret_cast<const double2*>(U), ldU, M,
+                       reinterpret_cast<double2*>(Zc), reinterpret_cast<double2*>(Uc),
+                       reinterpret_cast<double2*>(Wc));
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(real_complex_gemm(S, n_c, Zc, L, T, st));
+  HIP_OK(gram_launch(Zc, L, T, L, n_c, L, L, Gc, L, gws, st));
+  HIP_OK(gram_launch(Uc, M, Zc, L, n_c, M, L, P, L, gws, st));
+  HIP_OK(gram_launch(Wc, 3, Zc, L, n_c, 3, 3, Ew, 3, gws, st));
+  // static tensor: o^H K o
+  const double2* Nop = nullptr;
+  if (o) {
+    const int64_t cnt = N * 3;
+    hipLaunchKernelGGL(k_real_to_complex, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, o,
+                       cnt, reinterpret_cast<double2*>(Oc));
+    HIP_OK(hipGetLastError());
+    HIP_OK(spmm_launch(*K, Oc, 3, 3, KO, 3, st));
+    HIP_OK(gram_launch(Oc, 3, KO, 3, N, 3, 3, No, 3, gws, st));
+    Nop = reinterpret_cast<const double2*>(No);
+  }
+  hipLaunchKernelGGL(k_assemble, dim3(64), dim3(256), 0, st, M, eps_h,
+                     reinterpret_cast<const double2*>(KM), reinterpret_cast<const double2*>(UhU),
+                     reinterpret_cast<const double2*>(Gc), reinterpret_cast<const double2*>(P),
+                     reinterpret_cast<const double2*>(Ew), Nop, vol, alpha,
+                     reinterpret_cast<double2*>(A0), reinterpret_cast<double2*>(CM),
+                     reinterpret_cast<double2*>(g), reinterpret_cast<double2*>(G), E, N0);
+  HIP_OK(hipGetLastError());
+  return MPT_OK;
+}
+
+// ------------------------------------------------------------ a3+a4 sweep
+extern "C" mpt_status mpt_sweep(mpt_handle h, const mpt_rom* rom, const double* omega,
+                                int64_t n_omega, double* out, double* a_out, int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  ARG(n_omega >= 0, "n_omega < 0");
+  ARG(n_omega == 0 || (omega && out && status), "NULL omega/out/status");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(sweep_launch(*rom, omega, n_omega, out, a_out, status, nullptr, nullptr, h->stream));
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* omega,
+                                        int64_t n, const double* dout, double* dL_domega,
+                                        double* sig_dsig, int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  ARG(n >= 1, "n must be >= 1");
+  ARG(omega && dout && dL_domega && sig_dsig && status, "NULL pointer");
+  HIP_OK(hipSetDevice(h->device));
+  // scratch for the (discarded) forward outputs and the object offsets
+  const size_t need = align256((size_t)n * 18 * 8) + 256;
+  s = ensure_scr(h, need);
+  if (s != MPT_OK) return s;
+  double* fwd = reinterpret_cast<double*>(h->scr);
+  int64_t* offd = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(h->scr) +
+                                             align256((size_t)n * 18 * 8));
+  const int64_t offh[2] = {0, n};
+  HIP_OK(hipMemcpyAsync(offd, offh, sizeof(offh), hipMemcpyHostToDevice, h->stream));
+  HIP_OK(sweep_launch(*rom, omega, n, fwd, nullptr, status, dout, dL_domega, h->stream));
+  HIP_OK(sigma_reduce(omega, dL_domega, offd, 1, sig_dsig, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));  // offh is a host stack array
+  return MPT_OK;
+}
+
+// -------------------------------------------------------------- a5 select
+extern "C" mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n,
+                                           const double* out, const double* snap, int n_snap,
+                                           int n_star, double* new_omega, double* lambda,
+                                           double* Lambda_max) {
+  if (!h) return MPT_E_ARG;
+  ARG(omega && out && snap && new_omega && lambda && Lambda_max, "NULL pointer");
+  ARG(n >= 1 && n_snap >= 2 && n_star >= 1 && n_star <= 64, "bad sizes");
+  HIP_OK(hipSetDevice(h->device));
+  mpt_status s = ensure_scr(h, align256((size_t)n_snap * 8));
+  if (s != MPT_OK) return s;
+  HIP_OK(select_launch(omega, n, out, snap, n_snap, n_star, new_omega, lambda, Lambda_max,
+                       reinterpret_cast<int64_t*>(h->scr), h->stream));
+  return MPT_OK;
+}
+
+// -------------------------------------------------- a6/a7 batched launches
+namespace {
+
+double sweep_cost(int M) { return 2.67 * M * M * M + 172.0 * M * M; }
+
+struct Plan {
+  std::vector<int4> items[4];
+};
+
+mpt_status build_plan(mpt_handle h, const mpt_rom* roms_host, int n_obj, const int64_t* off,
+                      int per_item, Plan& plan) {
+  for (int o = 0; o < n_obj; ++o) {
+    mpt_status s = check_rom(h, &roms_host[o]);
+    if (s != MPT_OK) return s;
+    ARG(off[o + 1] >= off[o], "omega_off must be non-decreasing");
+    const int b = bucket_of(roms_host[o].M);
+    const int bi = b == 16 ? 0 : (b == 32 ? 1 : (b == 48 ? 2 : 3));
+    for (int64_t k = off[o]; k < off[o + 1]; k += per_item) {
+      const int cnt = (int)std::min<int64_t>(per_item, off[o + 1] - k);
+      plan.items[bi].push_back(make_int4(o, (int)k, cnt, roms_host[o].M));
+    }
+  }
+  for (auto& v : plan.items)
+    std::stable_sort(v.begin(), v.end(), [](const int4& a, const int4& b) {
+      return sweep_cost(a.w) * a.z > sweep_cost(b.w) * b.z;
+    });
+  return MPT_OK;
+}
+
+mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom* roms_dev,
+                          int n_obj, const int64_t* omega_off, const double* omega, double* out,
+                          int32_t* status, const mpt_tuning* tune, int use_graph,
+                          const double* dout, double* dom, double* sig) {
+  ARG(roms_host && roms_dev && omega_off && omega && status && n_obj >= 1, "NULL or empty");
+  ARG(out || dout, "NULL out");
+  HIP_OK(hipSetDevice(h->device));
+  mpt_tuning t = {8, 4, 2, 0};
+  if (tune) t = *tune;
+  ARG(t.omegas_per_item >= 1 && (t.waves_per_group == 1 || t.waves_per_group == 2 ||
+                                 t.waves_per_group == 4) && t.groups_per_cu >= 1,
+      "bad tuning");
+  const bool adj = dout != nullptr;
+  Plan plan;
+  mpt_status s = build_plan(h, roms_host, n_obj, omega_off, t.omegas_per_item, plan);
+  if (s != MPT_OK) return s;
+  size_t nitems = 0;
+  for (auto& v : plan.items) nitems += v.size();
+  const int64_t n_tot = omega_off[n_obj];
+  const size_t items_bytes = align256(nitems * sizeof(int4));
+  const size_t cnt_off = items_bytes;
+  const size_t off_off = cnt_off + 256;
+  const size_t fwd_off = off_off + align256((size_t)(n_obj + 1) * 8);
+  const size_t need = fwd_off + (adj ? align256((size_t)n_tot * 18 * 8) : 0);
+  // graph cache key
+  std::vector<int64_t> key = {(int64_t)roms_dev, (int64_t)omega, (int64_t)out, (int64_t)status,
+                              (int64_t)dout, (int64_t)dom, (int64_t)sig, n_obj,
+                              t.omegas_per_item, t.waves_per_group, t.groups_per_cu, adj};
+  for (auto& v : plan.items) key.push_back((int64_t)v.size());
+  for (int o = 0; o <= n_obj; ++o) key.push_back(omega_off[o]);
+  for (int o = 0; o < n_obj; ++o) key.push_back(roms_host[o].M);
+  const bool cached = use_graph && h->gexec && key == h->gkey && h->buf_bytes >= need;
+  if (!cached) {
+    s = ensure_buf(h, need);
+    if (s != MPT_OK) return s;
+    std::vector<int4> all;
+    all.reserve(nitems);
+    for (auto& v : plan.items) all.insert(all.end(), v.begin(), v.end());
+    char* b = reinterpret_cast<char*>(h->buf);
+    HIP_OK(hipMemcpyAsync(b, all.data(), nitems * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(b + off_off, omega_off, (size_t)(n_obj + 1) * 8, hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
+  }
+  char* b = reinterpret_cast<char*>(h->buf);
+  const int4* items = reinterpret_cast<const int4*>(b);
+  unsigned int* counters = reinterpret_cast<unsigned int*>(b + cnt_off);
+  const int64_t* offd = reinterpret_cast<const int64_t*>(b + off_off);
+  double* outp = adj ? reinterpret_cast<double*>(b + fwd_off) : out;
+  auto enqueue = [&](hipStream_t st) -> hipError_t {
+    hipError_t e = reset_counters(counters, 4, st);
+    if (e != hipSuccess) return e;
+    size_t base = 0;
+    const int buckets[4] = {16, 32, 48, 64};
+    for (int bi = 0; bi < 4; ++bi) {
+      const int ni = (int)plan.items[bi].size();
+      if (ni) {
+        const int wpg = (adj && buckets[bi] >= 48) ? std::min(2, t.waves_per_group) : t.waves_per_group;
+        int groups = h->n_cu * t.groups_per_cu;
+        groups = std::max(1, std::min(groups, (ni + wpg - 1) / wpg));
+        e = persistent_launch(buckets[bi], adj, roms_dev, items + base, ni, counters + bi, omega,
+                              outp, status, dout, dom, wpg, groups, st);
+        if (e != hipSuccess) return e;
+      }
+      base += ni;
+    }
+    if (adj) e = sigma_reduce(omega, dom, offd, n_obj, sig, st);
+    return e;
+  };
+  if (!use_graph) {
+    HIP_OK(enqueue(h->stream));
+    return MPT_OK;
+  }
+  if (!cached) {
+    if (h->gexec) {
+      HIP_OK(hipGraphExecDestroy(h->gexec));
+      h->gexec = nullptr;
+    }
+    // record on a private stream (the caller's may be the null stream, which
+    // cannot be captured); the instantiated graph is launched on the caller's
+    if (!h->cap) HIP_OK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue(h->cap);
+    hipError_t e2 = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(h, MPT_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(h, MPT_E_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+    HIP_OK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    HIP_OK(hipGraphDestroy(g));
+    h->gkey = key;
+  }
+  HIP_OK(hipGraphLaunch(h->gexec, h->stream));
+  return MPT_OK;
+}
+
+}  // namespace
+
+extern "C" mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host,
+                                        const mpt_rom* roms_dev, int n_obj,
+                                        const int64_t* omega_off, const double* omega, double* out,
+                                        int32_t* status, const mpt_tuning* tune, int use_graph) {
+  if (!h) return MPT_E_ARG;
+  ARG(out != nullptr, "NULL out");
+  return batched_common(h, roms_host, roms_dev, n_obj, omega_off, omega, out, status, tune,
+                        use_graph, nullptr, nullptr, nullptr);
+}
+
+extern "C" mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
+                                                const mpt_rom* roms_dev, int n_obj,
+                                                const int64_t* omega_off, const double* omega,
+                                                const double* dout, double* dL_domega,
+                                                double* sig_dsig, int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  ARG(dout && dL_domega && sig_dsig, "NULL adjoint pointer");
+  return batched_common(h, roms_host, roms_dev, n_obj, omega_off, omega, nullptr, status, nullptr,
+                        1, dout, dL_domega, sig_dsig);
+}

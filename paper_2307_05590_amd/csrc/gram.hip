@@ -1,0 +1,234 @@
+// Dense complex contractions on FP64 MFMA (v_mfma_f64_16x16x4f64):
+//   gram:   P = A^H B over N rows (split-N partials + fixed-order reduction)
+//   rotate: C = A V  (tall x small)
+//   rcgemm: T = S Z  (small real x complex)
+// Complex products use four real MFMAs (re.re, im.im, re.im, im.re).
+//
+// Operand layout of the 16x16x4 f64 MFMA for lane l (0..63):
+//   a: A[l % 16][l / 16]   b: B[l / 16][l % 16]
+//   d: D[(l / 16) + 4 * v][l % 16], v = 0..3   (checked on gfx950)
+#include <type_traits>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace mpt {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGramRows = 1024;  // rows per partial
+
+// grid: x = row chunk, y = wave-task group (4 waves per group);
+// wave-task t -> tile row I = t / JG, tile column group jg = t % JG (4 tiles)
+__global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict__ A, int64_t lda,
+                                                      const double2* __restrict__ B, int64_t ldb,
+                                                      int64_t N, int m, int n,
+                                                      double2* __restrict__ part) {
+  const int lane = __lane_id();
+  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int task = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (task >= TI * JG) return;
+  const int I = task / JG, jg = task % JG;
+  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+  const int64_t r1 = min(N, r0 + kGramRows);
+  const int ar = I * 16 + (lane & 15);  // column of A feeding this lane
+  const bool aok = ar < m;
+  double4_t accr[4], acci[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    accr[t] = double4_t{0, 0, 0, 0};
+    acci[t] = double4_t{0, 0, 0, 0};
+  }
+  for (int64_t k0 = r0; k0 < r1; k0 += 4) {
+    const int64_t row = k0 + (lane >> 4);
+    const bool rok = row < r1;
+    const double2 a = (rok && aok) ? A[row * lda + ar] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int J = jg * 4 + t;
+      if (J < TJ) {
+        const int bc = J * 16 + (lane & 15);
+        const double2 bb = (rok && bc < n) ? B[row * ldb + bc] : make_double2(0.0, 0.0);
+        // P = A^H B: re = ar.br + ai.bi ; im = ar.bi - ai.br
+        accr[t] = mfma(a.x, bb.x, accr[t]);
+        accr[t] = mfma(a.y, bb.y, accr[t]);
+        acci[t] = mfma(a.x, bb.y, acci[t]);
+        acci[t] = mfma(-a.y, bb.x, acci[t]);
+      }
+    }
+  }
+  double2* P = part + (size_t)blockIdx.x * m * n;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int J = jg * 4 + t;
+    if (J >= TJ) continue;
+    const int col = J * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rowo = I * 16 + (lane >> 4) + 4 * v;
+      if (rowo < m && col < n) P[(size_t)rowo * n + col] = make_double2(accr[t][v], acci[t][v]);
+    }
+  }
+}
+
+__global__ void k_sum_partials(const double2* __restrict__ part, int nparts, int mn,
+                               double2* __restrict__ P, int n, int64_t ldp) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mn) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = 0; p < nparts; ++p) {
+    const double2 v = part[(size_t)p * mn + idx];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  P[(idx / n) * ldp + idx % n] = s;
+}
+
+size_t gram_ws_size(int64_t N, int m, int n) {
+  const int64_t chunks = (N + kGramRows - 1) / kGramRows;
+  return (size_t)chunks * m * n * sizeof(double2);
+}
+
+hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                       int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t chunks = N > 0 ? (N + kGramRows - 1) / kGramRows : 0;
+  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int tasks = TI * JG;
+  double2* part = reinterpret_cast<double2*>(ws);
+  if (chunks > 0) {
+    hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)chunks, (tasks + 3) / 4), dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(A), lda,
+                       reinterpret_cast<const double2*>(B), ldb, N, m, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int mn = m * n;
+  hipLaunchKernelGGL(k_sum_partials, dim3((mn + 255) / 256), dim3(256), 0, st, part, (int)chunks,
+                     mn, reinterpret_cast<double2*>(P), n, ldp);
+  return hipGetLastError();
+}
+
+// C (N x n) = A (N x m) V (m x n); one wave per (16-row tile, group of 4
+// column tiles)
+__global__ __launch_bounds__(256) void k_rotate(const double2* __restrict__ A, int64_t lda,
+                                                int64_t N, int m, const double2* __restrict__ V,
+                                                int64_t ldv, int n, double2* __restrict__ C,
+                                                int64_t ldc) {
+  const int lane = __lane_id();
+  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t RT = (N + 15) / 16;
+  if (task >= RT * JG) return;
+  const int64_t rt = task / JG;
+  const int jg = (int)(task % JG);
+  const int64_t row = rt * 16 + (lane & 15);
+  const bool rok = row < N;
+  double4_t accr[4], acci[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    accr[t] = double4_t{0, 0, 0, 0};
+    acci[t] = double4_t{0, 0, 0, 0};
+  }
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    const double2 a = (rok && k < m) ? A[row * lda + k] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int J = jg * 4 + t;
+      if (J < TJ) {
+        const int col = J * 16 + (lane & 15);
+        const double2 v = (k < m && col < n) ? V[(int64_t)k * ldv + col] : make_double2(0.0, 0.0);
+        accr[t] = mfma(a.x, v.x, accr[t]);
+        accr[t] = mfma(-a.y, v.y, accr[t]);
+        acci[t] = mfma(a.x, v.y, acci[t]);
+        acci[t] = mfma(a.y, v.x, acci[t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int J = jg * 4 + t;
+    if (J >= TJ) continue;
+    const int col = J * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rt * 16 + (lane >> 4) + 4 * v;
+      if (r < N && col < n) C[r * ldc + col] = make_double2(accr[t][v], acci[t][v]);
+    }
+  }
+}
+
+hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
+                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st) {
+  if (N <= 0 || n <= 0) return hipSuccess;
+  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int64_t tasks = ((N + 15) / 16) * JG;
+  hipLaunchKernelGGL(k_rotate, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(A), lda, N, m,
+                     reinterpret_cast<const double2*>(V), ldv, n, reinterpret_cast<double2*>(C),
+                     ldc);
+  return hipGetLastError();
+}
+
+// T (r x n) = S (r x r real, row-major) Z (r x n complex)
+__global__ __launch_bounds__(256) void k_rcgemm(const double* __restrict__ S, int64_t r,
+                                                const double2* __restrict__ Z, int n,
+                                                double2* __restrict__ T) {
+  const int lane = __lane_id();
+  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t RT = (r + 15) / 16;
+  if (task >= RT * JG) return;
+  const int64_t rt = task / JG;
+  const int jg = (int)(task % JG);
+  const int64_t row = rt * 16 + (lane & 15);
+  const bool rok = row < r;
+  double4_t accr[4], acci[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    accr[t] = double4_t{0, 0, 0, 0};
+    acci[t] = double4_t{0, 0, 0, 0};
+  }
+  for (int64_t k0 = 0; k0 < r; k0 += 4) {
+    const int64_t k = k0 + (lane >> 4);
+    const double s = (rok && k < r) ? S[row * r + k] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int J = jg * 4 + t;
+      if (J < TJ) {
+        const int col = J * 16 + (lane & 15);
+        const double2 z = (k < r && col < n) ? Z[k * n + col] : make_double2(0.0, 0.0);
+        accr[t] = mfma(s, z.x, accr[t]);
+        acci[t] = mfma(s, z.y, acci[t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int J = jg * 4 + t;
+    if (J >= TJ) continue;
+    const int col = J * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t rr = rt * 16 + (lane >> 4) + 4 * v;
+      if (rr < r && col < n) T[rr * n + col] = make_double2(accr[t][v], acci[t][v]);
+    }
+  }
+}
+
+hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
+                             hipStream_t st) {
+  if (r <= 0 || n <= 0) return hipSuccess;
+  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int64_t tasks = ((r + 15) / 16) * JG;
+  hipLaunchKernelGGL(k_rcgemm, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st, S, r,
+                     reinterpret_cast<const double2*>(Z), n, reinterpret_cast<double2*>(T));
+  return hipGetLastError();
+}
+
+}  // namespace mpt

@@ -1,0 +1,52 @@
+// Internal launch entry points of libmpt (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpt.h"
+
+namespace mpt {
+
+int bucket_of(int M);
+
+// sweep.hip
+hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
+                        double* a_out, int32_t* status, const double* dout, double* dom,
+                        hipStream_t st);
+hipError_t persistent_launch(int bucket, bool adj, const mpt_rom* roms, const int4* items,
+                             int n_items, unsigned int* counter, const double* omega, double* out,
+                             int32_t* status, const double* dout, double* dom, int wpg, int groups,
+                             hipStream_t st);
+hipError_t reset_counters(unsigned int* c, int n, hipStream_t st);
+hipError_t sigma_reduce(const double* omega, const double* dom, const int64_t* off, int n_obj,
+                        double* sig, hipStream_t st);
+
+// select.hip
+hipError_t select_launch(const double* omega, int64_t n, const double* out, const double* snap,
+                         int n_snap, int n_star, double* new_omega, double* lambda,
+                         double* Lambda_max, int64_t* arg_ws, hipStream_t st);
+
+// spmm.hip
+hipError_t spmm_launch(const mpt_csr& K, const double* U, int64_t ldU, int M, double* Y,
+                       int64_t ldY, hipStream_t st);
+
+// gram.hip : complex contractions on FP64 MFMA
+//   P (m x n) = A^H B over N rows, A: N x m (lda), B: N x n (ldb), complex.
+//   Split-N partials in ws then a fixed-order reduction.
+size_t gram_ws_size(int64_t N, int m, int n);
+hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                       int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st);
+//   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv).
+hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
+                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st);
+//   T (r x n) = S (r x r, real) * Z (r x n, complex)
+hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
+                             hipStream_t st);
+
+// eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
+//   by cyclic two-sided Jacobi in one workgroup; A overwritten, V (n x n)
+//   eigenvectors in columns, lam eigenvalues (unsorted), info[0] sweeps used
+//   (or -1 when not converged).
+hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, hipStream_t st);
+
+}  // namespace mpt

@@ -1,0 +1,350 @@
+"""Python binding of libmpt (ctypes).  Argument marshalling only: every step of
+the hot path runs in the HIP kernels of libmpt.so; torch provides device
+memory and the stream.  Names follow the C ABI in include/mpt.h."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpt.so")
+
+MPT_OK, MPT_E_ARG, MPT_E_HIP, MPT_E_NOMEM, MPT_E_SINGULAR, MPT_E_NOTPD, MPT_E_UNSUPPORTED = range(7)
+
+
+class MptError(RuntimeError):
+    pass
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class _Rom(C.Structure):
+    _fields_ = [("M", C.c_int32), ("pad_", C.c_int32), ("KM", C.c_void_p), ("A0", C.c_void_p),
+                ("CM", C.c_void_p), ("g", C.c_void_p), ("G", C.c_void_p), ("E", C.c_void_p),
+                ("N0", C.c_void_p), ("alpha", C.c_double), ("alpha_lb", C.c_double)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("omegas_per_item", C.c_int32), ("waves_per_group", C.c_int32),
+                ("groups_per_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmpt.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MptError(f"{LIB_PATH} is missing: build it with paper_2307_05590_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, D, S = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_size_t
+        sig = {
+            "mpt_create": ([I32, P, P], I32),
+            "mpt_destroy": ([P], I32),
+            "mpt_set_stream": ([P, P], I32),
+            "mpt_last_error": ([P], C.c_char_p),
+            "mpt_max_reduced_dim": ([], I32),
+            "mpt_pod_basis_ws_size": ([I64, I32], S),
+            "mpt_pod_basis": ([P, P, I64, I64, I32, D, I32, P, I64, P, P, P, S], I32),
+            "mpt_project_ws_size": ([I64, I32, I64], S),
+            "mpt_project": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P,
+                             P, P, P, P, P, P, P, P, P, S], I32),
+            "mpt_spmm": ([P, P, P, I64, I32, P, I64], I32),
+            "mpt_sweep": ([P, P, P, I64, P, P, P], I32),
+            "mpt_select_snapshots": ([P, P, I64, P, P, I32, I32, P, P, P], I32),
+            "mpt_sweep_batched": ([P, P, P, I32, P, P, P, P, P, I32], I32),
+            "mpt_sweep_adjoint": ([P, P, P, I64, P, P, P, P], I32),
+            "mpt_sweep_adjoint_batched": ([P, P, P, I32, P, P, P, P, P, P], I32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """One libmpt handle bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device=None, stream=None):
+        dev = torch.device(device or "cuda")
+        self.index = dev.index if dev.index is not None else torch.cuda.current_device()
+        self.h = C.c_void_p()
+        st = stream if stream is not None else torch.cuda.current_stream(self.index)
+        self._check(lib().mpt_create(self.index, C.c_void_p(st.cuda_stream), C.byref(self.h)))
+        self.stream = st
+
+    def _check(self, status):
+        if status != MPT_OK:
+            msg = lib().mpt_last_error(self.h).decode() if self.h else ""
+            raise MptError(f"libmpt status {status}: {msg}")
+
+    def use_current_stream(self):
+        st = torch.cuda.current_stream(self.index)
+        if st != self.stream:
+            self._check(lib().mpt_set_stream(self.h, C.c_void_p(st.cuda_stream)))
+            self.stream = st
+
+    def close(self):
+        if self.h:
+            lib().mpt_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles = {}
+
+
+def handle(device=None) -> Handle:
+    dev = torch.device(device or "cuda")
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _handles:
+        _handles[idx] = Handle(torch.device("cuda", idx))
+    h = _handles[idx]
+    h.use_current_stream()
+    return h
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise MptError("libmpt expects contiguous CUDA tensors")
+
+
+@dataclass
+class Csr:
+    """CSR matrix on the device (int32 indices, float64 values)."""
+
+    n: int
+    rowptr: torch.Tensor
+    colind: torch.Tensor
+    val: torch.Tensor
+
+    @classmethod
+    def from_scipy(cls, K, device="cuda"):
+        K = K.tocsr()
+        K.sort_indices()
+        return cls(K.shape[0], torch.as_tensor(K.indptr.astype("int32"), device=device),
+                   torch.as_tensor(K.indices.astype("int32"), device=device),
+                   torch.as_tensor(K.data.astype("float64"), device=device))
+
+    def struct(self):
+        return _Csr(self.n, self.val.numel(), _ptr(self.rowptr), _ptr(self.colind), _ptr(self.val))
+
+
+@dataclass
+class Rom:
+    """Reduced model of one object (device tensors, complex128 / float64)."""
+
+    M: int
+    KM: torch.Tensor
+    A0: torch.Tensor
+    CM: torch.Tensor
+    g: torch.Tensor  # (3, M)
+    G: torch.Tensor  # (2M+3, 2M+3)
+    E: torch.Tensor  # (3, 3)
+    N0: torch.Tensor  # (3, 3)
+    alpha: float
+    alpha_lb: float = 1.0
+
+    def struct(self):
+        _dev_check(self.KM, self.A0, self.CM, self.g, self.G, self.E, self.N0)
+        return _Rom(self.M, 0, _ptr(self.KM), _ptr(self.A0), _ptr(self.CM), _ptr(self.g),
+                    _ptr(self.G), _ptr(self.E), _ptr(self.N0), float(self.alpha),
+                    float(self.alpha_lb))
+
+    @classmethod
+    def from_host(cls, d, alpha, alpha_lb=1.0, device="cuda"):
+        """From host arrays: KM, A0, CM (M x M), g (3 x M), G, E, N0."""
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt, device=device).contiguous()
+        cd, rd = torch.complex128, torch.float64
+        M = d["KM"].shape[0]
+        return cls(M, t(d["KM"], cd), t(d["A0"], cd), t(d["CM"], cd), t(d["g"], cd), t(d["G"], cd),
+                   t(d["E"], rd), t(d["N0"], rd), alpha, alpha_lb)
+
+
+def mpt_spmm(K: Csr, U: torch.Tensor) -> torch.Tensor:
+    h = handle(U.device)
+    _dev_check(U)
+    M = U.shape[1]
+    Y = torch.empty_like(U)
+    k = K.struct()
+    h._check(lib().mpt_spmm(h.h, C.byref(k), _ptr(U), M, M, _ptr(Y), M))
+    return Y
+
+
+def mpt_pod_basis(D: torch.Tensor, tol_sigma: float, M_cap: int):
+    """a1: returns (U (N x M), sigma (ncol), M).  Synchronises to read M."""
+    h = handle(D.device)
+    _dev_check(D)
+    N, ncol = D.shape
+    ws = torch.empty(lib().mpt_pod_basis_ws_size(N, ncol), dtype=torch.uint8, device=D.device)
+    U = torch.empty((N, M_cap), dtype=torch.complex128, device=D.device)
+    sigma = torch.empty(ncol, dtype=torch.float64, device=D.device)
+    M = C.c_int(0)
+    h._check(lib().mpt_pod_basis(h.h, _ptr(D), ncol, N, ncol, float(tol_sigma), int(M_cap), _ptr(U),
+                                 M_cap, _ptr(sigma), C.byref(M), _ptr(ws), ws.numel()))
+    return U[:, :M.value].contiguous(), sigma, M.value
+
+
+def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, S, alpha_lb=1.0, keep_Y=False):
+    """a2: Galerkin projection and residual Gram -> Rom (and optionally Y = K U)."""
+    h = handle(U.device)
+    _dev_check(c, w, o, vol, U, cond, S)
+    N, M = U.shape
+    nc = cond.numel()
+    dev = U.device
+    cd, rd = torch.complex128, torch.float64
+    KM = torch.empty((M, M), dtype=cd, device=dev)
+    A0 = torch.empty_like(KM)
+    CM = torch.empty_like(KM)
+    g = torch.empty((3, M), dtype=cd, device=dev)
+    G = torch.empty((2 * M + 3, 2 * M + 3), dtype=cd, device=dev)
+    E = torch.empty((3, 3), dtype=rd, device=dev)
+    N0 = torch.empty((3, 3), dtype=rd, device=dev)
+    Y = torch.empty((N, M), dtype=cd, device=dev) if keep_Y else None
+    ws = torch.empty(lib().mpt_project_ws_size(N, M, nc), dtype=torch.uint8, device=dev)
+    k = K.struct()
+    h._check(lib().mpt_project(h.h, C.byref(k), _ptr(c), float(eps_h), _ptr(w), _ptr(o), _ptr(vol),
+                               float(alpha), _ptr(U), M, M, _ptr(cond), nc, _ptr(S), _ptr(KM),
+                               _ptr(A0), _ptr(CM), _ptr(g), _ptr(G), _ptr(E), _ptr(N0), _ptr(Y),
+                               _ptr(ws), ws.numel()))
+    rom = Rom(M, KM, A0, CM, g, G, E, N0, float(alpha), float(alpha_lb))
+    return (rom, Y) if keep_Y else rom
+
+
+def mpt_sweep(rom: Rom, omega: torch.Tensor, want_a: bool = False):
+    """a3+a4: (n x 18 outputs [R~ | I | Delta], status[, a (n x 3 x M)])."""
+    h = handle(omega.device)
+    _dev_check(omega)
+    n = omega.numel()
+    out = torch.empty((n, 18), dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    a = torch.empty((n, 3, rom.M), dtype=torch.complex128, device=omega.device) if want_a else None
+    r = rom.struct()
+    h._check(lib().mpt_sweep(h.h, C.byref(r), _ptr(omega), n, _ptr(out), _ptr(a), _ptr(st)))
+    return (out, st, a) if want_a else (out, st)
+
+
+def mpt_select_snapshots(omega, out, snap, n_star):
+    """a5: (new omegas (n_star, NaN if missing), per-interval Lambda_n, Lambda)."""
+    h = handle(omega.device)
+    _dev_check(omega, out, snap)
+    dev = omega.device
+    new = torch.empty(n_star, dtype=torch.float64, device=dev)
+    lam = torch.empty(snap.numel() - 1, dtype=torch.float64, device=dev)
+    Lmax = torch.empty(1, dtype=torch.float64, device=dev)
+    h._check(lib().mpt_select_snapshots(h.h, _ptr(omega), omega.numel(), _ptr(out), _ptr(snap),
+                                        snap.numel(), n_star, _ptr(new), _ptr(lam), _ptr(Lmax)))
+    return new, lam, Lmax
+
+
+class Dictionary:
+    """Device-side array of Rom structs plus concatenated frequency lists."""
+
+    def __init__(self, roms, omegas, device="cuda"):
+        self.roms = list(roms)
+        self.n_obj = len(self.roms)
+        self._structs = (_Rom * self.n_obj)(*[r.struct() for r in self.roms])
+        raw = bytes(self._structs)
+        self.dev_structs = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        off = [0]
+        for w in omegas:
+            off.append(off[-1] + int(w.numel()))
+        self.off = (C.c_int64 * (self.n_obj + 1))(*off)
+        self.offsets = off
+        self.omega = torch.cat([w.to(device=device, dtype=torch.float64) for w in omegas]).contiguous()
+
+
+def mpt_sweep_batched(dic: Dictionary, tune=None, use_graph=True, out=None, status=None):
+    """a6: all objects in one persistent launch (a HIP graph when use_graph)."""
+    h = handle(dic.omega.device)
+    n = dic.omega.numel()
+    if out is None:
+        out = torch.empty((n, 18), dtype=torch.float64, device=dic.omega.device)
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=dic.omega.device)
+    t = None
+    if tune is not None:
+        t = _Tuning(int(tune[0]), int(tune[1]), int(tune[2]), 0)
+    h._check(lib().mpt_sweep_batched(h.h, dic._structs, _ptr(dic.dev_structs), dic.n_obj, dic.off,
+                                     _ptr(dic.omega), _ptr(out), _ptr(status),
+                                     C.byref(t) if t is not None else None, int(bool(use_graph))))
+    return out, status
+
+
+def mpt_sweep_adjoint(rom: Rom, omega, dout):
+    """a7: (dL/domega (n), sigma dL/dsigma (1), status)."""
+    h = handle(omega.device)
+    _dev_check(omega, dout)
+    n = omega.numel()
+    dom = torch.empty(n, dtype=torch.float64, device=omega.device)
+    sds = torch.empty(1, dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    r = rom.struct()
+    h._check(lib().mpt_sweep_adjoint(h.h, C.byref(r), _ptr(omega), n, _ptr(dout), _ptr(dom),
+                                     _ptr(sds), _ptr(st)))
+    return dom, sds, st
+
+
+def mpt_sweep_adjoint_batched(dic: Dictionary, dout):
+    h = handle(dic.omega.device)
+    n = dic.omega.numel()
+    dom = torch.empty(n, dtype=torch.float64, device=dic.omega.device)
+    sds = torch.empty(dic.n_obj, dtype=torch.float64, device=dic.omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=dic.omega.device)
+    h._check(lib().mpt_sweep_adjoint_batched(h.h, dic._structs, _ptr(dic.dev_structs), dic.n_obj,
+                                             dic.off, _ptr(dic.omega), _ptr(dout), _ptr(dom),
+                                             _ptr(sds), _ptr(st)))
+    return dom, sds, st
+
+
+class SweepFn(torch.autograd.Function):
+    """Differentiable signature sweep of one object.
+
+    forward(omega, sigma) -> (n, 12) [R~ (6) | I (6)] at conductivity sigma, the
+    reduced model having been projected at sigma0 (C_M, g, E scale with sigma,
+    basis frozen).  The model depends on omega * sigma only, so the sweep runs
+    at omega * sigma / sigma0; backward runs the adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, omega, sigma, rom, sigma0):
+        scale = sigma.detach() / sigma0
+        w_eff = (omega.detach() * scale).contiguous()
+        out, st = mpt_sweep(rom, w_eff)
+        ctx.save_for_backward(omega, sigma, w_eff)
+        ctx.rom, ctx.sigma0 = rom, sigma0
+        return out[:, :12]
+
+    @staticmethod
+    def backward(ctx, grad):
+        omega, sigma, w_eff = ctx.saved_tensors
+        dout = torch.zeros((omega.numel(), 18), dtype=torch.float64, device=omega.device)
+        dout[:, :12] = grad
+        dom_eff, sds, _ = mpt_sweep_adjoint(ctx.rom, w_eff, dout.contiguous())
+        scale = sigma.detach() / ctx.sigma0
+        g_omega = dom_eff * scale if ctx.needs_input_grad[0] else None
+        g_sigma = (sds[0] / sigma.detach()).reshape(sigma.shape) if ctx.needs_input_grad[1] else None
+        return g_omega, g_sigma, None, None
+
+
+def signature(omega, sigma, rom, sigma0):
+    return SweepFn.apply(omega, sigma, rom, sigma0)

@@ -1,0 +1,364 @@
+"""GPU parity: every hot-path step through the C ABI against the CPU oracle.
+
+Tolerances: tensors R~ and I 1e-10 normwise per frequency (each part relative
+to its own largest entry); certificates 1e-8 relative above the rounding floor
+of the G-form (64 eps |w|^T|G||w|), absolute below; integer decisions exact."""
+import numpy as np
+import pytest
+
+from oracle import rom as R
+from tests import _cases
+from tests._gpu_helpers import (PAIRS, delta_floor, oracle_rom, random_rom, tensor_errors,
+                                term_scales)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mpt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_05590_amd import mpt as m
+    m.lib()  # fails loudly when the library is missing
+    return m
+
+
+def _dev(a, dt=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _check_sweep(mpt, host, G, rom_o, alpha, omega, tag):
+    rom = mpt.Rom.from_host(host, alpha)
+    w = _dev(omega, torch.float64)
+    out, st, a_gpu = mpt.mpt_sweep(rom, w, want_a=True)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    assert int(st.abs().max()) == 0, tag
+    ref, a = R.sweep(rom_o, omega, G, alpha)
+    scales = term_scales(ref, omega, rom_o["N0"], rom_o["E"], alpha)
+    eR, eI = tensor_errors(out, ref, scales)
+    print(f"{tag}: max err R~ {eR.max():.2e} I {eI.max():.2e}", flush=True)
+    assert eR.max() <= 1e-10, tag
+    assert eI.max() <= 1e-10, tag
+    # reduced solutions: forward error of a backward-stable solve, <= c eps cond(A)
+    ag = np.swapaxes(a_gpu.cpu().numpy(), 1, 2)  # (n, M, 3)
+    A0 = host["A0"]
+    cond = np.array([np.linalg.cond(A0 - 1j * w_ * host["CM"]) for w_ in omega])
+    ea = np.linalg.norm(ag - a, axis=(1, 2)) / np.linalg.norm(a, axis=(1, 2))
+    print(f"{tag}: solution err / (eps cond) max {np.max(ea / (2.2e-16 * cond)):.2e}", flush=True)
+    assert np.all(ea <= 1e3 * 2.2e-16 * cond + 1e-14), tag
+    # certificates: the same quadratic forms at the GPU's own solution
+    dref = R.pack(R.certificate_gform(G, ag, omega, alpha))
+    fl = delta_floor(G, ag, omega, alpha)
+    d = np.abs(out[:, 12:] - dref)
+    print(f"{tag}: Delta err / floor max {np.max(d / (2.2e-16 * fl)):.2e}", flush=True)
+    assert np.all(d <= 1e-8 * np.abs(dref) + 64 * 2.2e-16 * fl), tag
+    return out
+
+
+@pytest.mark.parametrize("M", [1, 16, 17, 31, 47, 64])
+def test_sweep_random_roms(mpt, M):
+    rom_o, G, host, alpha = random_rom(M, seed=M)
+    omega = np.logspace(1, 6, 131)
+    rom_o["KM"] = host["KM"]
+    _check_sweep(mpt, host, G, rom_o, alpha, omega, f"random M={M}")
+
+
+@pytest.mark.parametrize("M", [3, 10, 33, 48])
+def test_sweep_ellipsoid_rom(mpt, M):
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    omega = np.logspace(1, 6, 257)
+    out = _check_sweep(mpt, host, G, rom_o, fo.alpha, omega, f"ellipsoid16 M={M}")
+    # against the explicit mesh sums (the IM analogue) at a few frequencies
+    sel = np.arange(0, 257, 32)
+    a = R.reduced_solve(rom_o, omega[sel])
+    Rt, I = R.tensors_mesh(fo, U, a, omega[sel], c.w, rom_o["N0"])
+    ref = np.concatenate([R.pack(Rt), R.pack(I)], 1)
+    sc = term_scales(ref, omega[sel], rom_o["N0"], rom_o["E"], fo.alpha)
+    eR, eI = tensor_errors(out[sel, :12], ref, sc)
+    assert eR.max() <= 1e-10 and eI.max() <= 1e-10
+
+
+def test_sweep_magnetic_rom(mpt):
+    c = _cases.magnetic10()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :12]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    assert np.abs(rom_o["N0"]).max() > 0
+    _check_sweep(mpt, host, G, rom_o, fo.alpha, np.logspace(1, 6, 65), "magnetic10 M=12")
+
+
+def test_sweep_empty_and_bad_args(mpt):
+    rom_o, G, host, alpha = random_rom(5, seed=1)
+    rom = mpt.Rom.from_host(host, alpha)
+    out, st = mpt.mpt_sweep(rom, torch.empty(0, dtype=torch.float64, device="cuda"))
+    assert out.shape == (0, 18)
+    bad = mpt.Rom.from_host(host, alpha)
+    bad.M = 65
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_sweep(bad, torch.ones(3, dtype=torch.float64, device="cuda"))
+
+
+def test_sweep_singular_flag(mpt):
+    """A zero pencil (A0 = C_M = 0) must be flagged, not silently returned."""
+    rom_o, G, host, alpha = random_rom(4, seed=2)
+    host = dict(host)
+    host["A0"] = np.zeros((4, 4))
+    host["CM"] = np.zeros((4, 4))
+    rom = mpt.Rom.from_host(host, alpha)
+    out, st = mpt.mpt_sweep(rom, _dev([1.0, 2.0], torch.float64))
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == mpt.MPT_E_SINGULAR)
+
+
+def test_sweep_deterministic(mpt):
+    rom_o, G, host, alpha = random_rom(40, seed=3)
+    rom = mpt.Rom.from_host(host, alpha)
+    w = _dev(np.logspace(1, 6, 500), torch.float64)
+    o1, _ = mpt.mpt_sweep(rom, w)
+    o2, _ = mpt.mpt_sweep(rom, w)
+    assert torch.equal(o1, o2)
+
+
+# ------------------------------------------------------------ selection (a5)
+def test_select_matches_oracle(mpt):
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :8]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    omega = np.logspace(1, 5, 400)
+    rom = mpt.Rom.from_host(host, fo.alpha)
+    w = _dev(omega, torch.float64)
+    out, _ = mpt.mpt_sweep(rom, w)
+    snaps = c.snap
+    new, lam, Lmax = mpt.mpt_select_snapshots(w, out, _dev(snaps, torch.float64), 2)
+    torch.cuda.synchronize()
+    ref_new, ref_L, ref_lam = R.select_snapshots(omega, out.cpu().numpy()[:, 12:], snaps, 2)
+    assert np.array_equal(new.cpu().numpy(), ref_new)
+    assert Lmax.item() == ref_L
+    assert np.array_equal(lam.cpu().numpy(), ref_lam)
+
+
+def test_select_ties_and_empty_intervals(mpt):
+    omega = np.arange(1.0, 11.0)
+    out = np.zeros((10, 18))
+    out[1, 14] = 5.0
+    out[2, 12] = 5.0
+    out[4, 15] = 7.0
+    out[9, 17] = 6.0
+    snaps = np.array([1.0, 4.0, 7.0, 10.0, 20.0, 30.0])
+    new, lam, Lmax = mpt.mpt_select_snapshots(_dev(omega, torch.float64), _dev(out, torch.float64),
+                                              _dev(snaps, torch.float64), 3)
+    torch.cuda.synchronize()
+    assert list(new.cpu().numpy()) == [5.0, 10.0, 2.0]
+    assert Lmax.item() == 7.0
+    lam = lam.cpu().numpy()
+    assert list(lam[:4]) == [5.0, 7.0, 0.0, 6.0] and np.isneginf(lam[4])
+
+
+# --------------------------------------------------------------- spmm / a2
+def test_spmm_matches_scipy(mpt):
+    c = _cases.ellipsoid16()
+    K = mpt.Csr.from_scipy(c.ops.K)
+    rng = np.random.default_rng(0)
+    for M in (1, 7, 16, 33, 48, 96):
+        U = rng.standard_normal((c.ops.N, M)) + 1j * rng.standard_normal((c.ops.N, M))
+        Y = mpt.mpt_spmm(K, _dev(U, torch.complex128)).cpu().numpy()
+        ref = c.ops.K @ U
+        assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), M
+
+
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("ellipsoid16", 48), ("magnetic10", 12)])
+def test_project_matches_oracle(mpt, case, M):
+    c = getattr(_cases, case)()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    ops = c.ops
+    rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
+                          _dev(c.w, torch.float64), _dev(c.o, torch.float64),
+                          _dev(ops.vol, torch.float64), ops.alpha, _dev(U, torch.complex128),
+                          _dev(ops.cond_idx, torch.int32), _dev(c.S, torch.float64))
+    torch.cuda.synchronize()
+    for name in ("KM", "A0", "CM", "g", "E", "N0"):
+        got = getattr(rom, name).cpu().numpy()
+        ref = host[name]
+        err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+        print(f"{case} M={M} {name}: {err:.2e}", flush=True)
+        assert err <= 1e-12, name
+    # G: the blocks built from S = P^T X^{-1} P are sums with heavy cancellation
+    # (S carries the 1/(eps h) gradient part), so each entry is compared with
+    # the magnitude of its terms, |Z_c|^T |S| |Z_c|.
+    got = rom.G.cpu().numpy()
+    cond = ops.cond_idx
+    Zc = np.concatenate([ops.c[cond, None] * c.w[cond], ops.c[cond, None] * U[cond]], 1)
+    mag = np.abs(Zc).T @ np.abs(c.S) @ np.abs(Zc)
+    wc = np.r_[0:3, 3 + M:3 + 2 * M]
+    Gmag = np.zeros_like(got, dtype=float)
+    Gmag[np.ix_(wc, wc)] = mag
+    Gmag = np.maximum(Gmag, np.abs(G).max() * 1e-3)
+    errG = np.max(np.abs(got - G) / Gmag)
+    print(f"{case} M={M} G: {errG:.2e} (relative to term magnitude)", flush=True)
+    assert errG <= 1e-12
+
+
+# ------------------------------------------------------------------- POD a1
+@pytest.mark.parametrize("case,tol,cap", [("ellipsoid16", 1e-6, 48), ("ellipsoid16", 1e-12, 20),
+                                          ("magnetic10", 1e-8, 24), ("sphere12", 1e-6, 16)])
+def test_pod_basis_matches_svd(mpt, case, tol, cap):
+    c = getattr(_cases, case)()
+    D = c.D
+    U_o, s_o, M_o = R.pod_basis(D, tol, cap)
+    U, sig, M = mpt.mpt_pod_basis(_dev(D, torch.complex128), tol, cap)
+    torch.cuda.synchronize()
+    sig = sig.cpu().numpy()
+    U = U.cpu().numpy()
+    assert M == M_o
+    assert np.all(np.abs(sig - s_o) <= 1e-10 * s_o + 1e-13 * s_o[0])
+    assert np.abs(U.conj().T @ U - np.eye(M)).max() <= 1e-12
+    Pg = U @ (U.conj().T @ D)
+    Po = U_o @ (U_o.conj().T @ D)
+    assert np.linalg.norm(Pg - Po) <= 1e-12 * np.linalg.norm(D)
+
+
+def test_end_to_end_ellipsoid(mpt):
+    """GPU basis + projection + sweep against the oracle's SVD + projection +
+    solves + mesh sums."""
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    ops = c.ops
+    U_o, s_o, M = R.pod_basis(c.D, 1e-6, 48)
+    rom_o, G, host = oracle_rom(fo, U_o, c.w, c.o, c.S, ops.cond_idx)
+    omega = np.logspace(1, 6, 40)
+    a = R.reduced_solve(rom_o, omega)
+    Rt, I = R.tensors_mesh(fo, U_o, a, omega, c.w, rom_o["N0"])
+    ref = np.concatenate([R.pack(Rt), R.pack(I)], 1)
+    U, sig, Mg = mpt.mpt_pod_basis(_dev(c.D, torch.complex128), 1e-6, 48)
+    assert Mg == M
+    rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
+                          _dev(c.w, torch.float64), _dev(c.o, torch.float64),
+                          _dev(ops.vol, torch.float64), ops.alpha, U,
+                          _dev(ops.cond_idx, torch.int32), _dev(c.S, torch.float64))
+    out, st = mpt.mpt_sweep(rom, _dev(omega, torch.float64))
+    torch.cuda.synchronize()
+    sc = term_scales(ref, omega, rom_o["N0"], rom_o["E"], fo.alpha)
+    eR, eI = tensor_errors(out.cpu().numpy()[:, :12], ref, sc)
+    print(f"end-to-end: R~ {eR.max():.2e} I {eI.max():.2e}", flush=True)
+    assert eR.max() <= 1e-10 and eI.max() <= 1e-10
+
+
+# --------------------------------------------------------------- adjoint a7
+def _objective_weights(out):
+    """dJ/dout for J = sum_omega sum_{ij, all 9} I_ij^2 + (R~_ij - N0_ij)^2."""
+    mult = np.array([1.0 if i == j else 2.0 for i, j in PAIRS])
+    return mult, out
+
+
+def test_adjoint_matches_forward_sensitivity(mpt):
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :10]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    omega = np.logspace(1, 6, 97)
+    rom = mpt.Rom.from_host(host, fo.alpha)
+    w = _dev(omega, torch.float64)
+    out, _ = mpt.mpt_sweep(rom, w)
+    o = out.cpu().numpy()
+    N0 = np.array([rom_o["N0"][i, j] for i, j in PAIRS])
+    mult = np.array([1.0 if i == j else 2.0 for i, j in PAIRS])
+    dout = np.zeros((omega.size, 18))
+    dout[:, :6] = 2 * (o[:, :6] - N0) * mult
+    dout[:, 6:12] = 2 * o[:, 6:12] * mult
+    dom, sds, st = mpt.mpt_sweep_adjoint(rom, w, _dev(dout, torch.float64))
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0
+    ref_w, ref_s = R.forward_sensitivity(rom_o, omega, fo.alpha, dout[:, :6], dout[:, 6:12])
+    dom = dom.cpu().numpy()
+    err = np.abs(dom - ref_w).max() / np.abs(ref_w).max()
+    print(f"adjoint dJ/domega rel err {err:.2e}; sigma term {sds.item():.6e} vs {ref_s:.6e}")
+    assert err <= 1e-8
+    assert abs(sds.item() - ref_s) <= 1e-8 * abs(ref_s)
+
+
+def test_autograd_fd_and_sigma_identity(mpt):
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :10]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    rom = mpt.Rom.from_host(host, fo.alpha)
+    sigma0 = 5.8e7
+    omega = torch.tensor(np.logspace(1, 6, 33), dtype=torch.float64, device="cuda", requires_grad=True)
+    sigma = torch.tensor(sigma0, dtype=torch.float64, device="cuda", requires_grad=True)
+    N0 = torch.tensor([rom_o["N0"][i, j] for i, j in PAIRS], dtype=torch.float64, device="cuda")
+    mult = torch.tensor([1.0 if i == j else 2.0 for i, j in PAIRS], dtype=torch.float64, device="cuda")
+
+    def J(w, s):
+        out = mpt.signature(w, s, rom, sigma0)
+        return (mult * (out[:, 6:12] ** 2 + (out[:, :6] - N0) ** 2)).sum()
+
+    val = J(omega, sigma)
+    val.backward()
+    gw = omega.grad.detach().cpu().numpy()
+    gs = sigma.grad.item()
+    # sigma dJ/dsigma = sum_k omega_k dJ/domega_k (model depends on omega sigma only)
+    assert abs(sigma0 * gs - np.sum(omega.detach().cpu().numpy() * gw)) <= 1e-10 * abs(sigma0 * gs)
+    with torch.no_grad():
+        for k in (0, 9, 20, 32):
+            h = 1e-6 * omega[k].item()
+            e = torch.zeros_like(omega)
+            e[k] = h
+            fd = (J(omega + e, sigma) - J(omega - e, sigma)).item() / (2 * h)
+            assert abs(fd - gw[k]) <= 1e-5 * abs(gw).max(), k
+        hs = 1e-6 * sigma0
+        fds = (J(omega, sigma + hs) - J(omega, sigma - hs)).item() / (2 * hs)
+        assert abs(fds - gs) <= 1e-5 * abs(gs)
+
+
+# --------------------------------------------------------------- batched a6
+def _dictionary(mpt, n_obj=7):
+    roms, omegas, refs = [], [], []
+    rng = np.random.default_rng(11)
+    for o in range(n_obj):
+        M = [1, 8, 16, 20, 33, 48, 64][o % 7]
+        rom_o, G, host, alpha = random_rom(M, seed=100 + o)
+        roms.append(mpt.Rom.from_host(host, alpha))
+        n = int(rng.integers(1, 300))
+        omegas.append(torch.tensor(np.sort(rng.uniform(10, 1e6, n)), dtype=torch.float64, device="cuda"))
+    return roms, omegas
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_equals_per_object(mpt, use_graph):
+    roms, omegas = _dictionary(mpt)
+    dic = mpt.Dictionary(roms, omegas)
+    outs = []
+    for rep in range(3):
+        out, st = mpt.mpt_sweep_batched(dic, tune=(4, 4, 2), use_graph=use_graph)
+        torch.cuda.synchronize()
+        _ = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        outs.append(out.clone())
+        assert int(st.abs().max()) == 0
+    for o, (r, w) in enumerate(zip(roms, omegas)):
+        ref, _ = mpt.mpt_sweep(r, w)
+        a, b = dic.offsets[o], dic.offsets[o + 1]
+        for out in outs:
+            assert torch.equal(out[a:b], ref), o
+
+
+def test_batched_adjoint_equals_per_object(mpt):
+    roms, omegas = _dictionary(mpt, 5)
+    dic = mpt.Dictionary(roms, omegas)
+    rng = np.random.default_rng(4)
+    dout = torch.tensor(rng.standard_normal((dic.omega.numel(), 18)), device="cuda")
+    dom, sds, st = mpt.mpt_sweep_adjoint_batched(dic, dout)
+    torch.cuda.synchronize()
+    for o, (r, w) in enumerate(zip(roms, omegas)):
+        a, b = dic.offsets[o], dic.offsets[o + 1]
+        d1, s1, _ = mpt.mpt_sweep_adjoint(r, w, dout[a:b].contiguous())
+        assert torch.equal(dom[a:b], d1)
+        assert abs(sds[o].item() - s1.item()) <= 1e-13 * abs(s1.item())
