@@ -287,8 +287,11 @@ extern "C" const char* mpt_last_error(mpt_handle h) { return h ? h->err.c_str() 
 extern "C" int mpt_max_reduced_dim(void) { return 64; }
 
 // ------------------------------------------------------------------ a1 POD
+constexpr int kJacobiSweeps = 40;
+constexpr double kJacobiTolPass1 = 1e-9;  // pass 1 only preconditions pass 2
+
 static void pod_layout(int64_t N, int m, size_t* off) {
-  // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 end
+  // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 jacobi record, 9 end
   size_t o = 0;
   off[0] = o; o = align256(o + (size_t)m * m * 16);
   off[1] = o; o = align256(o + (size_t)m * m * 16);
@@ -298,14 +301,15 @@ static void pod_layout(int64_t N, int m, size_t* off) {
   off[5] = o; o = align256(o + (size_t)m * 192 * 16);
   off[6] = o; o = align256(o + 64);
   off[7] = o; o = align256(o + 64);
-  off[8] = o;
+  off[8] = o; o = align256(o + jacobi_ws_size(m, kJacobiSweeps));
+  off[9] = o;
 }
 
 extern "C" size_t mpt_pod_basis_ws_size(int64_t N, int ncol) {
   if (N <= 0 || ncol <= 0) return 0;
-  size_t off[9];
+  size_t off[10];
   pod_layout(N, ncol, off);
-  return off[8];
+  return off[9];
 }
 
 extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N,
@@ -320,7 +324,7 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(hipSetDevice(h->device));
   const int m = ncol;
   const int Mc = std::min(M_cap, m);
-  size_t off[9];
+  size_t off[10];
   pod_layout(N, m, off);
   char* w = reinterpret_cast<char*>(ws);
   double* G0 = reinterpret_cast<double*>(w + off[0]);
@@ -331,14 +335,16 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   double* W = reinterpret_cast<double*>(w + off[5]);
   int* info = reinterpret_cast<int*>(w + off[6]);
   int* Mdev = reinterpret_cast<int*>(w + off[7]);
+  void* jws = w + off[8];
+  const double tol2 = 4.0 * m * 2.220446049250313e-16;
   hipStream_t st = h->stream;
   // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info, jws, kJacobiSweeps, kJacobiTolPass1, st));
   HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
   // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
   HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps, tol2, st));
   hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
                      reinterpret_cast<const double2*>(V0), m, tol_sigma, Mc, sigma,
                      reinterpret_cast<double2*>(W), Mdev);
@@ -348,8 +354,8 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   if (M_cap > Mc) HIP_OK(hipMemset2DAsync(reinterpret_cast<char*>(U) + (size_t)Mc * 16, ldU * 16, 0,
                                           (size_t)(M_cap - Mc) * 16, N, st));
   HIP_OK(hipMemcpyAsync(h->host_M, Mdev, sizeof(int), hipMemcpyDeviceToHost, st));
-  int hinfo[2] = {0, 0};
-  HIP_OK(hipMemcpyAsync(hinfo, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  int hinfo[4] = {0, 0, 0, 0};
+  HIP_OK(hipMemcpyAsync(hinfo, info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   *M_out = *h->host_M;
   if (hinfo[0] < 0 || hinfo[1] < 0) return fail(h, MPT_E_NOTPD, "Jacobi did not converge");

@@ -20,21 +20,29 @@ __device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kGramRows = 1024;  // rows per partial
+// rows per partial: chosen so that a launch has about a thousand workgroups
+// while the partial sums (chunks x m x n) stay small next to the operands
+__host__ __device__ inline int64_t gram_rows(int64_t N, int m, int n) {
+  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
+  const int64_t groups_per_chunk = (TI * JG + 3) / 4;
+  int64_t rows = N * groups_per_chunk / 1024;
+  rows = rows < 256 ? 256 : (rows > 8192 ? 8192 : rows);
+  return (rows + 3) / 4 * 4;
+}
 
 // grid: x = row chunk, y = wave-task group (4 waves per group);
 // wave-task t -> tile row I = t / JG, tile column group jg = t % JG (4 tiles)
 __global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict__ A, int64_t lda,
                                                       const double2* __restrict__ B, int64_t ldb,
-                                                      int64_t N, int m, int n,
+                                                      int64_t N, int m, int n, int64_t rows,
                                                       double2* __restrict__ part) {
   const int lane = __lane_id();
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int task = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (task >= TI * JG) return;
   const int I = task / JG, jg = task % JG;
-  const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
-  const int64_t r1 = min(N, r0 + kGramRows);
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int64_t r1 = min(N, r0 + rows);
   const int ar = I * 16 + (lane & 15);  // column of A feeding this lane
   const bool aok = ar < m;
   double4_t accr[4], acci[4];
@@ -75,13 +83,33 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict_
   }
 }
 
-__global__ void k_sum_partials(const double2* __restrict__ part, int nparts, int mn,
-                               double2* __restrict__ P, int n, int64_t ldp) {
+// partial sums: stage 1 sums a slice of the chunks per (entry, slice), stage 2
+// sums the slices; both in fixed order (deterministic)
+constexpr int kSumSlices = 16;
+
+__global__ void k_sum_partials1(const double2* __restrict__ part, int nparts, int mn,
+                                double2* __restrict__ mid) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = blockIdx.y;
+  if (idx >= mn) return;
+  const int per = (nparts + kSumSlices - 1) / kSumSlices;
+  const int p0 = sl * per, p1 = min(nparts, p0 + per);
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = p0; p < p1; ++p) {
+    const double2 v = part[(size_t)p * mn + idx];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  mid[(size_t)sl * mn + idx] = s;
+}
+
+__global__ void k_sum_partials2(const double2* __restrict__ mid, int mn,
+                                double2* __restrict__ P, int n, int64_t ldp) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mn) return;
   double2 s = make_double2(0.0, 0.0);
-  for (int p = 0; p < nparts; ++p) {
-    const double2 v = part[(size_t)p * mn + idx];
+  for (int sl = 0; sl < kSumSlices; ++sl) {
+    const double2 v = mid[(size_t)sl * mn + idx];
     s.x += v.x;
     s.y += v.y;
   }
@@ -89,27 +117,34 @@ __global__ void k_sum_partials(const double2* __restrict__ part, int nparts, int
 }
 
 size_t gram_ws_size(int64_t N, int m, int n) {
-  const int64_t chunks = (N + kGramRows - 1) / kGramRows;
-  return (size_t)chunks * m * n * sizeof(double2);
+  const int64_t rows = gram_rows(N, m, n);
+  const int64_t chunks = (N + rows - 1) / rows;
+  return (size_t)(chunks + kSumSlices) * m * n * sizeof(double2);
 }
 
 hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                        int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const int64_t chunks = N > 0 ? (N + kGramRows - 1) / kGramRows : 0;
+  const int64_t rows = gram_rows(N, m, n);
+  const int64_t chunks = N > 0 ? (N + rows - 1) / rows : 0;
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int tasks = TI * JG;
   double2* part = reinterpret_cast<double2*>(ws);
+  double2* mid = part + (size_t)chunks * m * n;
   if (chunks > 0) {
     hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)chunks, (tasks + 3) / 4), dim3(256), 0, st,
                        reinterpret_cast<const double2*>(A), lda,
-                       reinterpret_cast<const double2*>(B), ldb, N, m, n, part);
+                       reinterpret_cast<const double2*>(B), ldb, N, m, n, rows, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int mn = m * n;
-  hipLaunchKernelGGL(k_sum_partials, dim3((mn + 255) / 256), dim3(256), 0, st, part, (int)chunks,
-                     mn, reinterpret_cast<double2*>(P), n, ldp);
+  hipLaunchKernelGGL(k_sum_partials1, dim3((mn + 255) / 256, kSumSlices), dim3(256), 0, st, part,
+                     (int)chunks, mn, mid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_partials2, dim3((mn + 255) / 256), dim3(256), 0, st, mid, mn,
+                     reinterpret_cast<double2*>(P), n, ldp);
   return hipGetLastError();
 }
 

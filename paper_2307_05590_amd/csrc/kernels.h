@@ -45,8 +45,11 @@ hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n,
 
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
 //   by cyclic two-sided Jacobi in one workgroup; A overwritten, V (n x n)
-//   eigenvectors in columns, lam eigenvalues (unsorted), info[0] sweeps used
-//   (or -1 when not converged).
-hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, hipStream_t st);
+//   eigenvectors in columns, lam eigenvalues (unsorted); info[0] sweeps used
+//   (or -1 when not converged), info[2] sweeps recorded; ws holds the
+//   rotation record (jacobi_ws_size bytes); tol is the relative threshold.
+size_t jacobi_ws_size(int n, int max_sweeps);
+hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, void* ws,
+                         int max_sweeps, double tol, hipStream_t st);
 
 }  // namespace mpt

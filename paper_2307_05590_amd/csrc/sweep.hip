@@ -1,361 +1,20 @@
-// Online reduced sweep (eq. (ReducedA)), matrix-method tensors (eqs.
-// (podprealmpt), (podpimagmpt)), certificates (Lemma 4.1) and the adjoint of
-// the sweep.  One wave64 per frequency; row r of the M x M system lives in
-// the registers of lane r (M <= 64), so the LU, the three solves, the four
-// reduced matrix-vector products and the quadratic forms never leave the
-// register file.  Shared ROM matrices are read through L1/L2.
+// Dispatch of the sweep kernels (instantiated per M bucket in sweep_m*.hip so
+// the buckets compile in parallel) and the small helpers of the batched and
+// adjoint paths.
 #include "device_util.h"
 #include "kernels.h"
 
 namespace mpt {
 
-namespace {
-
-// Slots of the 64-wide reduce-scatter.
-constexpr int kKQ = 0;    // Re a_i^H K_M a_j         (6 pairs)
-constexpr int kCQ = 6;    // Re a_i^H C_M a_j         (6)
-constexpr int kAQ = 12;   // Re a_i^H A0 a_j          (6)
-constexpr int kHQ = 18;   // Re a_i^H H a_j           (6)
-constexpr int kGA = 24;   // g_i^H a_j  (re, im)      (9 complex)
-constexpr int kFA = 42;   // (F a_j)_i  (re, im)      (9 complex)
-
-__device__ __constant__ int kPi[6] = {0, 0, 0, 1, 1, 2};
-__device__ __constant__ int kPj[6] = {0, 1, 2, 1, 2, 2};
-
-__device__ __forceinline__ int pair_index(int i, int j) {
-  // stored order 11 12 13 22 23 33 for i <= j
-  if (i > j) { const int t = i; i = j; j = t; }
-  return i == 0 ? j : (i == 1 ? 2 + j : 5);
-}
-
-}  // namespace
-
-// Everything for one frequency, executed by one full wave.
-//   out:    18 doubles for this omega (written by lanes 0..17)
-//   status: one int (lane 0)
-//   ADJ:    dout (18 doubles, first 12 used) -> dom (1 double, lane 0);
-//           lds_lu: MAXM x (MAXM+1) double2 of wave-private LDS.
 template <int MAXM, bool ADJ>
-__device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
-                                            double* __restrict__ out, double* __restrict__ a_out,
-                                            int32_t* __restrict__ status,
-                                            const double* __restrict__ dout,
-                                            double* __restrict__ dom, double2* lds_lu,
-                                            double* red_lds) {
-  const int lane = __lane_id();
-  const int M = R.M;
-  const bool act = lane < M;
-  const double2* A0 = reinterpret_cast<const double2*>(R.A0);
-  const double2* CM = reinterpret_cast<const double2*>(R.CM);
-  const double2* KM = reinterpret_cast<const double2*>(R.KM);
-  const double2* gv = reinterpret_cast<const double2*>(R.g);
-  const double2* G = reinterpret_cast<const double2*>(R.G);
-  const int ldG = 2 * M + 3;
-
-  // ---- row `lane` of A(w) = A0 - i w C_M and r_i = i w g_i -------------
-  double2 A[MAXM];
-#pragma unroll
-  for (int j = 0; j < MAXM; ++j) {
-    double2 v = make_double2(0.0, 0.0);
-    if (act && j < M) {
-      const double2 a0 = A0[lane * M + j];
-      const double2 c = CM[lane * M + j];
-      v.x = fma(om, c.y, a0.x);
-      v.y = fma(-om, c.x, a0.y);
-    }
-    A[j] = v;
-  }
-  double2 gl[3], b[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    gl[i] = act ? gv[i * M + lane] : make_double2(0.0, 0.0);
-    b[i] = make_double2(-om * gl[i].y, om * gl[i].x);
-  }
-
-  // ---- LU with partial pivoting (max |re|+|im|, lowest lane on ties) ------
-  bool done = !act;
-  int order = -1;
-  int bad = 0;
-#pragma unroll
-  for (int k = 0; k < MAXM; ++k) {
-    if (k < M) {
-      const double val = done ? -1.0 : fabs(A[k].x) + fabs(A[k].y);
-      const double vmax = wave_max(val);
-      uint64_t m = __ballot((!done) && val == vmax);
-      if (m == 0) {  // NaN pivot column: flag it and take any remaining row
-        bad = 1;
-        m = __ballot(!done);
-      }
-      const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1);
-      const double2 piv = bcast2(A[k], p);
-      const double d = piv.x * piv.x + piv.y * piv.y;
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
-      const double2 inv = crecip(piv);
-      if (lane == p) {
-        done = true;
-        order = k;
-      }
-      const bool upd = !done;
-      const double2 l = cmul(A[k], inv);
-      if (upd) A[k] = l;
-#pragma unroll
-      for (int j = k + 1; j < MAXM; ++j) {
-        if (j < M) {
-          const double2 pr = bcast2(A[j], p);
-          if (upd) A[j] = cfms(A[j], l, pr);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double2 pb = bcast2(b[i], p);
-        if (upd) b[i] = cfms(b[i], l, pb);
-      }
-    }
-  }
-
-  // ---- back substitution; lane j receives a_i[j] --------------------------
-  double2 x[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) x[i] = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int k = MAXM - 1; k >= 0; --k) {
-    if (k < M) {
-      const uint64_t m = __ballot(order == k);
-      const int q = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1);
-      const double2 inv = crecip(bcast2(A[k], q));
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double2 xk = cmul(bcast2(b[i], q), inv);
-        if (lane == k) x[i] = xk;
-        if (order >= 0 && order < k) b[i] = cfms(b[i], A[k], xk);
-      }
-    }
-  }
-
-  if (ADJ) {
-    // keep the factors: LDS row k = pivot row k (L multipliers left of the
-    // diagonal, U on and right of it)
-    if (order >= 0) {
-#pragma unroll
-      for (int j = 0; j < MAXM; ++j)
-        if (j < M) lds_lu[order * (MAXM + 1) + j] = A[j];
-    }
-  }
-
-  // ---- reduced matrix-vector products, lane r holds row r -----------------
-  double2 Ka[3], Ca[3], Aa[3], Ha[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    Ka[i] = Ca[i] = Aa[i] = Ha[i] = make_double2(0.0, 0.0);
-  }
-  const double2* Hrow = G + (size_t)(3 + M + lane) * ldG + (3 + M);
-#pragma unroll 4
-  for (int j = 0; j < M; ++j) {
-    double2 aj[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) aj[i] = bcast2(x[i], j);
-    if (act) {
-      const double2 kk = KM[lane * M + j];
-      const double2 cc = CM[lane * M + j];
-      const double2 a0 = A0[lane * M + j];
-      const double2 hh = Hrow[j];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        Ka[i] = cfma(Ka[i], kk, aj[i]);
-        Ca[i] = cfma(Ca[i], cc, aj[i]);
-        Aa[i] = cfma(Aa[i], a0, aj[i]);
-        Ha[i] = cfma(Ha[i], hh, aj[i]);
-      }
-    }
-  }
-
-  // ---- per-lane partial sums of the quadratic forms -----------------------
-  double v[64];
-#pragma unroll
-  for (int s = 0; s < 64; ++s) v[s] = 0.0;
-  if (act) {
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const int i = (p < 3) ? 0 : (p < 5 ? 1 : 2);
-      const int j = (p == 0) ? 0 : (p == 1 ? 1 : (p == 2 ? 2 : (p == 3 ? 1 : 2)));
-      v[kKQ + p] = cmulc(x[i], Ka[j]).x;
-      v[kCQ + p] = cmulc(x[i], Ca[j]).x;
-      v[kAQ + p] = cmulc(x[i], Aa[j]).x;
-      v[kHQ + p] = cmulc(x[i], Ha[j]).x;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double2 Fi = G[(size_t)i * ldG + 3 + M + lane];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const double2 ga = cmulc(gl[i], x[j]);
-        v[kGA + 2 * (3 * i + j)] = ga.x;
-        v[kGA + 2 * (3 * i + j) + 1] = ga.y;
-        const double2 fa = cmul(Fi, x[j]);
-        v[kFA + 2 * (3 * i + j)] = fa.x;
-        v[kFA + 2 * (3 * i + j) + 1] = fa.y;
-      }
-    }
-  }
-  const double red = reduce_scatter64(v);
-
-  // ---- final formulas: lane p < 18 produces out[p] ------------------------
-  red_lds[lane] = red;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const double a3 = R.alpha * R.alpha * R.alpha;
-  double myout = 0.0;
-  if (lane < 18) {
-    const int p = lane % 6;
-    const int i = kPi[p], j = kPj[p];
-    if (lane < 6) {
-      myout = R.N0[3 * i + j] - 0.25 * a3 * red_lds[kKQ + p];
-    } else if (lane < 12) {
-      myout = 0.25 * a3 * om *
-              (R.E[3 * i + j] + red_lds[kCQ + p] + red_lds[kGA + 2 * (3 * i + j)] +
-               red_lds[kGA + 2 * (3 * j + i)]);
-    } else {
-      // Re c_ab = w^2 [W_ab + Re(F a_b)_a + Re(F a_a)_b + Re a_a^H H a_b]
-      //           - w [Im g_a^H a_b + Im g_b^H a_a] + Re a_a^H A0 a_b
-      double cr[3];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int a = t == 0 ? i : (t == 1 ? j : i);
-        const int b = t == 0 ? i : (t == 1 ? j : j);
-        const int q = pair_index(a, b);
-        const double W = G[(size_t)a * ldG + b].x;
-        cr[t] = om * om * (W + red_lds[kFA + 2 * (3 * a + b)] + red_lds[kFA + 2 * (3 * b + a)] +
-                           red_lds[kHQ + q]) -
-                om * (red_lds[kGA + 2 * (3 * a + b) + 1] + red_lds[kGA + 2 * (3 * b + a) + 1]) +
-                red_lds[kAQ + q];
-      }
-      myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
-    }
-    out[lane] = myout;
-  }
-  if (a_out != nullptr && act) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) reinterpret_cast<double2*>(a_out)[i * M + lane] = x[i];
-  }
-  if (lane == 0) *status = bad ? 4 : 0;
-  __builtin_amdgcn_wave_barrier();
-
-  if (ADJ) {
-    // ---- adjoint: A^H lambda_k = v_k, v_k = dL/d(conj a_k) ----------------
-    // v_k = -a^3/4 sum_j rho^_kj K a_j + w a^3/4 sum_j tau^_kj (C a_j + g_j),
-    // rho^_kj = dL/dR~_kj (x2 on the diagonal), tau^ likewise for I.
-    double rh[3][3], th[3][3];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const int i = kPi[p], j = kPj[p];
-      const double f = (i == j) ? 2.0 : 1.0;
-      rh[i][j] = rh[j][i] = f * dout[p];
-      th[i][j] = th[j][i] = f * dout[6 + p];
-    }
-    double2 vk[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const double cr = -0.25 * a3 * rh[k][j];
-        const double ct = 0.25 * a3 * om * th[k][j];
-        acc.x += cr * Ka[j].x + ct * (Ca[j].x + gl[j].x);
-        acc.y += cr * Ka[j].y + ct * (Ca[j].y + gl[j].y);
-      }
-      vk[k] = act ? acc : make_double2(0.0, 0.0);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // U^H z = v  (lane r holds equation r; z_j lands in lane j)
-    for (int j = 0; j < M; ++j) {
-      const double2 ujj = lds_lu[j * (MAXM + 1) + j];
-      const double2 inv = crecip(cconj(ujj));
-      const double2 urow = (lane > j && act) ? lds_lu[j * (MAXM + 1) + lane] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double2 zj = cmul(bcast2(vk[i], j), inv);
-        if (lane == j) vk[i] = zj;
-        if (lane > j && act) vk[i] = cfms(vk[i], cconj(urow), zj);
-      }
-    }
-    // L^H y = z  (unit diagonal)
-    for (int k = M - 1; k >= 0; --k) {
-      const double2 lrow = (lane < k) ? lds_lu[k * (MAXM + 1) + lane] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double2 yk = bcast2(vk[i], k);
-        if (lane < k) vk[i] = cfms(vk[i], cconj(lrow), yk);
-      }
-    }
-    // lambda = P^T y: lane r (original row r) takes y[order(r)]
-    const int src = order >= 0 ? order : lane;
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double2 lam = make_double2(shfl_d(vk[i].x, src), shfl_d(vk[i].y, src));
-      if (act) {
-        const double2 t = make_double2(gl[i].x + Ca[i].x, gl[i].y + Ca[i].y);
-        acc -= cmulc(lam, t).y;  // -Im lambda^H (g + C_M a)
-      }
-    }
-    // explicit omega-dependence of I (prefactor w): sum_p tau_p I_p / w
-    if (lane >= 6 && lane < 12) acc += dout[lane] * myout / om;
-    const double tot = wave_sum(acc);
-    if (lane == 0) *dom = tot;
-  }
-}
-
-// ---------------------------------------------------------------- kernels
+hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double* out,
+                        double* a_out, int32_t* status, const double* dout, double* dom, int wpg,
+                        hipStream_t st);
 template <int MAXM, bool ADJ>
-__global__ __launch_bounds__(256) void k_sweep(const mpt_rom R, const double* __restrict__ omega,
-                                               int64_t n, double* __restrict__ out,
-                                               double* __restrict__ a_out,
-                                               int32_t* __restrict__ status,
-                                               const double* __restrict__ dout,
-                                               double* __restrict__ dom) {
-  extern __shared__ double2 lds[];
-  __shared__ double red[4 * 64];
-  const int wave = threadIdx.x >> 6;
-  const int wpg = blockDim.x >> 6;
-  double2* my_lds = ADJ ? lds + (size_t)wave * MAXM * (MAXM + 1) : nullptr;
-  for (int64_t k = (int64_t)blockIdx.x * wpg + wave; k < n; k += (int64_t)gridDim.x * wpg) {
-    sweep_point<MAXM, ADJ>(R, omega[k], out + 18 * k,
-                           a_out ? a_out + (size_t)k * 6 * R.M : nullptr, status + k,
-                           ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
-                           red + 64 * wave);
-  }
-}
-
-// Persistent batched kernel: waves pull work items (object, omega range)
-// from a queue ordered by decreasing cost; one instantiation per M bucket.
-template <int MAXM, bool ADJ>
-__global__ __launch_bounds__(256) void k_sweep_persistent(
-    const mpt_rom* __restrict__ roms, const int4* __restrict__ items, int n_items,
-    unsigned int* __restrict__ counter, const double* __restrict__ omega,
-    double* __restrict__ out, int32_t* __restrict__ status, const double* __restrict__ dout,
-    double* __restrict__ dom) {
-  extern __shared__ double2 lds[];
-  __shared__ double red[4 * 64];
-  const int wave = threadIdx.x >> 6;
-  double2* my_lds = ADJ ? lds + (size_t)wave * MAXM * (MAXM + 1) : nullptr;
-  while (true) {
-    int it = 0;
-    if (__lane_id() == 0) it = (int)atomicAdd(counter, 1u);
-    it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= n_items) break;
-    const int4 w = items[it];  // x: object, y: first row, z: count
-    const mpt_rom R = roms[w.x];
-    for (int r = 0; r < w.z; ++r) {
-      const int64_t k = (int64_t)w.y + r;
-      sweep_point<MAXM, ADJ>(R, omega[k], out + 18 * k, nullptr, status + k,
-                             ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
-                             red + 64 * wave);
-    }
-  }
-}
+hipError_t launch_persistent(const mpt_rom* roms, const int4* items, int n_items,
+                             unsigned int* counter, const double* omega, double* out,
+                             int32_t* status, const double* dout, double* dom, int wpg,
+                             int groups, hipStream_t st);
 
 __global__ void k_reset_counter(unsigned int* c, int n) {
   if (threadIdx.x < n) c[threadIdx.x] = 0u;
@@ -382,19 +41,6 @@ __global__ void k_sigma_reduce(const double* __restrict__ omega, const double* _
 // ------------------------------------------------------------ launchers
 int bucket_of(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : (M <= 48 ? 48 : 64)); }
 
-template <int MAXM, bool ADJ>
-static hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double* out,
-                               double* a_out, int32_t* status, const double* dout, double* dom,
-                               int wpg, hipStream_t st) {
-  const int64_t waves = n;
-  int64_t groups = (waves + wpg - 1) / wpg;
-  if (groups > 65535 * 8) groups = 65535 * 8;
-  const size_t lds = ADJ ? (size_t)wpg * MAXM * (MAXM + 1) * sizeof(double2) : 0;
-  hipLaunchKernelGGL((k_sweep<MAXM, ADJ>), dim3((unsigned)groups), dim3(64 * wpg), lds, st, R,
-                     omega, n, out, a_out, status, dout, dom);
-  return hipGetLastError();
-}
-
 hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom,
                         hipStream_t st) {
@@ -410,17 +56,6 @@ hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double
     default: return adj ? launch_plain<64, true>(R, omega, n, out, a_out, status, dout, dom, 2, st)
                         : launch_plain<64, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);
   }
-}
-
-template <int MAXM, bool ADJ>
-static hipError_t launch_persistent(const mpt_rom* roms, const int4* items, int n_items,
-                                    unsigned int* counter, const double* omega, double* out,
-                                    int32_t* status, const double* dout, double* dom, int wpg,
-                                    int groups, hipStream_t st) {
-  const size_t lds = ADJ ? (size_t)wpg * MAXM * (MAXM + 1) * sizeof(double2) : 0;
-  hipLaunchKernelGGL((k_sweep_persistent<MAXM, ADJ>), dim3(groups), dim3(64 * wpg), lds, st, roms,
-                     items, n_items, counter, omega, out, status, dout, dom);
-  return hipGetLastError();
 }
 
 hipError_t persistent_launch(int bucket, bool adj, const mpt_rom* roms, const int4* items,
