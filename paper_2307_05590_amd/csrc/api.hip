@@ -380,7 +380,8 @@ static void proj_layout(int64_t N, int M, int64_t nc, size_t* off) {
   off[10] = o; o = align256(o + (size_t)N * 3 * 16);        // KO
   off[11] = o; o = align256(o + 9 * 16);                    // No
   off[12] = o;
-  o = align256(o + std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)));
+  o = align256(o + std::max(std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)),
+                            rcgemm_ws_size(nc, L)));
   off[13] = o;
 }
 
@@ -449,7 +450,7 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
                        reinterpret_cast<double2*>(Wc));
     HIP_OK(hipGetLastError());
   }
-  HIP_OK(real_complex_gemm(S, n_c, Zc, L, T, st));
+  HIP_OK(real_complex_gemm(S, n_c, Zc, L, T, gws, st));
   HIP_OK(gram_launch(Zc, L, T, L, n_c, L, L, Gc, L, gws, st));
   HIP_OK(gram_launch(Uc, M, Zc, L, n_c, M, L, P, L, gws, st));
   HIP_OK(gram_launch(Wc, 3, Zc, L, n_c, 3, 3, Ew, 3, gws, st));

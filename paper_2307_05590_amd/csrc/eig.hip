@@ -45,13 +45,24 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
   __shared__ int rp[kJacobiMaxN / 2], rq[kJacobiMaxN / 2];
   __shared__ int nrot;
   __shared__ double dmax;
+  // LDS copy with a padded row stride (n+1 complex) against bank conflicts
+  const int ld = SHARED_A ? n + 1 : n;
   double2* A = SHARED_A ? smem : Ag;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (SHARED_A)
-    for (int i = tid; i < n * n; i += nt) A[i] = Ag[i];
+    for (int i = tid; i < n * n; i += nt) A[(i / n) * ld + i % n] = Ag[i];
   const int ne = n + (n & 1);
   const int np = ne / 2;
   const int nblk = np * (np + 1) / 2;
+  // block table: e -> (ta, tb), ta <= tb, packed in the LDS tail
+  unsigned short* tab = reinterpret_cast<unsigned short*>(SHARED_A ? smem + (size_t)n * ld : smem);
+  for (int e = tid; e < nblk; e += nt) {
+    int t1 = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((t1 + 1) * (t1 + 2) / 2 <= e) ++t1;
+    while (t1 * (t1 + 1) / 2 > e) --t1;
+    tab[2 * e] = (unsigned short)(e - t1 * (t1 + 1) / 2);
+    tab[2 * e + 1] = (unsigned short)t1;
+  }
   int sweep = 0;
   bool converged = false;
   __syncthreads();
@@ -59,7 +70,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
     if (tid == 0) {
       nrot = 0;
       double m = 0.0;
-      for (int i = 0; i < n; ++i) m = fmax(m, fabs(A[i * n + i].x));
+      for (int i = 0; i < n; ++i) m = fmax(m, fabs(A[i * ld + i].x));
       dmax = m;
     }
     __syncthreads();
@@ -70,8 +81,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
         rr_pair(t, r, ne, p, q);
         Rot R = {1.0, 0.0, make_double2(1.0, 0.0)};
         if (q < n) {
-          const double a = A[p * n + p].x, d = A[q * n + q].x;
-          const double2 b = A[p * n + q];
+          const double a = A[p * ld + p].x, d = A[q * ld + q].x;
+          const double2 b = A[p * ld + q];
           const double ab = sqrt(b.x * b.x + b.y * b.y);
           if (ab > floor_abs && ab > 1e-300 && ab > tol * sqrt(fabs(a * d))) {
             const double tau = (d - a) / (2.0 * ab);
@@ -79,7 +90,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
             R.c = 1.0 / sqrt(1.0 + tt * tt);
             R.s = tt * R.c;
             R.ph = make_double2(b.x / ab, -b.y / ab);
-            atomicAdd(&nrot, 1);
+            nrot = 1;  // any rotation this sweep (benign same-value race)
           }
         }
         rot[t] = R;
@@ -90,20 +101,15 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
       __syncthreads();
       // 2x2 blocks (t1 <= t2): B <- Q1^H B Q2, Q = [[c, s], [-s ph, c ph]]
       for (int e = tid; e < nblk; e += nt) {
-        // map e -> (t1, t2) with t1 <= t2
-        int t1 = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((t1 + 1) * (t1 + 2) / 2 <= e) ++t1;
-        while (t1 * (t1 + 1) / 2 > e) --t1;
-        const int t2i = e - t1 * (t1 + 1) / 2;  // 0..t1
-        const int ta = t2i, tb = t1;              // ta <= tb
+        const int ta = tab[2 * e], tb = tab[2 * e + 1];  // ta <= tb
         const int p1 = rp[ta], q1 = rq[ta], p2 = rp[tb], q2 = rq[tb];
         const Rot R1 = rot[ta], R2 = rot[tb];
         if (R1.s == 0.0 && R2.s == 0.0) continue;
         const bool v1 = q1 < n, v2 = q2 < n;
-        double2 b00 = A[p1 * n + p2];
-        double2 b01 = v2 ? A[p1 * n + q2] : make_double2(0.0, 0.0);
-        double2 b10 = v1 ? A[q1 * n + p2] : make_double2(0.0, 0.0);
-        double2 b11 = (v1 && v2) ? A[q1 * n + q2] : make_double2(0.0, 0.0);
+        double2 b00 = A[p1 * ld + p2];
+        double2 b01 = v2 ? A[p1 * ld + q2] : make_double2(0.0, 0.0);
+        double2 b10 = v1 ? A[q1 * ld + p2] : make_double2(0.0, 0.0);
+        double2 b11 = (v1 && v2) ? A[q1 * ld + q2] : make_double2(0.0, 0.0);
         // right: B Q2 (columns p2, q2)
         if (R2.s != 0.0) {
           const double c = R2.c, s = R2.s;
@@ -126,26 +132,26 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
           b00 = n00; b01 = n01; b10 = n10; b11 = n11;
         }
         if (ta == tb) {  // diagonal block: exactly diagonal after the rotation
-          A[p1 * n + p1] = make_double2(b00.x, 0.0);
+          A[p1 * ld + p1] = make_double2(b00.x, 0.0);
           if (v1) {
-            A[q1 * n + q1] = make_double2(b11.x, 0.0);
-            A[p1 * n + q1] = make_double2(0.0, 0.0);
-            A[q1 * n + p1] = make_double2(0.0, 0.0);
+            A[q1 * ld + q1] = make_double2(b11.x, 0.0);
+            A[p1 * ld + q1] = make_double2(0.0, 0.0);
+            A[q1 * ld + p1] = make_double2(0.0, 0.0);
           }
         } else {
-          A[p1 * n + p2] = b00;
-          A[p2 * n + p1] = cconj(b00);
+          A[p1 * ld + p2] = b00;
+          A[p2 * ld + p1] = cconj(b00);
           if (v2) {
-            A[p1 * n + q2] = b01;
-            A[q2 * n + p1] = cconj(b01);
+            A[p1 * ld + q2] = b01;
+            A[q2 * ld + p1] = cconj(b01);
           }
           if (v1) {
-            A[q1 * n + p2] = b10;
-            A[p2 * n + q1] = cconj(b10);
+            A[q1 * ld + p2] = b10;
+            A[p2 * ld + q1] = cconj(b10);
           }
           if (v1 && v2) {
-            A[q1 * n + q2] = b11;
-            A[q2 * n + q1] = cconj(b11);
+            A[q1 * ld + q2] = b11;
+            A[q2 * ld + q1] = cconj(b11);
           }
         }
       }
@@ -157,9 +163,9 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double2* __restrict__
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += nt) lam[i] = A[i * n + i].x;
+  for (int i = tid; i < n; i += nt) lam[i] = A[i * ld + i].x;
   if (SHARED_A)
-    for (int i = tid; i < n * n; i += nt) Ag[i] = A[i];
+    for (int i = tid; i < n * n; i += nt) Ag[i] = A[(i / n) * ld + i % n];
   if (tid == 0) {
     info[0] = converged ? sweep + 1 : -1;
     info[2] = converged ? sweep + 1 : max_sweeps;  // recorded sweeps
@@ -209,12 +215,14 @@ hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, vo
   if (n <= 0) return hipSuccess;
   if (n > kJacobiMaxN) return hipErrorInvalidValue;
   Rot* rec = reinterpret_cast<Rot*>(ws);
-  const size_t lds = (size_t)n * n * sizeof(double2);
-  if (lds <= 148 * 1024) {
+  const int ne = n + (n & 1), np = ne / 2;
+  const size_t tab = (size_t)np * (np + 1) * sizeof(unsigned short) + 16;
+  const size_t lds = (size_t)n * (n + 1) * sizeof(double2) + tab;
+  if (lds <= 156 * 1024) {  // plus ~4 KB static: within the 160 KB of a CU
     hipLaunchKernelGGL((k_jacobi<true>), dim3(1), dim3(kJacobiThreads), lds, st,
                        reinterpret_cast<double2*>(A), n, lam, rec, info, max_sweeps, tol);
   } else {
-    hipLaunchKernelGGL((k_jacobi<false>), dim3(1), dim3(kJacobiThreads), 0, st,
+    hipLaunchKernelGGL((k_jacobi<false>), dim3(1), dim3(kJacobiThreads), tab, st,
                        reinterpret_cast<double2*>(A), n, lam, rec, info, max_sweeps, tol);
   }
   hipError_t e = hipGetLastError();

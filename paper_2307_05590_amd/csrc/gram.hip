@@ -35,12 +35,14 @@ __host__ __device__ inline int64_t gram_rows(int64_t N, int m, int n) {
 __global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict__ A, int64_t lda,
                                                       const double2* __restrict__ B, int64_t ldb,
                                                       int64_t N, int m, int n, int64_t rows,
-                                                      double2* __restrict__ part) {
+                                                      int herm, double2* __restrict__ part) {
   const int lane = __lane_id();
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int task = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (task >= TI * JG) return;
   const int I = task / JG, jg = task % JG;
+  // Hermitian product (A == B): tiles left of the diagonal come from their mirror
+  if (herm && jg * 4 + 3 < I) return;
   const int64_t r0 = (int64_t)blockIdx.x * rows;
   const int64_t r1 = min(N, r0 + rows);
   const int ar = I * 16 + (lane & 15);  // column of A feeding this lane
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict_
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int J = jg * 4 + t;
-      if (J < TJ) {
+      if (J < TJ && !(herm && J < I)) {
         const int bc = J * 16 + (lane & 15);
         const double2 bb = (rok && bc < n) ? B[row * ldb + bc] : make_double2(0.0, 0.0);
         // P = A^H B: re = ar.br + ai.bi ; im = ar.bi - ai.br
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict_
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int J = jg * 4 + t;
-    if (J >= TJ) continue;
+    if (J >= TJ || (herm && J < I)) continue;
     const int col = J * 16 + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -104,16 +106,20 @@ __global__ void k_sum_partials1(const double2* __restrict__ part, int nparts, in
 }
 
 __global__ void k_sum_partials2(const double2* __restrict__ mid, int mn,
-                                double2* __restrict__ P, int n, int64_t ldp) {
+                                double2* __restrict__ P, int n, int64_t ldp, int herm) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mn) return;
+  const int i = idx / n, j = idx % n;
+  // mirrored tile of a Hermitian product: conj of the computed (j, i) entry
+  const bool mirror = herm && (j / 16) < (i / 16);
+  const int src = mirror ? j * n + i : idx;
   double2 s = make_double2(0.0, 0.0);
   for (int sl = 0; sl < kSumSlices; ++sl) {
-    const double2 v = mid[(size_t)sl * mn + idx];
+    const double2 v = mid[(size_t)sl * mn + src];
     s.x += v.x;
     s.y += v.y;
   }
-  P[(idx / n) * ldp + idx % n] = s;
+  P[i * ldp + j] = mirror ? make_double2(s.x, -s.y) : s;
 }
 
 size_t gram_ws_size(int64_t N, int m, int n) {
@@ -131,10 +137,11 @@ hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ld
   const int tasks = TI * JG;
   double2* part = reinterpret_cast<double2*>(ws);
   double2* mid = part + (size_t)chunks * m * n;
+  const int herm = (A == B && lda == ldb && m == n) ? 1 : 0;
   if (chunks > 0) {
     hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)chunks, (tasks + 3) / 4), dim3(256), 0, st,
                        reinterpret_cast<const double2*>(A), lda,
-                       reinterpret_cast<const double2*>(B), ldb, N, m, n, rows, part);
+                       reinterpret_cast<const double2*>(B), ldb, N, m, n, rows, herm, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -144,7 +151,7 @@ hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ld
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_partials2, dim3((mn + 255) / 256), dim3(256), 0, st, mid, mn,
-                     reinterpret_cast<double2*>(P), n, ldp);
+                     reinterpret_cast<double2*>(P), n, ldp, herm);
   return hipGetLastError();
 }
 
@@ -210,10 +217,13 @@ hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const d
   return hipGetLastError();
 }
 
-// T (r x n) = S (r x r real, row-major) Z (r x n complex)
+// T (r x n) = S (r x r real, row-major) Z (r x n complex), split over the
+// reduction index in chunks of kRcK (grid.y) with a fixed-order final sum
+constexpr int kRcK = 128;
+
 __global__ __launch_bounds__(256) void k_rcgemm(const double* __restrict__ S, int64_t r,
                                                 const double2* __restrict__ Z, int n,
-                                                double2* __restrict__ T) {
+                                                double2* __restrict__ part) {
   const int lane = __lane_id();
   const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -223,26 +233,29 @@ __global__ __launch_bounds__(256) void k_rcgemm(const double* __restrict__ S, in
   const int jg = (int)(task % JG);
   const int64_t row = rt * 16 + (lane & 15);
   const bool rok = row < r;
+  const int64_t kb = (int64_t)blockIdx.y * kRcK, ke = min(r, kb + kRcK);
   double4_t accr[4], acci[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     accr[t] = double4_t{0, 0, 0, 0};
     acci[t] = double4_t{0, 0, 0, 0};
   }
-  for (int64_t k0 = 0; k0 < r; k0 += 4) {
+  for (int64_t k0 = kb; k0 < ke; k0 += 4) {
     const int64_t k = k0 + (lane >> 4);
-    const double s = (rok && k < r) ? S[row * r + k] : 0.0;
+    const bool kok = k < ke;
+    const double s = (rok && kok) ? S[row * r + k] : 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int J = jg * 4 + t;
       if (J < TJ) {
         const int col = J * 16 + (lane & 15);
-        const double2 z = (k < r && col < n) ? Z[k * n + col] : make_double2(0.0, 0.0);
+        const double2 z = (kok && col < n) ? Z[k * n + col] : make_double2(0.0, 0.0);
         accr[t] = mfma(s, z.x, accr[t]);
         acci[t] = mfma(s, z.y, acci[t]);
       }
     }
   }
+  double2* T = part + (size_t)blockIdx.y * r * n;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int J = jg * 4 + t;
@@ -256,13 +269,38 @@ __global__ __launch_bounds__(256) void k_rcgemm(const double* __restrict__ S, in
   }
 }
 
+__global__ void k_rc_sum(const double2* __restrict__ part, int nk, int64_t cnt,
+                         double2* __restrict__ T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int y = 0; y < nk; ++y) {
+    const double2 v = part[(size_t)y * cnt + i];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  T[i] = s;
+}
+
+size_t rcgemm_ws_size(int64_t r, int n) {
+  const int64_t nk = (r + kRcK - 1) / kRcK;
+  return (size_t)nk * r * n * sizeof(double2);
+}
+
 hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
-                             hipStream_t st) {
+                             void* ws, hipStream_t st) {
   if (r <= 0 || n <= 0) return hipSuccess;
   const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int64_t tasks = ((r + 15) / 16) * JG;
-  hipLaunchKernelGGL(k_rcgemm, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st, S, r,
-                     reinterpret_cast<const double2*>(Z), n, reinterpret_cast<double2*>(T));
+  const int nk = (int)((r + kRcK - 1) / kRcK);
+  double2* part = reinterpret_cast<double2*>(ws);
+  hipLaunchKernelGGL(k_rcgemm, dim3((unsigned)((tasks + 3) / 4), nk), dim3(256), 0, st, S, r,
+                     reinterpret_cast<const double2*>(Z), n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t cnt = r * n;
+  hipLaunchKernelGGL(k_rc_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, part, nk,
+                     cnt, reinterpret_cast<double2*>(T));
   return hipGetLastError();
 }
 

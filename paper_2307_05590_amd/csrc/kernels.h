@@ -39,9 +39,10 @@ hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ld
 //   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv).
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
                          int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st);
-//   T (r x n) = S (r x r, real) * Z (r x n, complex)
+//   T (r x n) = S (r x r, real) * Z (r x n, complex); ws of rcgemm_ws_size
+size_t rcgemm_ws_size(int64_t r, int n);
 hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
-                             hipStream_t st);
+                             void* ws, hipStream_t st);
 
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
 //   by cyclic two-sided Jacobi in one workgroup; A overwritten, V (n x n)
