@@ -11,7 +11,18 @@ Inputs (snapshots, operator, conductor block) are generated on the host before
 timing and are resident in HBM.  value = output frequencies (tensor +
 certificate each) per second of step time.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--forms]
+Two more forms sit beside the plain path (each prints its own JSON line):
+  --form batched   256-object dictionary on 32^3 grids (M ~ U{8..48}, 500-4000
+                   omegas each): one persistent, graph-captured, autotuned launch
+                   (mpt_sweep_batched) against the plain per-object path
+  --form adjoint   64 ellipsoids on 48^3 (M ~ U{8..32}, 2000 omegas): forward
+                   sweep + adjoint sweep (dJ/domega, dJ/dsigma) of
+                   J = sum |I_ij|^2 + |R~_ij - N0_ij|^2, batched and per object
+For these forms the dictionary's snapshots are refined to 1e-6 relative
+residual (the reduced models stay Galerkin projections of the full operator).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--form plain|batched|adjoint] [--objects N]
 """
 from __future__ import annotations
 
@@ -55,6 +66,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--form", choices=["plain", "batched", "adjoint"], default="plain")
+    ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -68,6 +81,8 @@ def main():
 
     mpt.lib()
     dev = torch.device("cuda:0")
+    if args.form != "plain":
+        return bench_dictionary(args)
     t0 = time.time()
     log("generating the ellipsoid48 workload (full-order snapshots on the host) ...")
     p = make_problem("ellipsoid48", verbose=True)
@@ -177,6 +192,188 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def build_dictionary(name, n_obj, dev, keep=2, tol_snap=1e-6):
+    """Full-order data per object on the host (shared region Green's function),
+    then the GPU POD basis (fixed rank) and projection per object."""
+    import torch
+
+    from paper_2307_05590_amd import mpt
+    from synth import WORKLOADS, make_problem
+    from synth.workloads import region_green
+    from synth.yee import YeeGrid
+
+    wl = WORKLOADS[name]
+    g = YeeGrid(wl.n)
+    C = g.curl()
+    t0 = time.time()
+    log(f"{name}: region Green's function on the {wl.n}^3 grid ...")
+    gr = region_green(name, g, verbose=True)
+    log(f"  {gr.idx.size} edges in {time.time() - t0:.0f} s")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    roms, omegas, sigmas, kept = [], [], [], []
+    for o in range(n_obj):
+        p = make_problem(name, o, grid=g, curl=C, tol=tol_snap, green=gr)
+        ops = p.ops
+        U, sig, M = mpt.mpt_pod_basis(T(p.D, torch.complex128), 0.0, p.M_cap)
+        rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K, dev), T(ops.c, torch.float64), ops.eps_h,
+                              T(p.w, torch.float64), T(p.o, torch.float64) if np.any(p.o) else None,
+                              T(ops.vol, torch.float64), ops.alpha, U, T(ops.cond_idx, torch.int32),
+                              T(p.S, torch.float64))
+        roms.append(rom)
+        omegas.append(T(p.omega, torch.float64))
+        sigmas.append(p.draw.shape.materials[0][0])
+        if len(kept) < keep:
+            kept.append(p)
+        if o % 16 == 15 or o == n_obj - 1:
+            torch.cuda.synchronize()
+            log(f"  {o + 1}/{n_obj} objects ({time.time() - t0:.0f} s)")
+    return roms, omegas, sigmas, kept
+
+
+def bench_dictionary(args):
+    import torch
+
+    from paper_2307_05590_amd import autotune, mpt
+
+    dev = torch.device("cuda:0")
+    name = "dictionary32" if args.form == "batched" else "adjoint48"
+    from synth import WORKLOADS
+    n_obj = args.objects or WORKLOADS[name].n_objects
+    roms, omegas, sigmas, kept = build_dictionary(name, n_obj, dev)
+    dic = mpt.Dictionary(roms, omegas)
+    n_units = int(dic.omega.numel())
+    Ms = np.array([r.M for r in roms])
+    flops = float(sum(sweep_flops(r.M) * w.numel() for r, w in zip(roms, omegas)))
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    res = {"plain_ms": None}
+    if args.form == "batched":
+        best, best_ms, cached = autotune.tune(dic, verbose=True)
+        log(f"autotuned schedule {best} ({best_ms:.3f} ms, cached={cached})")
+        out = torch.empty((n_units, 18), dtype=torch.float64, device=dev)
+        st = torch.empty(n_units, dtype=torch.int32, device=dev)
+
+        def step():
+            mpt.mpt_sweep_batched(dic, tune=best, use_graph=True, out=out, status=st)
+
+        def plain():
+            for r, w in zip(roms, omegas):
+                mpt.mpt_sweep(r, w)
+        tune_info = {"omegas_per_item": best[0], "waves_per_group": best[1], "groups_per_cu": best[2]}
+    else:
+        mult = torch.tensor([1.0, 2.0, 2.0, 1.0, 2.0, 2.0], dtype=torch.float64, device=dev)
+        n0 = torch.cat([torch.stack([r.N0[0, 0], r.N0[0, 1], r.N0[0, 2], r.N0[1, 1], r.N0[1, 2],
+                                     r.N0[2, 2]])[None].expand(w.numel(), 6)
+                        for r, w in zip(roms, omegas)])
+        dout = torch.zeros((n_units, 18), dtype=torch.float64, device=dev)
+        out = torch.empty((n_units, 18), dtype=torch.float64, device=dev)
+        st = torch.empty(n_units, dtype=torch.int32, device=dev)
+        best = (8, 2, 2)
+
+        def step():
+            mpt.mpt_sweep_batched(dic, tune=best, use_graph=True, out=out, status=st)
+            # dJ/dout of J = sum_omega sum_ij I_ij^2 + (R~_ij - N0_ij)^2 (caller's objective)
+            dout[:, :6] = 2.0 * (out[:, :6] - n0) * mult
+            dout[:, 6:12] = 2.0 * out[:, 6:12] * mult
+            mpt.mpt_sweep_adjoint_batched(dic, dout)
+
+        def plain():
+            for o, (r, w) in enumerate(zip(roms, omegas)):
+                a, b = dic.offsets[o], dic.offsets[o + 1]
+                o1, _ = mpt.mpt_sweep(r, w)
+                d = torch.zeros((w.numel(), 18), dtype=torch.float64, device=dev)
+                d[:, :6] = 2.0 * (o1[:, :6] - n0[a:b]) * mult
+                d[:, 6:12] = 2.0 * o1[:, 6:12] * mult
+                mpt.mpt_sweep_adjoint(r, w, d)
+        tune_info = {"omegas_per_item": best[0], "waves_per_group": best[1], "groups_per_cu": best[2]}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    t1 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    ms_step = 1e3 * elapsed / args.steps
+    assert int(st.abs().max()) == 0, "singular reduced system"
+    plain()
+    torch.cuda.synchronize()
+    p0, p1 = ev(), ev()
+    p0.record()
+    plain()
+    p1.record()
+    torch.cuda.synchronize()
+    plain_ms = p0.elapsed_time(p1)
+    value = n_units / (elapsed / args.steps)
+    kernel_ms = e0.elapsed_time(e1) / args.steps
+    # the adjoint kernel recomputes the forward work and adds the three A^H
+    # solves (24 M^2) and the gradient dots (~24 M^2)
+    fl = flops if args.form == "batched" else float(
+        sum((2 * sweep_flops(r.M) + 48 * r.M ** 2) * w.numel() for r, w in zip(roms, omegas)))
+    achieved = fl / (kernel_ms * 1e-3) / 1e12
+    cpu = None if args.no_cpu else cpu_baseline_dictionary(kept, args.form, args.cpu_seconds)
+    line = {
+        "metric": "MPT tensors/sec (3x3 + error cert per omega per object)" if args.form == "batched"
+                  else "MPT tensors/sec with adjoint gradients (dJ/domega, dJ/dsigma) per omega per object",
+        "value": round(value, 1), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"{name}: {n_obj} seeded objects" +
+                                (" (ellipsoids/cuboids/tori, random SO(3), sigma log-U[1e6,6e7], "
+                                 "mu_r in {1,8,32}) on 32^3 grids" if args.form == "batched"
+                                 else " (ellipsoids as ellipsoid48) on 48^3 grids")),
+                   "n_objects": n_obj, "n_units": n_units, "M_min": int(Ms.min()),
+                   "M_max": int(Ms.max()), "M_mean": round(float(Ms.mean()), 2),
+                   "schedule": tune_info},
+        "plain_path": {"value": round(n_units / (plain_ms * 1e-3), 1), "ms": round(plain_ms, 4),
+                       "speedup": round(plain_ms / kernel_ms, 3)},
+        "roofline": {"kernel": "persistent batched sweep" + (" + adjoint" if args.form == "adjoint" else ""),
+                     "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TF, 4),
+                     "traffic": None, "launch_ms": round(kernel_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_dictionary(kept, form, budget_s):
+    """The CPU oracle on a bounded sample: POD, projection, residual Gram and the
+    sweep (or the forward sensitivities) of the first objects."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import rom as R
+    from oracle.grid import FullOrder
+
+    done, t = 0, 0.0
+    for p in kept:
+        ops = p.ops
+        t0 = time.perf_counter()
+        fo = FullOrder(ops.grid.n, ops.sigma_e, ops.mu_f, ops.alpha, ops.eps)
+        U, s, M = R.pod_basis(p.D, 0.0, p.M_cap)
+        rom = R.project(fo.K, fo.c, fo.eps_h, p.w, U)
+        rom["N0"] = R.static_tensor_mesh(fo, p.o)
+        G = R.residual_gram_schur(p.S, ops.cond_idx, fo.c, p.w, U, rom["KM"], rom["UhU"], fo.eps_h)
+        t += time.perf_counter() - t0
+        om = p.omega[: max(1, int(len(p.omega) * min(1.0, budget_s / 20.0)))]
+        t0 = time.perf_counter()
+        out, _ = R.sweep(rom, om, G, ops.alpha)
+        if form == "adjoint":
+            w6 = np.ones((om.size, 6))
+            R.forward_sensitivity(rom, om, ops.alpha, w6, w6)
+        t += time.perf_counter() - t0
+        done += om.size
+        if t > budget_s:
+            break
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": round(done / t, 2), "unit": "tensors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(kept)} objects: oracle POD + projection + residual Gram + "
+                      f"{'sweep + forward sensitivities' if form == 'adjoint' else 'sweep'} "
+                      f"over {done} frequencies in {t:.1f} s"}
 
 
 def cpu_baseline(p, budget_s):

@@ -1,9 +1,15 @@
 // Online reduced sweep (eq. (ReducedA)), matrix-method tensors (eqs.
 // (podprealmpt), (podpimagmpt)), certificates (Lemma 4.1) and the adjoint of
-// the sweep.  One wave64 per frequency; row r of the M x M system lives in
-// the registers of lane r (M <= 64), so the LU, the three solves, the four
-// reduced matrix-vector products and the quadratic forms never leave the
-// register file.  Shared ROM matrices are read through L1/L2.
+// the sweep.
+//
+// A wave64 is split into segments of L = 16, 32 or 64 lanes (the smallest
+// that holds M rows); each segment solves one frequency, so a wave sweeps
+// 64/L frequencies at once.  Row r of the M x M system lives in the registers
+// of lane r of its segment: the LU with partial pivoting, the three solves,
+// the four reduced matrix-vector products and the quadratic forms never leave
+// the register file.  Pivot rows and solution entries are broadcast inside a
+// segment (v_readlane for whole waves, ds_bpermute otherwise); the quadratic
+// forms are reduce-scattered inside the segment in a fixed order.
 #pragma once
 #include "device_util.h"
 #include "kernels.h"
@@ -12,7 +18,7 @@ namespace mpt {
 
 namespace {
 
-// Slots of the 64-wide reduce-scatter.
+// Slots of the reduce-scatter (64 per frequency).
 constexpr int kKQ = 0;    // Re a_i^H K_M a_j         (6 pairs)
 constexpr int kCQ = 6;    // Re a_i^H C_M a_j         (6)
 constexpr int kAQ = 12;   // Re a_i^H A0 a_j          (6)
@@ -29,23 +35,65 @@ __device__ __forceinline__ int pair_index(int i, int j) {
   return i == 0 ? j : (i == 1 ? 2 + j : 5);
 }
 
+template <int MAXM>
+struct SegOf {
+  static constexpr int L = MAXM <= 16 ? 16 : (MAXM <= 32 ? 32 : 64);  // lanes per frequency
+  static constexpr int S = 64 / L;                                     // frequencies per wave
+};
+
+// broadcast from lane src of this lane's segment (src is a lane id of the wave)
+template <int L>
+__device__ __forceinline__ double seg_bcast(double v, int src) {
+  if constexpr (L == 64) return bcast(v, __builtin_amdgcn_readfirstlane(src));
+  else return shfl_d(v, src);
+}
+template <int L>
+__device__ __forceinline__ double2 seg_bcast2(double2 v, int src) {
+  return make_double2(seg_bcast<L>(v.x, src), seg_bcast<L>(v.y, src));
+}
+template <int L>
+__device__ __forceinline__ double seg_max(double v) {
+#pragma unroll
+  for (int m = L / 2; m >= 1; m >>= 1) v = fmax(v, shfl_xor_d(v, m));
+  return v;
+}
+template <int L>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int m = L / 2; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+// first lane (as a wave lane id) of the segment whose predicate holds; -1 if none
+template <int L>
+__device__ __forceinline__ int seg_first(bool pred, int base) {
+  const uint64_t m = __ballot(pred);
+  const uint64_t mask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+  const uint64_t s = (m >> base) & mask;
+  return s ? base + (__ffsll((unsigned long long)s) - 1) : -1;
+}
+
 }  // namespace
 
-// Everything for one frequency, executed by one full wave.
-//   out:    18 doubles for this omega (written by lanes 0..17)
-//   status: one int (lane 0)
-//   ADJ:    dout (18 doubles, first 12 used) -> dom (1 double, lane 0);
-//           lds_lu: MAXM x (MAXM+1) double2 of wave-private LDS.
+// Everything for one frequency, executed by one segment of L lanes.
+//   out:    18 doubles for this omega
+//   status: one int
+//   ADJ:    dout (18 doubles, first 12 used) -> dom (1 double);
+//           lds_lu: MAXM x (MAXM+1) double2 private to the segment.
+//   red_lds: 64 doubles private to the segment.
+//   valid:  false for a padding segment (computes, writes nothing).
 template <int MAXM, bool ADJ>
-__device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
+__device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, const bool valid,
                                             double* __restrict__ out, double* __restrict__ a_out,
                                             int32_t* __restrict__ status,
                                             const double* __restrict__ dout,
                                             double* __restrict__ dom, double2* lds_lu,
                                             double* red_lds) {
-  const int lane = __lane_id();
+  constexpr int L = SegOf<MAXM>::L;
+  const int wl = __lane_id();
+  const int ll = wl & (L - 1);   // lane within the segment
+  const int base = wl - ll;      // first lane of the segment
   const int M = R.M;
-  const bool act = lane < M;
+  const bool act = ll < M;
   const double2* A0 = reinterpret_cast<const double2*>(R.A0);
   const double2* CM = reinterpret_cast<const double2*>(R.CM);
   const double2* KM = reinterpret_cast<const double2*>(R.KM);
@@ -53,14 +101,14 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
   const double2* G = reinterpret_cast<const double2*>(R.G);
   const int ldG = 2 * M + 3;
 
-  // ---- row `lane` of A(w) = A0 - i w C_M and r_i = i w g_i -------------
+  // ---- row `ll` of A(w) = A0 - i w C_M and r_i = i w g_i ---------------
   double2 A[MAXM];
 #pragma unroll
   for (int j = 0; j < MAXM; ++j) {
     double2 v = make_double2(0.0, 0.0);
     if (act && j < M) {
-      const double2 a0 = A0[lane * M + j];
-      const double2 c = CM[lane * M + j];
+      const double2 a0 = A0[ll * M + j];
+      const double2 c = CM[ll * M + j];
       v.x = fma(om, c.y, a0.x);
       v.y = fma(-om, c.x, a0.y);
     }
@@ -69,11 +117,11 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
   double2 gl[3], b[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    gl[i] = act ? gv[i * M + lane] : make_double2(0.0, 0.0);
+    gl[i] = act ? gv[i * M + ll] : make_double2(0.0, 0.0);
     b[i] = make_double2(-om * gl[i].y, om * gl[i].x);
   }
 
-  // ---- LU with partial pivoting (max |re|+|im|, lowest lane on ties) ------
+  // ---- LU with partial pivoting (max |re|+|im|, lowest row on ties) -------
   bool done = !act;
   int order = -1;
   int bad = 0;
@@ -81,18 +129,17 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
   for (int k = 0; k < MAXM; ++k) {
     if (k < M) {
       const double val = done ? -1.0 : fabs(A[k].x) + fabs(A[k].y);
-      const double vmax = wave_max(val);
-      uint64_t m = __ballot((!done) && val == vmax);
-      if (m == 0) {  // NaN pivot column: flag it and take any remaining row
+      const double vmax = seg_max<L>(val);
+      int p = seg_first<L>((!done) && val == vmax, base);
+      if (p < 0) {  // NaN pivot column: flag it and take any remaining row
         bad = 1;
-        m = __ballot(!done);
+        p = seg_first<L>(!done, base);
       }
-      const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1);
-      const double2 piv = bcast2(A[k], p);
+      const double2 piv = seg_bcast2<L>(A[k], p);
       const double d = piv.x * piv.x + piv.y * piv.y;
       if (!(d > 0.0) || !isfinite(d)) bad = 1;
       const double2 inv = crecip(piv);
-      if (lane == p) {
+      if (wl == p) {
         done = true;
         order = k;
       }
@@ -102,39 +149,39 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
 #pragma unroll
       for (int j = k + 1; j < MAXM; ++j) {
         if (j < M) {
-          const double2 pr = bcast2(A[j], p);
+          const double2 pr = seg_bcast2<L>(A[j], p);
           if (upd) A[j] = cfms(A[j], l, pr);
         }
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 pb = bcast2(b[i], p);
+        const double2 pb = seg_bcast2<L>(b[i], p);
         if (upd) b[i] = cfms(b[i], l, pb);
       }
     }
   }
 
-  // ---- back substitution; lane j receives a_i[j] --------------------------
+  // ---- back substitution; lane j of the segment receives a_i[j] -----------
   double2 x[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) x[i] = make_double2(0.0, 0.0);
 #pragma unroll
   for (int k = MAXM - 1; k >= 0; --k) {
     if (k < M) {
-      const uint64_t m = __ballot(order == k);
-      const int q = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1);
-      const double2 inv = crecip(bcast2(A[k], q));
+      int q = seg_first<L>(order == k, base);
+      if (q < 0) q = base;  // only after a flagged breakdown
+      const double2 inv = crecip(seg_bcast2<L>(A[k], q));
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 xk = cmul(bcast2(b[i], q), inv);
-        if (lane == k) x[i] = xk;
+        const double2 xk = cmul(seg_bcast2<L>(b[i], q), inv);
+        if (ll == k) x[i] = xk;
         if (order >= 0 && order < k) b[i] = cfms(b[i], A[k], xk);
       }
     }
   }
 
   if (ADJ) {
-    // keep the factors: LDS row k = pivot row k (L multipliers left of the
+    // keep the factors: row k = pivot row k (L multipliers left of the
     // diagonal, U on and right of it)
     if (order >= 0) {
 #pragma unroll
@@ -149,16 +196,16 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
   for (int i = 0; i < 3; ++i) {
     Ka[i] = Ca[i] = Aa[i] = Ha[i] = make_double2(0.0, 0.0);
   }
-  const double2* Hrow = G + (size_t)(3 + M + lane) * ldG + (3 + M);
+  const double2* Hrow = G + (size_t)(3 + M + ll) * ldG + (3 + M);
 #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     double2 aj[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) aj[i] = bcast2(x[i], j);
+    for (int i = 0; i < 3; ++i) aj[i] = seg_bcast2<L>(x[i], base + j);
     if (act) {
-      const double2 kk = KM[lane * M + j];
-      const double2 cc = CM[lane * M + j];
-      const double2 a0 = A0[lane * M + j];
+      const double2 kk = KM[ll * M + j];
+      const double2 cc = CM[ll * M + j];
+      const double2 a0 = A0[ll * M + j];
       const double2 hh = Hrow[j];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -186,7 +233,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double2 Fi = G[(size_t)i * ldG + 3 + M + lane];
+      const double2 Fi = G[(size_t)i * ldG + 3 + M + ll];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         const double2 ga = cmulc(gl[i], x[j]);
@@ -198,48 +245,70 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
       }
     }
   }
-  const double red = reduce_scatter64(v);
-
-  // ---- final formulas: lane p < 18 produces out[p] ------------------------
-  red_lds[lane] = red;
+  // reduce-scatter inside the segment: lane ll ends with slots
+  // [ll * 64/L, (ll+1) * 64/L) summed over the segment (fixed order)
+#pragma unroll
+  for (int s = 0; (L >> s) > 1; ++s) {
+    const int hs = 32 >> s;       // half of the current slot count
+    const int lb = (L / 2) >> s;  // partner distance
+    const bool upper = (ll & lb) != 0;
+#pragma unroll
+    for (int t = 0; t < hs; ++t) {
+      const double lo = v[t], hi = v[t + hs];
+      const double send = upper ? lo : hi;
+      const double keep = upper ? hi : lo;
+      v[t] = keep + shfl_xor_d(send, lb);
+    }
+  }
+  constexpr int per = 64 / L;
+#pragma unroll
+  for (int t = 0; t < per; ++t) red_lds[ll * per + t] = v[t];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // ---- final formulas: outputs p = ll, ll + L, ... < 18 ------------------
   const double a3 = R.alpha * R.alpha * R.alpha;
-  double myout = 0.0;
-  if (lane < 18) {
-    const int p = lane % 6;
-    const int i = kPi[p], j = kPj[p];
-    if (lane < 6) {
-      myout = R.N0[3 * i + j] - 0.25 * a3 * red_lds[kKQ + p];
-    } else if (lane < 12) {
-      myout = 0.25 * a3 * om *
-              (R.E[3 * i + j] + red_lds[kCQ + p] + red_lds[kGA + 2 * (3 * i + j)] +
-               red_lds[kGA + 2 * (3 * j + i)]);
-    } else {
-      // Re c_ab = w^2 [W_ab + Re(F a_b)_a + Re(F a_a)_b + Re a_a^H H a_b]
-      //           - w [Im g_a^H a_b + Im g_b^H a_a] + Re a_a^H A0 a_b
-      double cr[3];
+  double iout = 0.0;  // I_p held by the lane computing output p in [6, 12)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int a = t == 0 ? i : (t == 1 ? j : i);
-        const int b = t == 0 ? i : (t == 1 ? j : j);
-        const int q = pair_index(a, b);
-        const double W = G[(size_t)a * ldG + b].x;
-        cr[t] = om * om * (W + red_lds[kFA + 2 * (3 * a + b)] + red_lds[kFA + 2 * (3 * b + a)] +
-                           red_lds[kHQ + q]) -
-                om * (red_lds[kGA + 2 * (3 * a + b) + 1] + red_lds[kGA + 2 * (3 * b + a) + 1]) +
-                red_lds[kAQ + q];
+  for (int p0 = 0; p0 < 18; p0 += L) {
+    const int po = p0 + ll;
+    if (po < 18) {
+      const int pp = po % 6;
+      const int i = kPi[pp], j = kPj[pp];
+      double myout;
+      if (po < 6) {
+        myout = R.N0[3 * i + j] - 0.25 * a3 * red_lds[kKQ + pp];
+      } else if (po < 12) {
+        myout = 0.25 * a3 * om *
+                (R.E[3 * i + j] + red_lds[kCQ + pp] + red_lds[kGA + 2 * (3 * i + j)] +
+                 red_lds[kGA + 2 * (3 * j + i)]);
+        iout = myout;
+      } else {
+        // Re c_ab = w^2 [W_ab + Re(F a_b)_a + Re(F a_a)_b + Re a_a^H H a_b]
+        //           - w [Im g_a^H a_b + Im g_b^H a_a] + Re a_a^H A0 a_b
+        double cr[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int a = t == 0 ? i : (t == 1 ? j : i);
+          const int bb = t == 0 ? i : (t == 1 ? j : j);
+          const int q = pair_index(a, bb);
+          const double W = G[(size_t)a * ldG + bb].x;
+          cr[t] = om * om * (W + red_lds[kFA + 2 * (3 * a + bb)] + red_lds[kFA + 2 * (3 * bb + a)] +
+                             red_lds[kHQ + q]) -
+                  om * (red_lds[kGA + 2 * (3 * a + bb) + 1] + red_lds[kGA + 2 * (3 * bb + a) + 1]) +
+                  red_lds[kAQ + q];
+        }
+        myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
       }
-      myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
+      if (valid) out[po] = myout;
     }
-    out[lane] = myout;
   }
-  if (a_out != nullptr && act) {
+  if (valid && a_out != nullptr && act) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) reinterpret_cast<double2*>(a_out)[i * M + lane] = x[i];
+    for (int i = 0; i < 3; ++i) reinterpret_cast<double2*>(a_out)[i * M + ll] = x[i];
   }
-  if (lane == 0) *status = bad ? 4 : 0;
+  if (valid && ll == 0) *status = bad ? 4 : 0;
   __builtin_amdgcn_wave_barrier();
 
   if (ADJ) {
@@ -274,25 +343,25 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
     for (int j = 0; j < M; ++j) {
       const double2 ujj = lds_lu[j * (MAXM + 1) + j];
       const double2 inv = crecip(cconj(ujj));
-      const double2 urow = (lane > j && act) ? lds_lu[j * (MAXM + 1) + lane] : make_double2(0.0, 0.0);
+      const double2 urow = (ll > j && act) ? lds_lu[j * (MAXM + 1) + ll] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 zj = cmul(bcast2(vk[i], j), inv);
-        if (lane == j) vk[i] = zj;
-        if (lane > j && act) vk[i] = cfms(vk[i], cconj(urow), zj);
+        const double2 zj = cmul(seg_bcast2<L>(vk[i], base + j), inv);
+        if (ll == j) vk[i] = zj;
+        if (ll > j && act) vk[i] = cfms(vk[i], cconj(urow), zj);
       }
     }
     // L^H y = z  (unit diagonal)
     for (int k = M - 1; k >= 0; --k) {
-      const double2 lrow = (lane < k) ? lds_lu[k * (MAXM + 1) + lane] : make_double2(0.0, 0.0);
+      const double2 lrow = (ll < k) ? lds_lu[k * (MAXM + 1) + ll] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 yk = bcast2(vk[i], k);
-        if (lane < k) vk[i] = cfms(vk[i], cconj(lrow), yk);
+        const double2 yk = seg_bcast2<L>(vk[i], base + k);
+        if (ll < k) vk[i] = cfms(vk[i], cconj(lrow), yk);
       }
     }
     // lambda = P^T y: lane r (original row r) takes y[order(r)]
-    const int src = order >= 0 ? order : lane;
+    const int src = base + (order >= 0 ? order : ll);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -303,9 +372,10 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om,
       }
     }
     // explicit omega-dependence of I (prefactor w): sum_p tau_p I_p / w
-    if (lane >= 6 && lane < 12) acc += dout[lane] * myout / om;
-    const double tot = wave_sum(acc);
-    if (lane == 0) *dom = tot;
+    if (ll >= 6 && ll < 12) acc += dout[ll] * iout / om;
+    const double tot = seg_sum<L>(acc);
+    if (valid && ll == 0) *dom = tot;
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -317,16 +387,23 @@ __global__ __launch_bounds__(256) void k_sweep(const mpt_rom R, const double* __
                                                int32_t* __restrict__ status,
                                                const double* __restrict__ dout,
                                                double* __restrict__ dom) {
+  constexpr int L = SegOf<MAXM>::L, S = SegOf<MAXM>::S;
   extern __shared__ double2 lds[];
-  __shared__ double red[4 * 64];
+  __shared__ double red[4 * 64 * S];
   const int wave = threadIdx.x >> 6;
   const int wpg = blockDim.x >> 6;
-  double2* my_lds = ADJ ? lds + (size_t)wave * MAXM * (MAXM + 1) : nullptr;
-  for (int64_t k = (int64_t)blockIdx.x * wpg + wave; k < n; k += (int64_t)gridDim.x * wpg) {
-    sweep_point<MAXM, ADJ>(R, omega[k], out + 18 * k,
-                           a_out ? a_out + (size_t)k * 6 * R.M : nullptr, status + k,
-                           ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
-                           red + 64 * wave);
+  const int seg = __lane_id() / L;
+  double2* my_lds = ADJ ? lds + ((size_t)wave * S + seg) * MAXM * (MAXM + 1) : nullptr;
+  double* my_red = red + (wave * S + seg) * 64;
+  for (int64_t k0 = ((int64_t)blockIdx.x * wpg + wave) * S; k0 < n;
+       k0 += (int64_t)gridDim.x * wpg * S) {
+    const int64_t k = k0 + seg;
+    const bool valid = k < n;
+    const int64_t kc = valid ? k : n - 1;
+    sweep_point<MAXM, ADJ>(R, omega[kc], valid, out + 18 * kc,
+                           a_out ? a_out + (size_t)kc * 6 * R.M : nullptr, status + kc,
+                           ADJ ? dout + 18 * kc : nullptr, ADJ ? dom + kc : nullptr, my_lds,
+                           my_red);
   }
 }
 
@@ -338,10 +415,13 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(
     unsigned int* __restrict__ counter, const double* __restrict__ omega,
     double* __restrict__ out, int32_t* __restrict__ status, const double* __restrict__ dout,
     double* __restrict__ dom) {
+  constexpr int L = SegOf<MAXM>::L, S = SegOf<MAXM>::S;
   extern __shared__ double2 lds[];
-  __shared__ double red[4 * 64];
+  __shared__ double red[4 * 64 * S];
   const int wave = threadIdx.x >> 6;
-  double2* my_lds = ADJ ? lds + (size_t)wave * MAXM * (MAXM + 1) : nullptr;
+  const int seg = __lane_id() / L;
+  double2* my_lds = ADJ ? lds + ((size_t)wave * S + seg) * MAXM * (MAXM + 1) : nullptr;
+  double* my_red = red + (wave * S + seg) * 64;
   while (true) {
     int it = 0;
     if (__lane_id() == 0) it = (int)atomicAdd(counter, 1u);
@@ -349,23 +429,25 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(
     if (it >= n_items) break;
     const int4 w = items[it];  // x: object, y: first row, z: count
     const mpt_rom R = roms[w.x];
-    for (int r = 0; r < w.z; ++r) {
-      const int64_t k = (int64_t)w.y + r;
-      sweep_point<MAXM, ADJ>(R, omega[k], out + 18 * k, nullptr, status + k,
+    for (int r = 0; r < w.z; r += S) {
+      const bool valid = r + seg < w.z;
+      const int64_t k = (int64_t)w.y + (valid ? r + seg : w.z - 1);
+      sweep_point<MAXM, ADJ>(R, omega[k], valid, out + 18 * k, nullptr, status + k,
                              ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
-                             red + 64 * wave);
+                             my_red);
     }
   }
 }
 
 template <int MAXM, bool ADJ>
 hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double* out,
-                               double* a_out, int32_t* status, const double* dout, double* dom,
-                               int wpg, hipStream_t st) {
-  const int64_t waves = n;
+                        double* a_out, int32_t* status, const double* dout, double* dom, int wpg,
+                        hipStream_t st) {
+  constexpr int S = SegOf<MAXM>::S;
+  const int64_t waves = (n + S - 1) / S;
   int64_t groups = (waves + wpg - 1) / wpg;
   if (groups > 65535 * 8) groups = 65535 * 8;
-  const size_t lds = ADJ ? (size_t)wpg * MAXM * (MAXM + 1) * sizeof(double2) : 0;
+  const size_t lds = ADJ ? (size_t)wpg * S * MAXM * (MAXM + 1) * sizeof(double2) : 0;
   hipLaunchKernelGGL((k_sweep<MAXM, ADJ>), dim3((unsigned)groups), dim3(64 * wpg), lds, st, R,
                      omega, n, out, a_out, status, dout, dom);
   return hipGetLastError();
@@ -373,10 +455,11 @@ hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double
 
 template <int MAXM, bool ADJ>
 hipError_t launch_persistent(const mpt_rom* roms, const int4* items, int n_items,
-                                    unsigned int* counter, const double* omega, double* out,
-                                    int32_t* status, const double* dout, double* dom, int wpg,
-                                    int groups, hipStream_t st) {
-  const size_t lds = ADJ ? (size_t)wpg * MAXM * (MAXM + 1) * sizeof(double2) : 0;
+                             unsigned int* counter, const double* omega, double* out,
+                             int32_t* status, const double* dout, double* dom, int wpg,
+                             int groups, hipStream_t st) {
+  constexpr int S = SegOf<MAXM>::S;
+  const size_t lds = ADJ ? (size_t)wpg * S * MAXM * (MAXM + 1) * sizeof(double2) : 0;
   hipLaunchKernelGGL((k_sweep_persistent<MAXM, ADJ>), dim3(groups), dim3(64 * wpg), lds, st, roms,
                      items, n_items, counter, omega, out, status, dout, dom);
   return hipGetLastError();

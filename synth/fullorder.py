@@ -86,15 +86,49 @@ class SpectralX1:
         return np.concatenate([rx.reshape(nx, B), ry.reshape(nx, B), rz.reshape(nx, B)], 0)
 
 
+class RegionGreen:
+    """X_1^{-1} restricted to the interior edges inside a centred box.
+
+    Computed once per grid (one spectral solve per edge of the box); every
+    object inside the box then gets its conductor block and its permeability
+    correction from dense sub-blocks instead of its own spectral solves."""
+
+    def __init__(self, grid: YeeGrid, eps_h: float, half_width: float, chunk: int = 48,
+                 verbose: bool = False):
+        self.grid = grid
+        mid = grid.edge_midpoints()
+        self.idx = np.flatnonzero(np.all(np.abs(mid) <= half_width, axis=1)).astype(np.int64)
+        sx = SpectralX1(grid, eps_h)
+        n = self.idx.size
+        self.G = np.empty((n, n))
+        t0 = __import__("time").time()
+        for c0 in range(0, n, chunk):
+            cols = self.idx[c0:c0 + chunk]
+            E = np.zeros((grid.N, cols.size))
+            E[cols, np.arange(cols.size)] = 1.0
+            self.G[:, c0:c0 + cols.size] = sx.apply(E, chunk)[self.idx]
+            if verbose and (c0 // chunk) % 40 == 0:
+                print(f"  region Green's function {c0}/{n} ({__import__('time').time() - t0:.0f} s)",
+                      flush=True)
+        self.G = 0.5 * (self.G + self.G.T)
+
+    def positions(self, edges):
+        pos = np.searchsorted(self.idx, edges)
+        if np.any(pos >= self.idx.size) or np.any(self.idx[np.minimum(pos, self.idx.size - 1)] != edges):
+            raise ValueError("object edges outside the region of the Green's function")
+        return pos
+
+
 class FullOrderSolver:
     """Snapshots q_i(omega), theta~^(0) DOFs o_i and the conductor block S."""
 
-    def __init__(self, ops: Operators, C=None, chunk: int = 24):
+    def __init__(self, ops: Operators, C=None, chunk: int = 24, green: RegionGreen | None = None):
         self.ops = ops
         g = ops.grid
         self.chunk = chunk
         self.sx = SpectralX1(g, ops.eps_h)
         self.cond = ops.cond_idx.astype(np.int64)
+        self.green = green
         F = np.flatnonzero(ops.mu_f != 1.0)
         self.F = F
         self._S = None
@@ -105,13 +139,25 @@ class FullOrderSolver:
             self.CFT = self.CF.T.tocsc()
             delta = 1.0 / ops.mu_f[F] - 1.0
             nF = F.size
-            Gam = np.empty((nF, nF))
-            Wc = np.empty((self.cond.size, nF))
-            for c0 in range(0, nF, chunk):
-                cols = self.CFT[:, c0:c0 + chunk].toarray()
-                W = self.sx.apply(cols, chunk)
-                Gam[:, c0:c0 + chunk] = self.CF @ W
-                Wc[:, c0:c0 + chunk] = W[self.cond]
+            if green is not None:
+                CFc = self.CF.tocoo()
+                pos = green.positions(np.unique(CFc.col))
+                lut = np.full(g.N, -1, dtype=np.int64)
+                lut[np.unique(CFc.col)] = pos
+                import scipy.sparse as sp
+                CFR = sp.csr_matrix((CFc.data, (CFc.row, lut[CFc.col])), shape=(nF, green.idx.size))
+                GC = CFR @ green.G  # (nF, nR)
+                Gam = np.asarray((CFR @ GC.T))
+                cpos = green.positions(self.cond)
+                Wc = np.asarray(GC[:, cpos].T)
+            else:
+                Gam = np.empty((nF, nF))
+                Wc = np.empty((self.cond.size, nF))
+                for c0 in range(0, nF, chunk):
+                    cols = self.CFT[:, c0:c0 + chunk].toarray()
+                    W = self.sx.apply(cols, chunk)
+                    Gam[:, c0:c0 + chunk] = self.CF @ W
+                    Wc[:, c0:c0 + chunk] = W[self.cond]
             Gam = 0.5 * (Gam + Gam.T)
             self.cap = sla.lu_factor(np.diag(g.h / delta) + Gam)
             self.Wc = Wc
@@ -137,6 +183,12 @@ class FullOrderSolver:
     # ---- conductor Schur block ---------------------------------------
     def schur(self) -> np.ndarray:
         """S = P^T X^{-1} P over the conductor edges (n_c x n_c, symmetric)."""
+        if self._S is None and self.green is not None:
+            cpos = self.green.positions(self.cond)
+            S = self.green.G[np.ix_(cpos, cpos)].copy()
+            if self.F.size:
+                S -= self.Wc @ sla.lu_solve(self.cap, self.Wc.T)
+            self._S = 0.5 * (S + S.T)
         if self._S is None:
             N = self.ops.N
             nc = self.cond.size

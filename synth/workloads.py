@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .fullorder import FullOrderSolver
+from .fullorder import FullOrderSolver, RegionGreen
 from .shapes import Shape, cuboid, ellipsoid, random_rotation, shell_sphere, sphere, torus
 from .yee import Operators, YeeGrid, build_operators
 
@@ -155,9 +155,21 @@ class Problem:
         self.snap_residual = max(self.snap_residual, hist[-1])
 
 
+# half-width of the box that contains every object of a dictionary workload
+REGION_HALF_WIDTH = {"dictionary32": 1.5, "adjoint48": 1.5}
+
+
+def region_green(name: str, grid: YeeGrid, verbose: bool = False) -> RegionGreen:
+    """Shared X_1^{-1} block for the objects of a dictionary workload (mu_r
+    corrections are applied per object)."""
+    wl = WORKLOADS[name]
+    return RegionGreen(grid, wl.eps * grid.h, REGION_HALF_WIDTH[name] + 1.01 * grid.h,
+                       verbose=verbose)
+
+
 def make_problem(name: str, obj: int = 0, n: int | None = None, n_snap: int | None = None,
                  n_omega: int | None = None, tol: float = 1e-12, grid: YeeGrid | None = None,
-                 curl=None, verbose: bool = False) -> Problem:
+                 curl=None, verbose: bool = False, green: RegionGreen | None = None) -> Problem:
     """Build one object's full-order data.  n / n_snap / n_omega override sizes (tests)."""
     wl = WORKLOADS[name]
     draw = draw_object(wl, obj)
@@ -166,7 +178,7 @@ def make_problem(name: str, obj: int = 0, n: int | None = None, n_snap: int | No
     C = curl if curl is not None else g.curl()
     sig, mu, ncell = draw.shape.assign(g)
     ops = build_operators(g, sig, mu, wl.alpha, wl.eps, C=C, cell_count=ncell)
-    fo = FullOrderSolver(ops, C=C)
+    fo = FullOrderSolver(ops, C=C, green=green)
     o, _ = fo.theta0()
     K = wl.n_snap if n_snap is None else n_snap
     snap = log_grid(*wl.snap_range, K)
