@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--form", choices=["plain", "batched", "adjoint"], default="plain")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -81,6 +83,8 @@ def main():
 
     mpt.lib()
     dev = torch.device("cuda:0")
+    if args.calibrate:
+        copy_calibration(dev)
     if args.form != "plain":
         return bench_dictionary(args)
     t0 = time.time()
@@ -192,6 +196,24 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(dev):
+    """Three plain device-to-device copies of 1 GiB (read 1 GiB, write 1 GiB):
+    the per-dispatch FETCH_SIZE / WRITE_SIZE they report calibrate the HBM
+    counters of the other kernels."""
+    import torch
+
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x {COPY_BYTES} bytes")
+    del a, b
 
 
 def build_dictionary(name, n_obj, dev, keep=2, tol_snap=1e-6):

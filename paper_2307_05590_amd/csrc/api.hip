@@ -289,6 +289,10 @@ extern "C" int mpt_max_reduced_dim(void) { return 64; }
 // ------------------------------------------------------------------ a1 POD
 constexpr int kJacobiSweeps = 40;
 constexpr double kJacobiTolPass1 = 1e-9;  // pass 1 only preconditions pass 2
+// absolute rotation floor (times max |g_ii|): only entries at the underflow
+// end are left alone, so pass 1 also orders the sub-rounding part of D^H D,
+// which keeps the pass-2 Gram close to diagonal (fewer pass-2 sweeps)
+constexpr double kJacobiFloor = 1e-30;
 
 static void pod_layout(int64_t N, int m, size_t* off) {
   // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 jacobi record, 9 end
@@ -340,11 +344,12 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   hipStream_t st = h->stream;
   // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info, jws, kJacobiSweeps, kJacobiTolPass1, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info, jws, kJacobiSweeps, kJacobiTolPass1, kJacobiFloor,
+                       st));
   HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
   // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
   HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps, tol2, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps, tol2, kJacobiFloor, st));
   hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
                      reinterpret_cast<const double2*>(V0), m, tol_sigma, Mc, sigma,
                      reinterpret_cast<double2*>(W), Mdev);

@@ -26,7 +26,7 @@ __host__ __device__ inline int64_t gram_rows(int64_t N, int m, int n) {
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
   const int64_t groups_per_chunk = (TI * JG + 3) / 4;
   int64_t rows = N * groups_per_chunk / 1024;
-  rows = rows < 256 ? 256 : (rows > 8192 ? 8192 : rows);
+  rows = rows < 16 ? 16 : (rows > 8192 ? 8192 : rows);
   return (rows + 3) / 4 * 4;
 }
 

@@ -45,12 +45,14 @@ hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n,
                              void* ws, hipStream_t st);
 
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
-//   by cyclic two-sided Jacobi in one workgroup; A overwritten, V (n x n)
+//   by cyclic two-sided Jacobi in one workgroup; V (n x n)
 //   eigenvectors in columns, lam eigenvalues (unsorted); info[0] sweeps used
 //   (or -1 when not converged), info[2] sweeps recorded; ws holds the
-//   rotation record (jacobi_ws_size bytes); tol is the relative threshold.
+//   rotation record and a packed copy of A (jacobi_ws_size bytes); A is read
+//   only; tol is the relative rotation threshold and floor_rel the absolute
+//   one (times max |a_ii|).
 size_t jacobi_ws_size(int n, int max_sweeps);
 hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, void* ws,
-                         int max_sweeps, double tol, hipStream_t st);
+                         int max_sweeps, double tol, double floor_rel, hipStream_t st);
 
 }  // namespace mpt
