@@ -288,10 +288,7 @@ extern "C" int mpt_max_reduced_dim(void) { return 64; }
 
 // ------------------------------------------------------------------ a1 POD
 constexpr int kJacobiSweeps = 40;
-constexpr double kJacobiTolPass1 = 1e-9;  // pass 1 only preconditions pass 2
-// absolute rotation floor (times max |g_ii|): only entries at the underflow
-// end are left alone, so pass 1 also orders the sub-rounding part of D^H D,
-// which keeps the pass-2 Gram close to diagonal (fewer pass-2 sweeps)
+// absolute rotation floor of the pass-2 Jacobi (times max |g_ii|)
 constexpr double kJacobiFloor = 1e-30;
 
 static void pod_layout(int64_t N, int m, size_t* off) {
@@ -305,7 +302,7 @@ static void pod_layout(int64_t N, int m, size_t* off) {
   off[5] = o; o = align256(o + (size_t)m * 192 * 16);
   off[6] = o; o = align256(o + 64);
   off[7] = o; o = align256(o + 64);
-  off[8] = o; o = align256(o + jacobi_ws_size(m, kJacobiSweeps));
+  off[8] = o; o = align256(o + std::max(jacobi_ws_size(m, kJacobiSweeps), tridiag_ws_size(m)));
   off[9] = o;
 }
 
@@ -344,8 +341,8 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   hipStream_t st = h->stream;
   // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info, jws, kJacobiSweeps, kJacobiTolPass1, kJacobiFloor,
-                       st));
+  HIP_OK(hipMemsetAsync(info, 0, 4 * sizeof(int), st));
+  HIP_OK(tridiag_eig_launch(G0, m, V0, lam, jws, st));
   HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
   // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
   HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));

@@ -52,6 +52,13 @@ hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n,
 //   only; tol is the relative rotation threshold and floor_rel the absolute
 //   one (times max |a_ii|).
 size_t jacobi_ws_size(int n, int max_sweeps);
+// tridiag.hip : Hermitian eigen-decomposition (n <= 192) by Householder
+//   tridiagonalisation, multisection, inverse iteration, Gram-Schmidt and
+//   back-transformation; absolute accuracy ~ eps ||A||.  A (n x n) is read
+//   only; V (n x n, V[i n + j] = component i of eigenvector j), lam unsorted.
+size_t tridiag_ws_size(int n);
+hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, void* ws,
+                              hipStream_t st);
 hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, void* ws,
                          int max_sweeps, double tol, double floor_rel, hipStream_t st);
 

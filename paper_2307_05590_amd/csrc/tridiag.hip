@@ -1,0 +1,468 @@
+// Hermitian eigen-decomposition of a small matrix (n <= 192) to absolute
+// accuracy ~ eps ||A||, for the first pass of the POD basis, where the
+// eigenvectors only have to rotate the snapshot Gram close to diagonal:
+//   1. Householder reduction to tridiagonal form, H_k = I - g_k u_k u_k^H
+//      (one workgroup, packed lower triangle in LDS);
+//   2. a diagonal unitary that makes the off-diagonal real;
+//   3. all eigenvalues of the real tridiagonal by multisection on Sturm
+//      counts (every eigenvalue's interval tested at P points per step);
+//   4. eigenvectors by inverse iteration with partial pivoting, one wave each;
+//   5. two passes of modified Gram-Schmidt in decreasing eigenvalue order;
+//   6. back-transformation V = H_0 ... H_{n-3} Phi Z, one wave per column.
+// The work is O(n^3) once, against about a dozen O(n^3) sweeps for Jacobi.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace mpt {
+
+constexpr int kTriMaxN = 192;
+constexpr int kTriThreads = 1024;
+constexpr size_t kTriLdsBudget = 150 * 1024;
+constexpr int kTriWaves = 4;  // waves per workgroup of the per-vector kernels
+
+__device__ __forceinline__ int lpos(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+__device__ __forceinline__ double2 lget(const double2* A, int i, int j) {
+  return i >= j ? A[lpos(i, j)] : cconj(A[lpos(j, i)]);
+}
+
+// 1. + 2.: d (n), e (n-1, >= 0), phases ph (n), reflectors Hv (row k holds
+// u_k in columns k+1..n-1) and their scalars g (n-2)
+template <bool SHARED>
+__global__ __launch_bounds__(kTriThreads) void k_hetrd(const double2* __restrict__ Ag, int n,
+                                                       double2* __restrict__ Ap,
+                                                       double2* __restrict__ Hv,
+                                                       double* __restrict__ gam,
+                                                       double* __restrict__ dout,
+                                                       double* __restrict__ eout,
+                                                       double2* __restrict__ ph) {
+  extern __shared__ double2 smem[];
+  __shared__ double2 u[kTriMaxN], p[kTriMaxN], beta[kTriMaxN];
+  __shared__ double g_sh;
+  double2* A = SHARED ? smem : Ap;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = __lane_id(), wave = tid >> 6;
+  for (int i = tid; i < n * n; i += nt) {
+    const int r = i / n, c = i % n;
+    if (r >= c) A[lpos(r, c)] = Ag[i];
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int L = n - k - 1;  // trailing block rows/cols o .. n-1
+    const int o = k + 1;
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = lane; i < L; i += 64) {
+        const double2 x = A[lpos(o + i, k)];
+        s += x.x * x.x + x.y * x.y;
+      }
+      s = wave_sum(s);
+      const double alpha = sqrt(s);
+      const double2 x0 = A[lpos(o, k)];
+      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+      const bool refl = alpha > 1e-300;
+      double2 th = make_double2(1.0, 0.0);
+      if (ax0 > 0.0) th = make_double2(x0.x / ax0, x0.y / ax0);
+      const double g = refl ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+      for (int i = lane; i < L; i += 64) {
+        double2 x = A[lpos(o + i, k)];
+        if (i == 0) x = make_double2(x.x + th.x * alpha, x.y + th.y * alpha);
+        if (!refl) x = make_double2(0.0, 0.0);
+        u[i] = x;
+        Hv[(size_t)k * n + o + i] = x;
+      }
+      if (lane == 0) {
+        g_sh = g;
+        gam[k] = g;
+        beta[k] = refl ? make_double2(-th.x * alpha, -th.y * alpha) : x0;
+        dout[k] = A[lpos(k, k)].x;
+      }
+    }
+    __syncthreads();
+    const double g = g_sh;
+    if (g == 0.0) continue;  // uniform: column already reduced
+    // p = g A22 u, eight threads per row
+    const int s8 = tid & 7;
+    for (int i = tid >> 3; i < L; i += nt >> 3) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = s8; j < L; j += 8) acc = cfma(acc, lget(A, o + i, o + j), u[j]);
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1) {
+        acc.x += shfl_xor_d(acc.x, m);
+        acc.y += shfl_xor_d(acc.y, m);
+      }
+      if (s8 == 0) p[i] = make_double2(g * acc.x, g * acc.y);
+    }
+    __syncthreads();
+    // K = g/2 Re(u^H p) (every wave computes it), w = p - K u,
+    // A22 <- A22 - u w^H - w u^H on the lower triangle
+    double kk = 0.0;
+    for (int i = lane; i < L; i += 64) kk += cmulc(u[i], p[i]).x;
+    kk = 0.5 * g * wave_sum(kk);
+    const int nl = L * (L + 1) / 2;
+    for (int e = tid; e < nl; e += nt) {
+      int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      while (i * (i + 1) / 2 > e) --i;
+      const int j = e - i * (i + 1) / 2;
+      const double2 ui = u[i], uj = u[j], pi = p[i], pj = p[j];
+      const double2 wi = make_double2(pi.x - kk * ui.x, pi.y - kk * ui.y);
+      const double2 wj = make_double2(pj.x - kk * uj.x, pj.y - kk * uj.y);
+      double2 a = A[lpos(o + i, o + j)];
+      a = cfms(a, ui, cconj(wj));
+      a = cfms(a, wi, cconj(uj));
+      A[lpos(o + i, o + j)] = a;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      dout[n - 2] = A[lpos(n - 2, n - 2)].x;
+      beta[n - 2] = A[lpos(n - 1, n - 2)];
+    }
+    dout[n - 1] = A[lpos(n - 1, n - 1)].x;
+    double2 f = make_double2(1.0, 0.0);
+    ph[0] = f;
+    for (int k = 0; k + 1 < n; ++k) {
+      const double2 b = beta[k];
+      const double ab = sqrt(b.x * b.x + b.y * b.y);
+      eout[k] = ab;
+      if (ab > 0.0) f = cmul(f, make_double2(b.x / ab, b.y / ab));
+      ph[k + 1] = f;
+    }
+  }
+}
+
+// 3. eigenvalues (ascending) of the real symmetric tridiagonal (d, e)
+__global__ __launch_bounds__(kTriThreads) void k_tri_eigvals(const double* __restrict__ d,
+                                                             const double* __restrict__ e, int n,
+                                                             double* __restrict__ lam) {
+  __shared__ double sd[kTriMaxN], se2[kTriMaxN], lo[kTriMaxN], hi[kTriMaxN];
+  __shared__ int cnt[kTriThreads];
+  __shared__ double gb[3];
+  const int tid = threadIdx.x, lane = __lane_id();
+  for (int i = tid; i < n; i += blockDim.x) {
+    sd[i] = d[i];
+    se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double gl = 1e308, gu = -1e308, em = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+      gl = fmin(gl, sd[i] - r);
+      gu = fmax(gu, sd[i] + r);
+      em = fmax(em, se2[i]);
+    }
+    gl = -wave_max(-gl);
+    gu = wave_max(gu);
+    em = wave_max(em);
+    if (tid == 0) {
+      const double tn = fmax(fabs(gl), fabs(gu));
+      gb[0] = gl - 4.0 * 2.220446049250313e-16 * tn * n;
+      gb[1] = gu + 4.0 * 2.220446049250313e-16 * tn * n;
+      gb[2] = 1e-290 * fmax(1.0, em);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += blockDim.x) {
+    lo[j] = gb[0];
+    hi[j] = gb[1];
+  }
+  const double pivmin = gb[2];
+  const int P = min((int)(blockDim.x / n), 32);
+  // interval shrinks by P+1 per step; 1e17 covers the Gershgorin width to eps
+  const int iters = (int)ceil(39.2 / log((double)(P + 1)));
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    const int j = tid / P, q = tid % P;
+    if (j < n) {
+      const double x = lo[j] + (hi[j] - lo[j]) * (double)(q + 1) / (double)(P + 1);
+      double s = sd[0] - x;
+      int c = s < 0.0 ? 1 : 0;
+      for (int i = 1; i < n; ++i) {
+        if (fabs(s) < pivmin) s = -pivmin;
+        double r = __builtin_amdgcn_rcp(s);
+        r = fma(r, fma(-s, r, 1.0), r);
+        s = (sd[i] - x) - se2[i - 1] * r;
+        c += s < 0.0 ? 1 : 0;
+      }
+      cnt[tid] = c;
+    }
+    __syncthreads();
+    if (tid < n) {
+      const int jj = tid;
+      double nl = lo[jj], nh = hi[jj];
+      for (int qq = 0; qq < P; ++qq) {
+        const double x = lo[jj] + (hi[jj] - lo[jj]) * (double)(qq + 1) / (double)(P + 1);
+        if (cnt[jj * P + qq] <= jj) nl = fmax(nl, x);
+        else nh = fmin(nh, x);
+      }
+      lo[jj] = nl;
+      hi[jj] = nh;
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < n; j += blockDim.x) lam[j] = 0.5 * (lo[j] + hi[j]);
+}
+
+// 4. inverse iteration: three solves of (T - lam_j) x = b with Gaussian
+// elimination with partial pivoting (lane 0; factors in LDS), each followed
+// by normalisation.  Z row j = eigenvector j.
+__global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __restrict__ d,
+                                                              const double* __restrict__ e,
+                                                              const double* __restrict__ lam,
+                                                              int n, double* __restrict__ Z) {
+  __shared__ double f0[kTriWaves][kTriMaxN], f1[kTriWaves][kTriMaxN], f2[kTriWaves][kTriMaxN],
+      fm[kTriWaves][kTriMaxN], bx[kTriWaves][kTriMaxN], yv[kTriWaves][kTriMaxN];
+  __shared__ unsigned char fsw[kTriWaves][kTriMaxN];
+  const int wave = threadIdx.x >> 6, lane = __lane_id();
+  const int j = blockIdx.x * kTriWaves + wave;
+  if (j >= n) return;
+  double* U0 = f0[wave];
+  double* U1 = f1[wave];
+  double* U2 = f2[wave];
+  double* mm = fm[wave];
+  double* b = bx[wave];
+  double* y = yv[wave];
+  unsigned char* sw = fsw[wave];
+  // norm of T for the pivot floor
+  double tn = 0.0;
+  for (int i = lane; i < n; i += 64)
+    tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
+  tn = wave_max(tn);
+  const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
+  const double lj = lam[j];
+  for (int i = lane; i < n; i += 64) b[i] = 1.0 + 0.1 * sin(0.7 * i + 1.3 * j);
+  if (lane == 0) {
+    double xr = d[0] - lj, yr = n > 1 ? e[0] : 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double ei = e[i], an = d[i + 1] - lj, en = i + 2 < n ? e[i + 1] : 0.0;
+      double mi;
+      if (fabs(ei) > fabs(xr)) {
+        sw[i] = 1;
+        mi = xr / ei;
+        U0[i] = ei;
+        U1[i] = an;
+        U2[i] = en;
+        const double nx = yr - mi * an, ny = -mi * en;
+        xr = nx;
+        yr = ny;
+      } else {
+        sw[i] = 0;
+        const double pv = xr != 0.0 ? xr : tiny;
+        mi = ei / pv;
+        U0[i] = pv;
+        U1[i] = yr;
+        U2[i] = 0.0;
+        xr = an - mi * yr;
+        yr = en;
+      }
+      mm[i] = mi;
+    }
+    U0[n - 1] = xr;
+    for (int i = 0; i < n; ++i)
+      if (fabs(U0[i]) < tiny) U0[i] = U0[i] >= 0.0 ? tiny : -tiny;
+  }
+  for (int s = 0; s < 3; ++s) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+      double bc = b[0];
+      for (int i = 0; i + 1 < n; ++i) {
+        if (sw[i]) {
+          y[i] = b[i + 1];
+          bc = bc - mm[i] * b[i + 1];
+        } else {
+          y[i] = bc;
+          bc = b[i + 1] - mm[i] * bc;
+        }
+      }
+      y[n - 1] = bc;
+      double x1 = 0.0, x2 = 0.0;  // x[i+1], x[i+2]
+      for (int i = n - 1; i >= 0; --i) {
+        double v = y[i] - U1[i] * x1 - U2[i] * x2;
+        if (i + 1 >= n) v = y[i];
+        double xi = v / U0[i];
+        if (fabs(xi) > 1e150) {  // rescale what is computed so far
+          for (int t = i + 1; t < n; ++t) b[t] *= 1e-150;
+          x1 *= 1e-150;
+          x2 *= 1e-150;
+          xi *= 1e-150;
+        }
+        b[i] = xi;
+        x2 = x1;
+        x1 = xi;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double nr = 0.0;
+    for (int i = lane; i < n; i += 64) nr += b[i] * b[i];
+    nr = wave_sum(nr);
+    const double inv = 1.0 / sqrt(nr);
+    for (int i = lane; i < n; i += 64) b[i] *= inv;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = lane; i < n; i += 64) Z[(size_t)j * n + i] = b[i];
+}
+
+// 5. two passes of modified Gram-Schmidt over the rows of Z in decreasing
+// eigenvalue order (lam ascending, so row n-1 first)
+template <bool SHARED>
+__global__ __launch_bounds__(kTriThreads) void k_tri_mgs(double* __restrict__ Zg, int n) {
+  extern __shared__ double zs[];
+  double* Z = SHARED ? zs : Zg;
+  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  if (SHARED)
+    for (int i = tid; i < n * n; i += blockDim.x) Z[i] = Zg[i];
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int s = 0; s < n; ++s) {
+      const int j = n - 1 - s;
+      const double* zj = Z + (size_t)j * n;
+      double nr = 0.0;
+      for (int i = lane; i < n; i += 64) nr += zj[i] * zj[i];
+      const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
+      for (int jj = wave; jj < j; jj += nw) {
+        double* zk = Z + (size_t)jj * n;
+        double dt = 0.0;
+        for (int i = lane; i < n; i += 64) dt += zj[i] * zk[i];
+        dt = wave_sum(dt) * inv * inv;
+        for (int i = lane; i < n; i += 64) zk[i] -= dt * zj[i];
+      }
+      __syncthreads();
+      if (wave == j % nw)
+        for (int i = lane; i < n; i += 64) Z[(size_t)j * n + i] *= inv;
+      // the scaled row j is read again only after the next barrier
+    }
+    __syncthreads();
+  }
+  if (SHARED)
+    for (int i = tid; i < n * n; i += blockDim.x) Zg[i] = Z[i];
+}
+
+// 6. V[:, j] = H_0 ... H_{n-3} Phi z_j; V row-major n x n (V[i n + j])
+__global__ __launch_bounds__(64 * kTriWaves) void k_tri_back(const double* __restrict__ Z,
+                                                             const double2* __restrict__ ph,
+                                                             const double2* __restrict__ Hv,
+                                                             const double* __restrict__ gam, int n,
+                                                             double2* __restrict__ V) {
+  constexpr int kSlots = (kTriMaxN + 63) / 64;
+  __shared__ double gs[kTriMaxN];
+  const int wave = threadIdx.x >> 6, lane = __lane_id();
+  for (int i = threadIdx.x; i + 2 < n; i += blockDim.x) gs[i] = gam[i];
+  __syncthreads();
+  const int j = blockIdx.x * kTriWaves + wave;
+  if (j >= n) return;
+  double2 y[kSlots];
+#pragma unroll
+  for (int t = 0; t < kSlots; ++t) {
+    const int i = lane + 64 * t;
+    y[t] = make_double2(0.0, 0.0);
+    if (i < n) {
+      const double z = Z[(size_t)j * n + i];
+      const double2 f = ph[i];
+      y[t] = make_double2(f.x * z, f.y * z);
+    }
+  }
+  // reflector k + 1's entries are loaded while reflector k is applied
+  auto load_u = [&](int k, double2 (&uu)[kSlots]) {
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) {
+      const int i = lane + 64 * t;
+      uu[t] = (k >= 0 && i > k && i < n) ? Hv[(size_t)k * n + i] : make_double2(0.0, 0.0);
+    }
+  };
+  double2 un[kSlots];
+  load_u(n - 3, un);
+  for (int k = n - 3; k >= 0; --k) {
+    double2 uu[kSlots];
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) uu[t] = un[t];
+    load_u(k - 1, un);
+    const double g = gs[k];
+    if (g == 0.0) continue;
+    double2 dt = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) dt = cfmac(dt, uu[t], y[t]);
+    dt.x = wave_sum(dt.x) * g;
+    dt.y = wave_sum(dt.y) * g;
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) y[t] = cfms(y[t], uu[t], dt);
+  }
+#pragma unroll
+  for (int t = 0; t < kSlots; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n) V[(size_t)i * n + j] = y[t];
+  }
+}
+
+struct TriLayout {
+  size_t ap, hv, gam, d, e, ph, z, end;
+};
+static TriLayout tri_layout(int n) {
+  TriLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t r = o; o = (o + b + 255) / 256 * 256; return r; };
+  L.ap = take((size_t)n * (n + 1) / 2 * sizeof(double2));
+  L.hv = take((size_t)n * n * sizeof(double2));
+  L.gam = take((size_t)n * sizeof(double));
+  L.d = take((size_t)n * sizeof(double));
+  L.e = take((size_t)n * sizeof(double));
+  L.ph = take((size_t)n * sizeof(double2));
+  L.z = take((size_t)n * n * sizeof(double));
+  L.end = o;
+  return L;
+}
+
+size_t tridiag_ws_size(int n) { return n > 0 ? tri_layout(n).end : 0; }
+
+hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, void* ws,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > kTriMaxN) return hipErrorInvalidValue;
+  const TriLayout L = tri_layout(n);
+  char* w = reinterpret_cast<char*>(ws);
+  double2* Ap = reinterpret_cast<double2*>(w + L.ap);
+  double2* Hv = reinterpret_cast<double2*>(w + L.hv);
+  double* gam = reinterpret_cast<double*>(w + L.gam);
+  double* d = reinterpret_cast<double*>(w + L.d);
+  double* e = reinterpret_cast<double*>(w + L.e);
+  double2* ph = reinterpret_cast<double2*>(w + L.ph);
+  double* Z = reinterpret_cast<double*>(w + L.z);
+  const double2* Ag = reinterpret_cast<const double2*>(A);
+  const size_t lds_a = (size_t)n * (n + 1) / 2 * sizeof(double2);
+  if (lds_a <= kTriLdsBudget)
+    hipLaunchKernelGGL((k_hetrd<true>), dim3(1), dim3(kTriThreads), lds_a, st, Ag, n, Ap, Hv, gam,
+                       d, e, ph);
+  else
+    hipLaunchKernelGGL((k_hetrd<false>), dim3(1), dim3(kTriThreads), 0, st, Ag, n, Ap, Hv, gam, d,
+                       e, ph);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_tri_eigvals, dim3(1), dim3(kTriThreads), 0, st, d, e, n, lam);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int nb = (n + kTriWaves - 1) / kTriWaves;
+  hipLaunchKernelGGL(k_tri_invit, dim3(nb), dim3(64 * kTriWaves), 0, st, d, e, lam, n, Z);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const size_t lds_z = (size_t)n * n * sizeof(double);
+  if (lds_z <= kTriLdsBudget)
+    hipLaunchKernelGGL((k_tri_mgs<true>), dim3(1), dim3(kTriThreads), lds_z, st, Z, n);
+  else
+    hipLaunchKernelGGL((k_tri_mgs<false>), dim3(1), dim3(kTriThreads), 0, st, Z, n);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_tri_back, dim3(nb), dim3(64 * kTriWaves), 0, st, Z, ph, Hv, gam, n,
+                     reinterpret_cast<double2*>(V));
+  return hipGetLastError();
+}
+
+}  // namespace mpt
