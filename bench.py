@@ -21,8 +21,12 @@ Two more forms sit beside the plain path (each prints its own JSON line):
 For these forms the dictionary's snapshots are refined to 1e-6 relative
 residual (the reduced models stay Galerkin projections of the full operator).
 
+  --form adaptive  64^3 two-material sphere: three adaptive rounds (Algorithm 1)
+                   with host solves at the selected frequencies, then the hot
+                   path at the final snapshot set (M <= 96, 10^5 omegas)
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--form plain|batched|adjoint] [--objects N]
+                       [--form plain|batched|adjoint|adaptive] [--objects N]
 """
 from __future__ import annotations
 
@@ -46,6 +50,41 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_ellipsoid48.md")
+KERNEL_SOURCES = {
+    "sweep": ["paper_2307_05590_amd/csrc/sweep_impl.h", "paper_2307_05590_amd/csrc/sweep.hip",
+              "paper_2307_05590_amd/csrc/device_util.h"],
+    "spmm": ["paper_2307_05590_amd/csrc/spmm.hip", "paper_2307_05590_amd/csrc/device_util.h"],
+}
+
+
+def source_digest(kind):
+    import hashlib
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each scaled by what
+    the counter reads for a plain 1 GiB copy), or None when the summary is
+    missing or the kernel's sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            text = f.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    k = blob.get("kernels", {}).get(kind)
+    cal = blob.get("calibration", {})
+    if not k or k.get("source_sha1") != source_digest(kind):
+        return None
+    return 1024.0 * (k["fetch_kib"] * cal["fetch_factor"] + k["write_kib"] * cal["write_factor"])
+
+
 def sweep_flops(M):
     """Algorithmic FP64 flops per (object, omega): complex LU 8/3 M^3, forming A
     4 M^2, three solves 24 M^2, four reduced mat-vecs on three vectors 96 M^2,
@@ -66,7 +105,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--form", choices=["plain", "batched", "adjoint"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive"], default="plain")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -85,6 +124,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.calibrate:
         copy_calibration(dev)
+    if args.form == "adaptive":
+        return bench_adaptive(args)
     if args.form != "plain":
         return bench_dictionary(args)
     t0 = time.time()
@@ -162,7 +203,8 @@ def main():
     dominant = max(stages, key=lambda s: ms[s])
     roofline = {"kernel": "sweep (k_sweep: reduced LU + solves + tensors + certificates)",
                 "bound": "alu", "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF,
-                "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4),
+                "traffic": measured_traffic("sweep"),
                 "flops_per_unit": sweep_flops(M), "units_per_launch": n_omega,
                 "launch_ms": round(ms["sweep"], 4)}
 
@@ -192,7 +234,8 @@ def main():
         "roofline": roofline,
         "spmm": {"bound": "hbm", "achieved": round(spmm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(spmm_gbs / HBM_PEAK_GBS, 4), "launch_ms": round(spmm_ms, 4),
-                 "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M)},
+                 "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M),
+                 "traffic": measured_traffic("spmm")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -396,6 +439,114 @@ def cpu_baseline_dictionary(kept, form, budget_s):
             "sample": f"{len(kept)} objects: oracle POD + projection + residual Gram + "
                       f"{'sweep + forward sensitivities' if form == 'adjoint' else 'sweep'} "
                       f"over {done} frequencies in {t:.1f} s"}
+
+
+def bench_adaptive(args):
+    """Adaptive POD (Algorithm 1) on the 64^3 two-material sphere (steel core
+    mu_r 50, sigma 6e6 in an aluminium shell sigma 3.5e7): 48 initial
+    snapshots, three rounds of POD + projection + sweep with certificates over
+    10^5 omegas + selection of two new frequencies, each followed by host
+    full-order solves at those frequencies (untimed), then the timed step: one
+    pass of the hot path at the final snapshot set (M <= 96)."""
+    import torch
+
+    from paper_2307_05590_amd import mpt
+    from synth import make_problem
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    log("shell64: 48 initial snapshots on the 64^3 grid (host) ...")
+    p = make_problem("shell64", verbose=True)
+    ops = p.ops
+    log(f"generated in {time.time() - t0:.0f} s: N={ops.N} nnz={ops.K.nnz} "
+        f"n_c={ops.cond_idx.size} D={p.D.shape}")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    K = mpt.Csr.from_scipy(ops.K, dev)
+    c = T(ops.c, torch.float64)
+    w = T(p.w, torch.float64)
+    o = T(p.o, torch.float64) if np.any(p.o) else None
+    vol = T(ops.vol, torch.float64)
+    cond = T(ops.cond_idx, torch.int32)
+    S = T(p.S, torch.float64)
+    omega = T(p.omega, torch.float64)
+    tol, cap, nstar = p.wl.tol_sigma, p.wl.m_cap, p.wl.n_star
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(D, snap, record=None):
+        e = [ev() for _ in range(5)]
+        e[0].record()
+        U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
+        e[1].record()
+        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, S)
+        e[2].record()
+        out, st = mpt.mpt_sweep(rom, omega)
+        e[3].record()
+        new, lam, Lmax = mpt.mpt_select_snapshots(omega, out, snap, nstar)
+        e[4].record()
+        if record is not None:
+            record.append(e)
+        return M, sig, out, st, new, Lmax
+
+    rounds = []
+    for r in range(p.wl.adapt_rounds):
+        D = T(p.D, torch.complex128)
+        snap = T(np.sort(p.snap_omega), torch.float64)
+        rec = []
+        M, sig, out, st, new, Lmax = step(D, snap, rec)
+        torch.cuda.synchronize()
+        assert int(st.abs().max()) == 0, "singular reduced system"
+        new_h = new.cpu().numpy()
+        new_h = new_h[np.isfinite(new_h)]
+        ms = [rec[0][i].elapsed_time(rec[0][i + 1]) for i in range(4)]
+        rounds.append({"columns": int(p.D.shape[1]), "M": int(M), "Lambda": float(Lmax.item()),
+                       "new_omega": [float(x) for x in new_h], "gpu_ms": round(sum(ms), 3)})
+        log(f"round {r + 1}: {p.D.shape[1]} columns, M={M}, Lambda={Lmax.item():.3e}, "
+            f"new omega {new_h}, GPU {sum(ms):.2f} ms (pod/project/sweep/select {ms})")
+        del D
+        t1 = time.time()
+        p.add_snapshots(new_h)
+        log(f"  host snapshots at the new frequencies in {time.time() - t1:.0f} s")
+    D = T(p.D, torch.complex128)
+    snap = T(np.sort(p.snap_omega), torch.float64)
+    for _ in range(args.warmup):
+        step(D, snap)
+    torch.cuda.synchronize()
+    rec = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        M, sig, out, st, new, Lmax = step(D, snap, rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    assert int(st.abs().max()) == 0, "singular reduced system"
+    stages = ["pod", "project", "sweep", "select"]
+    ms = {s_: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in rec])) for i, s_ in
+          enumerate(stages)}
+    n_omega = omega.numel()
+    value = n_omega / (elapsed / args.steps)
+    sweep_tf = sweep_flops(M) * n_omega / (ms["sweep"] * 1e-3) / 1e12
+    log(f"final: {p.D.shape[1]} columns, M={M}, ms/step {1e3 * elapsed / args.steps:.3f}, {ms}")
+    cpu = None if args.no_cpu else cpu_baseline(p, args.cpu_seconds)
+    line = {
+        "metric": "MPT tensors/sec (3x3 + error cert per omega per object)",
+        "value": round(value, 1), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "shell64: steel core (mu_r 50, sigma 6e6) in an aluminium shell "
+                               "(sigma 3.5e7) on a 64^3 Yee grid, 48 + 3x2 adaptive snapshots, "
+                               "TOL 1e-8, M<=96, 1e5 omegas",
+                   "N": int(ops.N), "nnz": int(ops.K.nnz), "n_snap": int(p.snap_omega.size),
+                   "M": int(M), "n_omega": int(n_omega), "rounds": rounds},
+        "stages_ms": {k: round(v, 4) for k, v in ms.items()},
+        "roofline": {"kernel": "sweep (M > 64: LDS-resident system, one workgroup per omega)"
+                     if M > 64 else "sweep (k_sweep)", "bound": "alu",
+                     "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4), "traffic": None,
+                     "flops_per_unit": sweep_flops(M), "units_per_launch": int(n_omega),
+                     "launch_ms": round(ms["sweep"], 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(p, budget_s):

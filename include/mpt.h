@@ -76,6 +76,9 @@ typedef struct {
  *                 I terms of (I_tensor_coeffs) under Remark 3.1)
  *   N0  3 x 3     static tensor (eq. (NRI), first line)
  * alpha is the object size (m); alpha_lb the stability bound of Lemma 4.1.
+ * KM, A0, CM and G are Hermitian by definition and must be stored Hermitian:
+ * the sweep reads row r of these matrices as the conjugate of column r (one
+ * coalesced load per column).  mpt_project stores them exactly Hermitian.
  */
 typedef struct {
   int32_t M;
@@ -96,8 +99,11 @@ typedef struct {
  *     "Form D_i" / "obtain the TSVDs").
  * D: N x ncol complex (ldD >= ncol), the joint snapshot matrix
  *    [q_1(w_1..K) | q_2(...) | q_3(...)].
- * Thin SVD by two passes of Gram / Hermitian Jacobi eigen-decomposition /
- * rotation (FP64 MFMA Gram), then truncation: M = #{s_m/s_1 >= tol_sigma},
+ * Thin SVD by two passes of Gram / Hermitian eigen-decomposition / rotation
+ * (FP64 MFMA Gram and rotation): pass 1 eigen-decomposes D^H D by Householder
+ * tridiagonalisation, multisection and inverse iteration, pass 2 the Gram of
+ * the rotated snapshots by Jacobi (relative accuracy of the small singular
+ * values).  Then truncation: M = #{s_m/s_1 >= tol_sigma},
  * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
  * a cluster).  Writes U (N x M_cap, ldU >= M_cap; columns >= M are zero),
  * sigma (ncol, descending).  *M_out is a HOST pointer: the call synchronises
@@ -144,9 +150,12 @@ mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU
  *   p = 6..11  I  (same order)
  *   p = 12..17 Delta (same order), w^(i) = [i w e_i ; -a_i ; i w a_i].
  * a_out (n_omega x 3 x M complex) receives a_i when non-NULL.
- * status[k] = 0, or MPT_E_SINGULAR when a pivot was zero / non-finite (the
- * call then also returns MPT_E_SINGULAR after synchronising).  rom is a
- * HOST struct holding device pointers.  1 <= M <= mpt_max_reduced_dim().
+ * status[k] (device) = 0, or MPT_E_SINGULAR when a pivot was zero or
+ * non-finite.  The call does not synchronise: it returns MPT_OK once the work
+ * is enqueued, and the caller reads status after the stream.  rom is a HOST
+ * struct holding device pointers.  1 <= M <= mpt_max_reduced_dim() (96);
+ * M <= 64 runs one frequency per wave segment in registers, larger M one
+ * frequency per workgroup with the system in LDS.
  */
 mpt_status mpt_sweep(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n_omega,
                      double* out, double* a_out, int32_t* status);
@@ -171,7 +180,8 @@ mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n, co
  * count and materials.  roms: DEVICE array of n_obj mpt_rom.  omega_off
  * (n_obj + 1, host) indexes omega / out / status: object o owns rows
  * omega_off[o] .. omega_off[o+1]-1.  Results equal mpt_sweep object by
- * object.  tune: NULL for the tuned defaults.
+ * object.  tune: NULL for the tuned defaults.  Every object needs M <= 64
+ * (MPT_E_UNSUPPORTED otherwise).
  */
 typedef struct {
   int32_t omegas_per_item;   /* frequencies per work item (>= 1) */
@@ -193,7 +203,8 @@ mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host, const mpt_r
  * A (recomputed here; nothing is kept between calls), and
  * sig_dsig = sigma_* dL/dsigma_* (one value) for a single conductivity
  * that scales C_sigma, g and E with the basis frozen.
- * Same sizes and rom rules as mpt_sweep.
+ * Same sizes and rom rules as mpt_sweep, with M <= 64 (MPT_E_UNSUPPORTED
+ * otherwise).
  */
 mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n,
                              const double* dout, double* dL_domega, double* sig_dsig,

@@ -84,7 +84,7 @@ mpt_status ensure_scr(mpt_handle h, size_t bytes) {
 
 mpt_status check_rom(mpt_handle h, const mpt_rom* R) {
   ARG(R != nullptr, "rom is NULL");
-  ARG(R->M >= 1 && R->M <= 64, "rom M must be in [1, 64]");
+  ARG(R->M >= 1 && R->M <= 96, "rom M must be in [1, 96]");
   ARG(R->KM && R->A0 && R->CM && R->g && R->G && R->E && R->N0, "rom has a NULL matrix");
   ARG(R->alpha > 0.0 && R->alpha_lb > 0.0, "rom alpha and alpha_lb must be positive");
   return MPT_OK;
@@ -178,10 +178,17 @@ __global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KM,
                            const double2* __restrict__ UhU, const double2* __restrict__ Gc,
                            const double2* __restrict__ P, const double2* __restrict__ Ew,
                            const double2* __restrict__ No, const double* __restrict__ vol,
-                           double alpha, double2* __restrict__ A0, double2* __restrict__ CM,
-                           double2* __restrict__ g, double2* __restrict__ G,
-                           double* __restrict__ E, double* __restrict__ N0) {
+                           double alpha, double2* __restrict__ KMo, double2* __restrict__ A0,
+                           double2* __restrict__ CM, double2* __restrict__ g,
+                           double2* __restrict__ G, double* __restrict__ E,
+                           double* __restrict__ N0) {
   const int L = 2 * M + 3;
+  // K_M, U^H U and C_M are Hermitian by definition; the two computed
+  // triangles are averaged (the sweep reads them column-wise)
+  auto herm = [&](const double2* X, int ld, int off, int i, int j) {
+    const double2 u = X[i * ld + off + j], t = X[j * ld + off + i];
+    return make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
+  };
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nthreads = gridDim.x * blockDim.x;
   // position maps: G index -> (block, local)
@@ -203,7 +210,7 @@ __global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KM,
       const double2 u = Gc[ia * LG + ib], t = Gc[ib * LG + ia];
       v = make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
     } else if (ca == 1 && cb == 1) {
-      const double2 k = KM[la * M + lb], u = UhU[la * M + lb];
+      const double2 k = herm(KM, M, 0, la, lb), u = herm(UhU, M, 0, la, lb);
       v = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
     } else if (ca == 1) {  // x row, w/c column: (X U)^H X^{-1} Z = U^H Z = P
       const int ib = cb == 0 ? lb : 3 + lb;
@@ -216,9 +223,10 @@ __global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KM,
   }
   for (int e = tid; e < M * M; e += nthreads) {
     const int i = e / M, j = e % M;
-    const double2 k = KM[e], u = UhU[e];
+    const double2 k = herm(KM, M, 0, i, j), u = herm(UhU, M, 0, i, j);
+    KMo[e] = k;
     A0[e] = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
-    CM[e] = P[i * (M + 3) + 3 + j];
+    CM[e] = herm(P, M + 3, 3, i, j);
   }
   for (int e = tid; e < 3 * M; e += nthreads) {
     const int i = e / M, m = e % M;
@@ -284,7 +292,7 @@ extern "C" mpt_status mpt_set_stream(mpt_handle h, void* hip_stream) {
 
 extern "C" const char* mpt_last_error(mpt_handle h) { return h ? h->err.c_str() : "null handle"; }
 
-extern "C" int mpt_max_reduced_dim(void) { return 64; }
+extern "C" int mpt_max_reduced_dim(void) { return 96; }
 
 // ------------------------------------------------------------------ a1 POD
 constexpr int kJacobiSweeps = 40;
@@ -381,17 +389,18 @@ static void proj_layout(int64_t N, int M, int64_t nc, size_t* off) {
   off[9] = o; o = align256(o + (size_t)N * 3 * 16);         // Oc (o as complex)
   off[10] = o; o = align256(o + (size_t)N * 3 * 16);        // KO
   off[11] = o; o = align256(o + 9 * 16);                    // No
-  off[12] = o;
+  off[12] = o; o = align256(o + (size_t)M * M * 16);        // U^H K U before symmetrising
+  off[13] = o;
   o = align256(o + std::max(std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)),
                             rcgemm_ws_size(nc, L)));
-  off[13] = o;
+  off[14] = o;
 }
 
 extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c) {
   if (N <= 0 || M <= 0) return 0;
-  size_t off[14];
+  size_t off[15];
   proj_layout(N, M, n_c, off);
-  return off[13];
+  return off[14];
 }
 
 extern "C" mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU,
@@ -421,7 +430,7 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
   hipStream_t st = h->stream;
   const int64_t N = K->n;
   const int L = M + 3;
-  size_t off[14];
+  size_t off[15];
   proj_layout(N, M, n_c, off);
   char* wsb = reinterpret_cast<char*>(ws);
   double* Yb = Y ? Y : reinterpret_cast<double*>(wsb + off[0]);
@@ -437,12 +446,12 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
   double* Oc = reinterpret_cast<double*>(wsb + off[9]);
   double* KO = reinterpret_cast<double*>(wsb + off[10]);
   double* No = reinterpret_cast<double*>(wsb + off[11]);
-  void* gws = wsb + off[12];
+  double* KMt = reinterpret_cast<double*>(wsb + off[12]);
+  void* gws = wsb + off[13];
 
   // Y = K U; K_M = U^H Y; U^H U
   HIP_OK(spmm_launch(*K, U, ldU, M, Yb, ldY, st));
-  HIP_OK(gram_launch(U, ldU, Yb, ldY, N, M, M, KM, M, gws, st));
-  HIP_OK(gram_launch(U, ldU, U, ldU, N, M, M, UhU, M, gws, st));
+  HIP_OK(gram2_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, gws, st));
   // conductor block: Zc = [c w | c U], T = S Zc, Gc = Zc^H T, P = Uc^H Zc
   {
     const int64_t tot = n_c * L;
@@ -468,11 +477,12 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
     Nop = reinterpret_cast<const double2*>(No);
   }
   hipLaunchKernelGGL(k_assemble, dim3(64), dim3(256), 0, st, M, eps_h,
-                     reinterpret_cast<const double2*>(KM), reinterpret_cast<const double2*>(UhU),
+                     reinterpret_cast<const double2*>(KMt), reinterpret_cast<const double2*>(UhU),
                      reinterpret_cast<const double2*>(Gc), reinterpret_cast<const double2*>(P),
                      reinterpret_cast<const double2*>(Ew), Nop, vol, alpha,
-                     reinterpret_cast<double2*>(A0), reinterpret_cast<double2*>(CM),
-                     reinterpret_cast<double2*>(g), reinterpret_cast<double2*>(G), E, N0);
+                     reinterpret_cast<double2*>(KM), reinterpret_cast<double2*>(A0),
+                     reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g),
+                     reinterpret_cast<double2*>(G), E, N0);
   HIP_OK(hipGetLastError());
   return MPT_OK;
 }
@@ -496,6 +506,7 @@ extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const 
   if (!h) return MPT_E_ARG;
   mpt_status s = check_rom(h, rom);
   if (s != MPT_OK) return s;
+  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the adjoint sweep takes M <= 64");
   ARG(n >= 1, "n must be >= 1");
   ARG(omega && dout && dL_domega && sig_dsig && status, "NULL pointer");
   HIP_OK(hipSetDevice(h->device));
@@ -544,6 +555,8 @@ mpt_status build_plan(mpt_handle h, const mpt_rom* roms_host, int n_obj, const i
   for (int o = 0; o < n_obj; ++o) {
     mpt_status s = check_rom(h, &roms_host[o]);
     if (s != MPT_OK) return s;
+    if (roms_host[o].M > 64)
+      return fail(h, MPT_E_UNSUPPORTED, "batched sweeps take M <= 64");
     ARG(off[o + 1] >= off[o], "omega_off must be non-decreasing");
     const int b = bucket_of(roms_host[o].M);
     const int bi = b == 16 ? 0 : (b == 32 ? 1 : (b == 48 ? 2 : 3));

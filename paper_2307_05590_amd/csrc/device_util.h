@@ -70,15 +70,81 @@ __device__ __forceinline__ double shfl_d(double v, int src_lane) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, shfl_xor_d(v, m));
+// DPP lane moves of a double (both halves with the same control); lanes the
+// control does not write keep `old`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, 0xf,
+                                             0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7-i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15-i within 16 lanes
+
+// sum / max over each group of 16 lanes (a DPP row), result in every lane
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<kDppXor1>(v, 0.0);
+  v += dpp_d<kDppXor2>(v, 0.0);
+  v += dpp_d<kDppHalfMirror>(v, 0.0);
+  v += dpp_d<kDppMirror>(v, 0.0);
   return v;
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+__device__ __forceinline__ double row16_max(double v) {
+  v = fmax(v, dpp_d<kDppXor1>(v, v));
+  v = fmax(v, dpp_d<kDppXor2>(v, v));
+  v = fmax(v, dpp_d<kDppHalfMirror>(v, v));
+  v = fmax(v, dpp_d<kDppMirror>(v, v));
   return v;
+}
+// combine each lane's value with the one 16 (32) lanes away, gfx950
+// v_permlane16_swap / v_permlane32_swap: the two results of the swap hold
+// both values of every lane pair
+__device__ __forceinline__ void swap16_d(double v, double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false,
+                                                   false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void swap32_d(double v, double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false,
+                                                   false);
+  a = __hiloint2double(hi[0], lo[0]);
+  b = __hiloint2double(hi[1], lo[1]);
+}
+// max over groups of 16 / 32 / 64 lanes, result in every lane of the group
+template <int L>
+__device__ __forceinline__ double group_max(double v) {
+  v = row16_max(v);
+  if constexpr (L >= 32) {
+    double a, b;
+    swap16_d(v, a, b);
+    v = fmax(a, b);
+  }
+  if constexpr (L >= 64) {
+    double a, b;
+    swap32_d(v, a, b);
+    v = fmax(a, b);
+  }
+  return v;
+}
+
+// wave-wide sum / max, result (uniform) in every lane: DPP inside each row of
+// 16 lanes, then the four row results by v_readlane in a fixed order
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = row16_max(v);
+  return fmax(fmax(bcast(v, 0), bcast(v, 16)), fmax(bcast(v, 32), bcast(v, 48)));
 }
 
 // Reduce-scatter of 64 per-lane partial sums: on return, lane l holds the

@@ -20,67 +20,149 @@ __device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// rows per partial: chosen so that a launch has about a thousand workgroups
-// while the partial sums (chunks x m x n) stay small next to the operands
-__host__ __device__ inline int64_t gram_rows(int64_t N, int m, int n) {
-  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
-  const int64_t groups_per_chunk = (TI * JG + 3) / 4;
-  int64_t rows = N * groups_per_chunk / 1024;
-  rows = rows < 16 ? 16 : (rows > 8192 ? 8192 : rows);
-  return (rows + 3) / 4 * 4;
+// ---------------------------------------------------------------- Gram
+// One workgroup owns every output tile of its chunk of rows, so each row is
+// read from HBM once and shared by the waves through L1/L2.  The tiles (16x16)
+// of up to two products - P1 = A^H B (all tiles, or I <= J when A == B) and
+// P2 = A^H A (I <= J) - are split into contiguous runs over the waves; a wave
+// keeps its run in MFMA accumulators and reloads an A fragment only when the
+// tile row changes.  Per-chunk partials are summed in a fixed order
+// (deterministic).
+constexpr int kGramMaxChunks = 512;
+
+struct GramPlan {
+  int TI, TJ, t1, t2, T;  // tile rows / cols of P1, tiles of P1, P2, total
+  bool herm1;
+  int waves, maxt;
+  int64_t chunks, rows;
+};
+
+static int herm_tiles(int TI) { return TI * (TI + 1) / 2; }
+
+static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
+  GramPlan g;
+  g.TI = (m + 15) / 16;
+  g.TJ = (n + 15) / 16;
+  g.herm1 = herm1;
+  g.t1 = herm1 ? herm_tiles(g.TI) : g.TI * g.TJ;
+  g.t2 = dual ? herm_tiles(g.TI) : 0;
+  g.T = g.t1 + g.t2;
+  // 4 waves with up to 8 tiles each, else 8 waves with up to 10 (m <= 192)
+  g.waves = g.T <= 32 ? 4 : 8;
+  const int per = (g.T + g.waves - 1) / g.waves;
+  g.maxt = g.waves == 8 ? 10 : (per <= 2 ? 2 : (per <= 4 ? 4 : (per <= 6 ? 6 : 8)));
+  int64_t ch = (N + 15) / 16;
+  if (ch > kGramMaxChunks) ch = kGramMaxChunks;
+  if (ch < 1) ch = 1;
+  g.rows = ((N + ch - 1) / ch + 3) / 4 * 4;
+  g.chunks = N > 0 ? (N + g.rows - 1) / g.rows : 0;
+  return g;
 }
 
-// grid: x = row chunk, y = wave-task group (4 waves per group);
-// wave-task t -> tile row I = t / JG, tile column group jg = t % JG (4 tiles)
-__global__ __launch_bounds__(256) void k_gram_partial(const double2* __restrict__ A, int64_t lda,
-                                                      const double2* __restrict__ B, int64_t ldb,
-                                                      int64_t N, int m, int n, int64_t rows,
-                                                      int herm, double2* __restrict__ part) {
+// tile index t -> (I, J) of the list: t < t1: P1 tiles, else P2 tiles
+__device__ __forceinline__ void tile_of(int t, int TI, int TJ, int t1, bool herm1, int& I, int& J,
+                                        int& which) {
+  which = t < t1 ? 0 : 1;
+  int u = t < t1 ? t : t - t1;
+  if (which == 0 && !herm1) {
+    I = u / TJ;
+    J = u % TJ;
+    return;
+  }
+  // upper triangle, row-major: row I holds TI - I tiles
+  I = 0;
+  while (u >= TI - I) {
+    u -= TI - I;
+    ++I;
+  }
+  J = I + u;
+}
+
+template <int MAXT, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
+                                                     const double2* __restrict__ B, int64_t ldb,
+                                                     int64_t N, int m, int n, int64_t rows,
+                                                     int herm1, int t1, int T,
+                                                     double2* __restrict__ part1,
+                                                     double2* __restrict__ part2) {
   const int lane = __lane_id();
-  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
-  const int task = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (task >= TI * JG) return;
-  const int I = task / JG, jg = task % JG;
-  // Hermitian product (A == B): tiles left of the diagonal come from their mirror
-  if (herm && jg * 4 + 3 < I) return;
-  const int64_t r0 = (int64_t)blockIdx.x * rows;
-  const int64_t r1 = min(N, r0 + rows);
-  const int ar = I * 16 + (lane & 15);  // column of A feeding this lane
-  const bool aok = ar < m;
-  double4_t accr[4], acci[4];
+  // wave-uniform values in scalar registers, so the tile loop branches on SCC
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int TI = (m + 15) / 16, TJ = (n + 15) / 16;
+  const int tb = (wave * T) / nw, te = ((wave + 1) * T) / nw;  // this wave's run
+  const int nt = te - tb;
+  int tI[MAXT], tJ[MAXT], tw[MAXT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < MAXT; ++t) {
+    tI[t] = tJ[t] = tw[t] = 0;
+    if (t < nt) tile_of(tb + t, TI, TJ, t1, herm1 != 0, tI[t], tJ[t], tw[t]);
+    tI[t] = __builtin_amdgcn_readfirstlane(tI[t]);
+    tJ[t] = __builtin_amdgcn_readfirstlane(tJ[t]);
+    tw[t] = __builtin_amdgcn_readfirstlane(tw[t]);
+  }
+  double4_t accr[MAXT], acci[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
     accr[t] = double4_t{0, 0, 0, 0};
     acci[t] = double4_t{0, 0, 0, 0};
   }
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int64_t r1 = min(N, r0 + rows);
+  const int cl = lane & 15;
+  // loads are clamped into range and masked with selects (no branches), so
+  // the compiler can issue every fragment load of a step back to back
+  const double2 z2 = make_double2(0.0, 0.0);
   for (int64_t k0 = r0; k0 < r1; k0 += 4) {
     const int64_t row = k0 + (lane >> 4);
     const bool rok = row < r1;
-    const double2 a = (rok && aok) ? A[row * lda + ar] : make_double2(0.0, 0.0);
+    const int64_t rowc = rok ? row : r1 - 1;
+    const double2* ar = A + rowc * lda;
+    const double2* br = B + rowc * ldb;
+    double2 fa[MAXT], fb[MAXT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int J = jg * 4 + t;
-      if (J < TJ && !(herm && J < I)) {
-        const int bc = J * 16 + (lane & 15);
-        const double2 bb = (rok && bc < n) ? B[row * ldb + bc] : make_double2(0.0, 0.0);
-        // P = A^H B: re = ar.br + ai.bi ; im = ar.bi - ai.br
-        accr[t] = mfma(a.x, bb.x, accr[t]);
-        accr[t] = mfma(a.y, bb.y, accr[t]);
-        acci[t] = mfma(a.x, bb.y, acci[t]);
-        acci[t] = mfma(-a.y, bb.x, acci[t]);
+    for (int t = 0; t < MAXT; ++t) {  // all loads of the step first
+      fa[t] = fb[t] = z2;
+      if (t < nt) {
+        const int I = tI[t], J = tJ[t];
+        if (t == 0 || I != tI[t > 0 ? t - 1 : 0]) {  // wave-uniform
+          const int c = I * 16 + cl;
+          const double2 x = ar[c < m ? c : m - 1];
+          fa[t] = (rok && c < m) ? x : z2;
+        } else {
+          fa[t] = fa[t > 0 ? t - 1 : 0];
+        }
+        const int c = J * 16 + cl;
+        const bool self = tw[t] == 1 || herm1;
+        const int cmax = self ? m : n;
+        const double2* src = self ? ar : br;
+        const double2 y = src[c < cmax ? c : cmax - 1];
+        fb[t] = (rok && c < cmax) ? y : z2;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      if (t < nt) {
+        const double2 a = fa[t], b = fb[t];
+        // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
+        accr[t] = mfma(a.x, b.x, accr[t]);
+        accr[t] = mfma(a.y, b.y, accr[t]);
+        acci[t] = mfma(a.x, b.y, acci[t]);
+        acci[t] = mfma(-a.y, b.x, acci[t]);
       }
     }
   }
-  double2* P = part + (size_t)blockIdx.x * m * n;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int J = jg * 4 + t;
-    if (J >= TJ || (herm && J < I)) continue;
-    const int col = J * 16 + (lane & 15);
+  for (int t = 0; t < MAXT; ++t) {
+    if (t >= nt) continue;
+    const int I = tI[t], J = tJ[t];
+    const bool second = tw[t] == 1;
+    const int ncol = second ? m : n;
+    double2* P = (second ? part2 + (size_t)blockIdx.x * m * m : part1 + (size_t)blockIdx.x * m * n);
+    const int col = J * 16 + cl;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rowo = I * 16 + (lane >> 4) + 4 * v;
-      if (rowo < m && col < n) P[(size_t)rowo * n + col] = make_double2(accr[t][v], acci[t][v]);
+      if (rowo < m && col < ncol) P[(size_t)rowo * ncol + col] = make_double2(accr[t][v], acci[t][v]);
     }
   }
 }
@@ -123,94 +205,148 @@ __global__ void k_sum_partials2(const double2* __restrict__ mid, int mn,
 }
 
 size_t gram_ws_size(int64_t N, int m, int n) {
-  const int64_t rows = gram_rows(N, m, n);
-  const int64_t chunks = (N + rows - 1) / rows;
-  return (size_t)(chunks + kSumSlices) * m * n * sizeof(double2);
+  // room for the dual form (P1 m x n and P2 m x m) at the largest chunk count
+  const GramPlan g = gram_plan(N, m, n, false, true);
+  const size_t mn = (size_t)m * n, mm = (size_t)m * m;
+  return ((size_t)g.chunks * (mn + mm) + kSumSlices * (mn > mm ? mn : mm)) * sizeof(double2);
 }
 
-hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
-                       int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st) {
-  if (m <= 0 || n <= 0) return hipSuccess;
-  const int64_t rows = gram_rows(N, m, n);
-  const int64_t chunks = N > 0 ? (N + rows - 1) / rows : 0;
-  const int TI = (m + 15) / 16, TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
-  const int tasks = TI * JG;
-  double2* part = reinterpret_cast<double2*>(ws);
-  double2* mid = part + (size_t)chunks * m * n;
-  const int herm = (A == B && lda == ldb && m == n) ? 1 : 0;
-  if (chunks > 0) {
-    hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)chunks, (tasks + 3) / 4), dim3(256), 0, st,
-                       reinterpret_cast<const double2*>(A), lda,
-                       reinterpret_cast<const double2*>(B), ldb, N, m, n, rows, herm, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+static hipError_t gram_reduce(const double2* part, int64_t chunks, int m, int n, double* P,
+                              int64_t ldp, bool herm, double2* mid, hipStream_t st) {
   const int mn = m * n;
   hipLaunchKernelGGL(k_sum_partials1, dim3((mn + 255) / 256, kSumSlices), dim3(256), 0, st, part,
                      (int)chunks, mn, mid);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_partials2, dim3((mn + 255) / 256), dim3(256), 0, st, mid, mn,
-                     reinterpret_cast<double2*>(P), n, ldp, herm);
+                     reinterpret_cast<double2*>(P), n, ldp, herm ? 1 : 0);
   return hipGetLastError();
 }
 
-// C (N x n) = A (N x m) V (m x n); one wave per (16-row tile, group of 4
-// column tiles)
+hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                        int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                        void* ws, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const bool herm1 = (A == B && lda == ldb && m == n);
+  const bool dual = P2 != nullptr;
+  const GramPlan g = gram_plan(N, m, n, herm1, dual);
+  double2* part1 = reinterpret_cast<double2*>(ws);
+  double2* part2 = part1 + (size_t)g.chunks * m * n;
+  double2* mid = part2 + (dual ? (size_t)g.chunks * m * m : 0);
+  if (g.chunks > 0) {
+    const dim3 grid((unsigned)g.chunks), block(64 * g.waves);
+    const double2* Ac = reinterpret_cast<const double2*>(A);
+    const double2* Bc = reinterpret_cast<const double2*>(B);
+#define MPT_GC(MT)                                                                               \
+  hipLaunchKernelGGL((k_gram_chunk<MT, (MT > 8 ? 8 : 4)>), grid, block, 0, st, Ac, lda, Bc, ldb, \
+                     N, m, n, g.rows, herm1 ? 1 : 0, g.t1, g.T, part1, part2)
+    switch (g.maxt) {
+      case 2: MPT_GC(2); break;
+      case 4: MPT_GC(4); break;
+      case 6: MPT_GC(6); break;
+      case 8: MPT_GC(8); break;
+      default: MPT_GC(10); break;
+    }
+#undef MPT_GC
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    hipError_t e = hipMemsetAsync(part1, 0, (size_t)m * n * sizeof(double2), st);
+    if (e == hipSuccess && dual) e = hipMemsetAsync(part2, 0, (size_t)m * m * sizeof(double2), st);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t ch = g.chunks > 0 ? g.chunks : 1;
+  hipError_t e = gram_reduce(part1, ch, m, n, P1, ldp1, herm1, mid, st);
+  if (e != hipSuccess || !dual) return e;
+  return gram_reduce(part2, ch, m, m, P2, ldp2, true, mid, st);
+}
+
+hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                       int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st) {
+  return gram2_launch(A, lda, B, ldb, N, m, n, P, ldp, nullptr, 0, ws, st);
+}
+
+// ------------------------------------------------------------- rotation
+// C (N x n) = A (N x m) V (m x n).  A wave owns RT row tiles x CT column tiles
+// (register blocking: RT + CT fragment loads feed 4 RT CT MFMAs per k step);
+// the waves sharing a row block are adjacent, so A rows are reused in L1/L2.
+template <int RT, int CT>
 __global__ __launch_bounds__(256) void k_rotate(const double2* __restrict__ A, int64_t lda,
                                                 int64_t N, int m, const double2* __restrict__ V,
                                                 int64_t ldv, int n, double2* __restrict__ C,
                                                 int64_t ldc) {
   const int lane = __lane_id();
-  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
-  const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t RT = (N + 15) / 16;
-  if (task >= RT * JG) return;
-  const int64_t rt = task / JG;
-  const int jg = (int)(task % JG);
-  const int64_t row = rt * 16 + (lane & 15);
-  const bool rok = row < N;
-  double4_t accr[4], acci[4];
+  const int TJ = (n + 15) / 16, CG = (TJ + CT - 1) / CT;
+  const int64_t task = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t RB = (N + 16 * RT - 1) / (16 * RT);
+  if (task >= RB * CG) return;
+  const int64_t rb = task / CG;
+  const int cg = (int)(task % CG);
+  const int cl = lane & 15, kl = lane >> 4;
+  double4_t accr[RT][CT], acci[RT][CT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    accr[t] = double4_t{0, 0, 0, 0};
-    acci[t] = double4_t{0, 0, 0, 0};
-  }
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      accr[r][c] = double4_t{0, 0, 0, 0};
+      acci[r][c] = double4_t{0, 0, 0, 0};
+    }
+  auto load = [&](int k0, double2 (&a)[RT], double2 (&v)[CT]) {
+    const int k = k0 + kl;
+    const int kc = k < m ? k : m - 1;
+    const double2 z2 = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int64_t row = rb * 16 * RT + r * 16 + cl;
+      const double2 x = A[(row < N ? row : N - 1) * lda + kc];
+      a[r] = (row < N && k < m) ? x : z2;
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = (cg * CT + c) * 16 + cl;
+      const double2 x = V[(int64_t)kc * ldv + (col < n ? col : n - 1)];
+      v[c] = (k < m && col < n) ? x : z2;
+    }
+  };
+  double2 a[RT], v[CT];
+  load(0, a, v);
   for (int k0 = 0; k0 < m; k0 += 4) {
-    const int k = k0 + (lane >> 4);
-    const double2 a = (rok && k < m) ? A[row * lda + k] : make_double2(0.0, 0.0);
+    double2 na[RT], nv[CT];
+    load(k0 + 4, na, nv);  // next step's fragments in flight during the MFMAs
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int J = jg * 4 + t;
-      if (J < TJ) {
-        const int col = J * 16 + (lane & 15);
-        const double2 v = (k < m && col < n) ? V[(int64_t)k * ldv + col] : make_double2(0.0, 0.0);
-        accr[t] = mfma(a.x, v.x, accr[t]);
-        accr[t] = mfma(-a.y, v.y, accr[t]);
-        acci[t] = mfma(a.x, v.y, acci[t]);
-        acci[t] = mfma(a.y, v.x, acci[t]);
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        accr[r][c] = mfma(a[r].x, v[c].x, accr[r][c]);
+        accr[r][c] = mfma(-a[r].y, v[c].y, accr[r][c]);
+        acci[r][c] = mfma(a[r].x, v[c].y, acci[r][c]);
+        acci[r][c] = mfma(a[r].y, v[c].x, acci[r][c]);
+      }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a[r] = na[r];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) v[c] = nv[c];
+  }
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = (cg * CT + c) * 16 + cl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = rb * 16 * RT + r * 16 + kl + 4 * q;
+        if (row < N && col < n) C[row * ldc + col] = make_double2(accr[r][c][q], acci[r][c][q]);
       }
     }
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int J = jg * 4 + t;
-    if (J >= TJ) continue;
-    const int col = J * 16 + (lane & 15);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = rt * 16 + (lane >> 4) + 4 * v;
-      if (r < N && col < n) C[r * ldc + col] = make_double2(accr[t][v], acci[t][v]);
-    }
-  }
 }
 
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
                          int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st) {
   if (N <= 0 || n <= 0) return hipSuccess;
-  const int TJ = (n + 15) / 16, JG = (TJ + 3) / 4;
-  const int64_t tasks = ((N + 15) / 16) * JG;
-  hipLaunchKernelGGL(k_rotate, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st,
+  constexpr int RT = 2, CT = 3;
+  const int TJ = (n + 15) / 16, CG = (TJ + CT - 1) / CT;
+  const int64_t tasks = ((N + 16 * RT - 1) / (16 * RT)) * CG;
+  hipLaunchKernelGGL((k_rotate<RT, CT>), dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(A), lda, N, m,
                      reinterpret_cast<const double2*>(V), ldv, n, reinterpret_cast<double2*>(C),
                      ldc);

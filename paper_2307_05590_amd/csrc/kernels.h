@@ -36,6 +36,10 @@ hipError_t spmm_launch(const mpt_csr& K, const double* U, int64_t ldU, int M, do
 size_t gram_ws_size(int64_t N, int m, int n);
 hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                        int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st);
+//   P1 = A^H B (m x n) and P2 = A^H A (m x m) in one pass over the rows
+hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                        int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                        void* ws, hipStream_t st);
 //   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv).
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
                          int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st);

@@ -41,11 +41,18 @@ __global__ void k_sigma_reduce(const double* __restrict__ omega, const double* _
 // ------------------------------------------------------------ launchers
 int bucket_of(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : (M <= 48 ? 48 : 64)); }
 
+hipError_t sweep_big_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
+                            double* a_out, int32_t* status, hipStream_t st);
+
 hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom,
                         hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const bool adj = dout != nullptr;
+  if (R.M > 64) {  // LDS-resident kernel; no adjoint form at this size
+    if (adj) return hipErrorInvalidValue;
+    return sweep_big_launch(R, omega, n, out, a_out, status, st);
+  }
   switch (bucket_of(R.M)) {
     case 16: return adj ? launch_plain<16, true>(R, omega, n, out, a_out, status, dout, dom, 4, st)
                         : launch_plain<16, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);

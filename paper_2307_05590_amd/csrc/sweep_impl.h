@@ -53,9 +53,7 @@ __device__ __forceinline__ double2 seg_bcast2(double2 v, int src) {
 }
 template <int L>
 __device__ __forceinline__ double seg_max(double v) {
-#pragma unroll
-  for (int m = L / 2; m >= 1; m >>= 1) v = fmax(v, shfl_xor_d(v, m));
-  return v;
+  return group_max<L>(v);  // DPP inside rows, permlane swaps across rows
 }
 template <int L>
 __device__ __forceinline__ double seg_sum(double v) {
@@ -70,6 +68,55 @@ __device__ __forceinline__ int seg_first(bool pred, int base) {
   const uint64_t mask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
   const uint64_t s = (m >> base) & mask;
   return s ? base + (__ffsll((unsigned long long)s) - 1) : -1;
+}
+
+// value of the partner lane at distance D (a lane pairing that flips bit
+// log2 D of the lane id): permlane swaps across rows, DPP mirrors inside
+template <int D>
+__device__ __forceinline__ double xch(double x, int wl) {
+  if constexpr (D == 32) {
+    double a, b;
+    swap32_d(x, a, b);
+    return (wl & 32) ? a : b;
+  } else if constexpr (D == 16) {
+    double a, b;
+    swap16_d(x, a, b);
+    return (wl & 16) ? a : b;
+  } else if constexpr (D == 8) {
+    return dpp_d<kDppMirror>(x, 0.0);
+  } else if constexpr (D == 4) {
+    return dpp_d<kDppHalfMirror>(x, 0.0);
+  } else if constexpr (D == 2) {
+    return dpp_d<kDppXor2>(x, 0.0);
+  } else {
+    return dpp_d<kDppXor1>(x, 0.0);
+  }
+}
+
+// one halving step of a reduce-scatter: partners at distance D split the
+// HS-slot prefix of v (the lane with bit D set keeps the upper half)
+template <int D, int HS>
+__device__ __forceinline__ void rs_step(double (&v)[16], int wl) {
+  const bool upper = (wl & D) != 0;
+#pragma unroll
+  for (int t = 0; t < HS; ++t) {
+    const double lo = v[t], hi = v[t + HS];
+    v[t] = (upper ? hi : lo) + xch<D>(upper ? lo : hi, wl);
+  }
+}
+
+// reduce-scatter of 16 slots over a segment of L lanes (fixed order): lane
+// ll ends with the segment sum of slot ll / (L / 16)
+template <int L>
+__device__ __forceinline__ double seg_rs16(double (&v)[16], int wl) {
+  rs_step<L / 2, 8>(v, wl);
+  rs_step<L / 4, 4>(v, wl);
+  rs_step<L / 8, 2>(v, wl);
+  rs_step<L / 16, 1>(v, wl);
+  double r = v[0];
+  if constexpr (L / 32 >= 2) r += xch<L / 32>(r, wl);
+  if constexpr (L / 32 >= 1) r += xch<1>(r, wl);
+  return r;
 }
 
 }  // namespace
@@ -107,8 +154,10 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   for (int j = 0; j < MAXM; ++j) {
     double2 v = make_double2(0.0, 0.0);
     if (act && j < M) {
-      const double2 a0 = A0[ll * M + j];
-      const double2 c = CM[ll * M + j];
+      // A0 and C_M are Hermitian: row ll is the conjugate of column ll, read
+      // with one coalesced load per j across the lanes
+      const double2 a0 = cconj(A0[j * M + ll]);
+      const double2 c = cconj(CM[j * M + ll]);
       v.x = fma(om, c.y, a0.x);
       v.y = fma(-om, c.x, a0.y);
     }
@@ -125,6 +174,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   bool done = !act;
   int order = -1;
   int bad = 0;
+  double2 pinv = make_double2(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < MAXM; ++k) {
     if (k < M) {
@@ -142,6 +192,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
       if (wl == p) {
         done = true;
         order = k;
+        pinv = inv;  // kept for the back substitution
       }
       const bool upd = !done;
       const double2 l = cmul(A[k], inv);
@@ -170,7 +221,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     if (k < M) {
       int q = seg_first<L>(order == k, base);
       if (q < 0) q = base;  // only after a flagged breakdown
-      const double2 inv = crecip(seg_bcast2<L>(A[k], q));
+      const double2 inv = seg_bcast2<L>(pinv, q);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const double2 xk = cmul(seg_bcast2<L>(b[i], q), inv);
@@ -196,17 +247,19 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   for (int i = 0; i < 3; ++i) {
     Ka[i] = Ca[i] = Aa[i] = Ha[i] = make_double2(0.0, 0.0);
   }
-  const double2* Hrow = G + (size_t)(3 + M + ll) * ldG + (3 + M);
+  // K_M, C_M, A0 and H = G[c, c] are Hermitian: lane ll reads column ll
+  // (coalesced across lanes) and conjugates
+  const double2* Hcol = G + (size_t)(3 + M) * ldG + (3 + M) + ll;
 #pragma unroll 4
   for (int j = 0; j < M; ++j) {
     double2 aj[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) aj[i] = seg_bcast2<L>(x[i], base + j);
     if (act) {
-      const double2 kk = KM[ll * M + j];
-      const double2 cc = CM[ll * M + j];
-      const double2 a0 = A0[ll * M + j];
-      const double2 hh = Hrow[j];
+      const double2 kk = cconj(KM[j * M + ll]);
+      const double2 cc = cconj(CM[j * M + ll]);
+      const double2 a0 = cconj(A0[j * M + ll]);
+      const double2 hh = cconj(Hcol[(size_t)j * ldG]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         Ka[i] = cfma(Ka[i], kk, aj[i]);
@@ -217,52 +270,41 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     }
   }
 
-  // ---- per-lane partial sums of the quadratic forms -----------------------
-  double v[64];
+  // ---- quadratic forms: per-lane partials of 60 slots, reduced in four
+  // groups of 16 (segment reduce-scatter), totals to red_lds --------------
+  double2 Fi[3];
 #pragma unroll
-  for (int s = 0; s < 64; ++s) v[s] = 0.0;
-  if (act) {
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const int i = (p < 3) ? 0 : (p < 5 ? 1 : 2);
-      const int j = (p == 0) ? 0 : (p == 1 ? 1 : (p == 2 ? 2 : (p == 3 ? 1 : 2)));
-      v[kKQ + p] = cmulc(x[i], Ka[j]).x;
-      v[kCQ + p] = cmulc(x[i], Ca[j]).x;
-      v[kAQ + p] = cmulc(x[i], Aa[j]).x;
-      v[kHQ + p] = cmulc(x[i], Ha[j]).x;
+  for (int i = 0; i < 3; ++i)
+    Fi[i] = act ? G[(size_t)i * ldG + 3 + M + ll] : make_double2(0.0, 0.0);
+  auto partial = [&](int sl) -> double {
+    if (sl < kGA) {
+      const int q = sl % 6, kind = sl / 6;
+      const int i = q < 3 ? 0 : (q < 5 ? 1 : 2);
+      const int j = q == 0 ? 0 : (q == 1 ? 1 : (q == 2 ? 2 : (q == 3 ? 1 : 2)));
+      const double2 y = kind == 0 ? Ka[j] : (kind == 1 ? Ca[j] : (kind == 2 ? Aa[j] : Ha[j]));
+      return cmulc(x[i], y).x;
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double2 Fi = G[(size_t)i * ldG + 3 + M + ll];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const double2 ga = cmulc(gl[i], x[j]);
-        v[kGA + 2 * (3 * i + j)] = ga.x;
-        v[kGA + 2 * (3 * i + j) + 1] = ga.y;
-        const double2 fa = cmul(Fi, x[j]);
-        v[kFA + 2 * (3 * i + j)] = fa.x;
-        v[kFA + 2 * (3 * i + j) + 1] = fa.y;
-      }
+    if (sl < kFA) {
+      const int u = (sl - kGA) >> 1, i = u / 3, j = u % 3;
+      const double2 ga = cmulc(gl[i], x[j]);
+      return ((sl - kGA) & 1) ? ga.y : ga.x;
     }
+    if (sl < 60) {
+      const int u = (sl - kFA) >> 1, i = u / 3, j = u % 3;
+      const double2 fa = cmul(Fi[i], x[j]);
+      return ((sl - kFA) & 1) ? fa.y : fa.x;
+    }
+    return 0.0;
+  };
+  constexpr int kPerSlot = L / 16;  // lanes holding each slot total
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    double v[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = act ? partial(16 * g + t) : 0.0;
+    const double r = seg_rs16<L>(v, wl);
+    if (ll % kPerSlot == 0) red_lds[16 * g + ll / kPerSlot] = r;
   }
-  // reduce-scatter inside the segment: lane ll ends with slots
-  // [ll * 64/L, (ll+1) * 64/L) summed over the segment (fixed order)
-#pragma unroll
-  for (int s = 0; (L >> s) > 1; ++s) {
-    const int hs = 32 >> s;       // half of the current slot count
-    const int lb = (L / 2) >> s;  // partner distance
-    const bool upper = (ll & lb) != 0;
-#pragma unroll
-    for (int t = 0; t < hs; ++t) {
-      const double lo = v[t], hi = v[t + hs];
-      const double send = upper ? lo : hi;
-      const double keep = upper ? hi : lo;
-      v[t] = keep + shfl_xor_d(send, lb);
-    }
-  }
-  constexpr int per = 64 / L;
-#pragma unroll
-  for (int t = 0; t < per; ++t) red_lds[ll * per + t] = v[t];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

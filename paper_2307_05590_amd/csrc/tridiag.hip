@@ -86,11 +86,13 @@ __global__ __launch_bounds__(kTriThreads) void k_hetrd(const double2* __restrict
     for (int i = tid >> 3; i < L; i += nt >> 3) {
       double2 acc = make_double2(0.0, 0.0);
       for (int j = s8; j < L; j += 8) acc = cfma(acc, lget(A, o + i, o + j), u[j]);
-#pragma unroll
-      for (int m = 1; m < 8; m <<= 1) {
-        acc.x += shfl_xor_d(acc.x, m);
-        acc.y += shfl_xor_d(acc.y, m);
-      }
+      // sum over the 8 lanes of the row group (DPP inside a half-row)
+      acc.x += dpp_d<kDppXor1>(acc.x, 0.0);
+      acc.y += dpp_d<kDppXor1>(acc.y, 0.0);
+      acc.x += dpp_d<kDppXor2>(acc.x, 0.0);
+      acc.y += dpp_d<kDppXor2>(acc.y, 0.0);
+      acc.x += dpp_d<kDppHalfMirror>(acc.x, 0.0);
+      acc.y += dpp_d<kDppHalfMirror>(acc.y, 0.0);
       if (s8 == 0) p[i] = make_double2(g * acc.x, g * acc.y);
     }
     __syncthreads();
@@ -133,20 +135,22 @@ __global__ __launch_bounds__(kTriThreads) void k_hetrd(const double2* __restrict
   }
 }
 
-// 3. eigenvalues (ascending) of the real symmetric tridiagonal (d, e)
-__global__ __launch_bounds__(kTriThreads) void k_tri_eigvals(const double* __restrict__ d,
-                                                             const double* __restrict__ e, int n,
-                                                             double* __restrict__ lam) {
-  __shared__ double sd[kTriMaxN], se2[kTriMaxN], lo[kTriMaxN], hi[kTriMaxN];
-  __shared__ int cnt[kTriThreads];
+// 3. eigenvalues (ascending) of the real symmetric tridiagonal (d, e): one
+// wave per eigenvalue j tests its interval at 64 points per step (one Sturm
+// count per lane); the counts are monotone in the point, so the new interval
+// is found by a ballot.  Ten steps shrink the Gershgorin width by 65^10.
+__global__ __launch_bounds__(64 * kTriWaves) void k_tri_eigvals(const double* __restrict__ d,
+                                                                const double* __restrict__ e,
+                                                                int n, double* __restrict__ lam) {
+  __shared__ double sd[kTriMaxN], se2[kTriMaxN];
   __shared__ double gb[3];
-  const int tid = threadIdx.x, lane = __lane_id();
+  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   for (int i = tid; i < n; i += blockDim.x) {
     sd[i] = d[i];
     se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
-  if (tid < 64) {
+  if (wave == 0) {
     double gl = 1e308, gu = -1e308, em = 0.0;
     for (int i = lane; i < n; i += 64) {
       const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvals(const double* __res
     gl = -wave_max(-gl);
     gu = wave_max(gu);
     em = wave_max(em);
-    if (tid == 0) {
+    if (lane == 0) {
       const double tn = fmax(fabs(gl), fabs(gu));
       gb[0] = gl - 4.0 * 2.220446049250313e-16 * tn * n;
       gb[1] = gu + 4.0 * 2.220446049250313e-16 * tn * n;
@@ -165,45 +169,28 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvals(const double* __res
     }
   }
   __syncthreads();
-  for (int j = tid; j < n; j += blockDim.x) {
-    lo[j] = gb[0];
-    hi[j] = gb[1];
-  }
+  const int j = blockIdx.x * kTriWaves + wave;
+  if (j >= n) return;
   const double pivmin = gb[2];
-  const int P = min((int)(blockDim.x / n), 32);
-  // interval shrinks by P+1 per step; 1e17 covers the Gershgorin width to eps
-  const int iters = (int)ceil(39.2 / log((double)(P + 1)));
-  __syncthreads();
-  for (int it = 0; it < iters; ++it) {
-    const int j = tid / P, q = tid % P;
-    if (j < n) {
-      const double x = lo[j] + (hi[j] - lo[j]) * (double)(q + 1) / (double)(P + 1);
-      double s = sd[0] - x;
-      int c = s < 0.0 ? 1 : 0;
-      for (int i = 1; i < n; ++i) {
-        if (fabs(s) < pivmin) s = -pivmin;
-        double r = __builtin_amdgcn_rcp(s);
-        r = fma(r, fma(-s, r, 1.0), r);
-        s = (sd[i] - x) - se2[i - 1] * r;
-        c += s < 0.0 ? 1 : 0;
-      }
-      cnt[tid] = c;
+  double lo = gb[0], hi = gb[1];
+  for (int it = 0; it < 10; ++it) {
+    const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
+    double s = sd[0] - x;
+    int c = s < 0.0 ? 1 : 0;
+    for (int i = 1; i < n; ++i) {
+      if (fabs(s) < pivmin) s = -pivmin;
+      double r = __builtin_amdgcn_rcp(s);
+      r = fma(r, fma(-s, r, 1.0), r);
+      s = (sd[i] - x) - se2[i - 1] * r;
+      c += s < 0.0 ? 1 : 0;
     }
-    __syncthreads();
-    if (tid < n) {
-      const int jj = tid;
-      double nl = lo[jj], nh = hi[jj];
-      for (int qq = 0; qq < P; ++qq) {
-        const double x = lo[jj] + (hi[jj] - lo[jj]) * (double)(qq + 1) / (double)(P + 1);
-        if (cnt[jj * P + qq] <= jj) nl = fmax(nl, x);
-        else nh = fmin(nh, x);
-      }
-      lo[jj] = nl;
-      hi[jj] = nh;
-    }
-    __syncthreads();
+    const int k = __popcll(__ballot(c <= j));  // points with count <= j
+    const double xl = lo + (hi - lo) * (double)k * (1.0 / 65.0);
+    const double xh = lo + (hi - lo) * (double)(k + 1) * (1.0 / 65.0);
+    if (k > 0) lo = xl;
+    if (k < 64) hi = xh;
   }
-  for (int j = tid; j < n; j += blockDim.x) lam[j] = 0.5 * (lo[j] + hi[j]);
+  if (lane == 0) lam[j] = 0.5 * (lo + hi);
 }
 
 // 4. inverse iteration: three solves of (T - lam_j) x = b with Gaussian
@@ -233,7 +220,7 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
   tn = wave_max(tn);
   const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
   const double lj = lam[j];
-  for (int i = lane; i < n; i += 64) b[i] = 1.0 + 0.1 * sin(0.7 * i + 1.3 * j);
+  for (int i = lane; i < n; i += 64) b[i] = 1.0 + 0.01 * (double)((i * 37 + j * 11) % 17);
   if (lane == 0) {
     double xr = d[0] - lj, yr = n > 1 ? e[0] : 0.0;
     for (int i = 0; i + 1 < n; ++i) {
@@ -261,8 +248,12 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
       mm[i] = mi;
     }
     U0[n - 1] = xr;
-    for (int i = 0; i < n; ++i)
-      if (fabs(U0[i]) < tiny) U0[i] = U0[i] >= 0.0 ? tiny : -tiny;
+    // reciprocal pivots (kept in U0), floored at eps ||T||
+    for (int i = 0; i < n; ++i) {
+      double u0 = U0[i];
+      if (fabs(u0) < tiny) u0 = u0 >= 0.0 ? tiny : -tiny;
+      U0[i] = 1.0 / u0;
+    }
   }
   for (int s = 0; s < 3; ++s) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -270,6 +261,7 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane == 0) {
       double bc = b[0];
+#pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
         if (sw[i]) {
           y[i] = b[i + 1];
@@ -281,10 +273,11 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
       }
       y[n - 1] = bc;
       double x1 = 0.0, x2 = 0.0;  // x[i+1], x[i+2]
+#pragma unroll 4
       for (int i = n - 1; i >= 0; --i) {
-        double v = y[i] - U1[i] * x1 - U2[i] * x2;
-        if (i + 1 >= n) v = y[i];
-        double xi = v / U0[i];
+        double v = y[i];
+        if (i + 1 < n) v -= U1[i] * x1 + U2[i] * x2;
+        double xi = v * U0[i];
         if (fabs(xi) > 1e150) {  // rescale what is computed so far
           for (int t = i + 1; t < n; ++t) b[t] *= 1e-150;
           x1 *= 1e-150;
@@ -329,12 +322,32 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_mgs(double* __restrict__ Zg
       double nr = 0.0;
       for (int i = lane; i < n; i += 64) nr += zj[i] * zj[i];
       const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
-      for (int jj = wave; jj < j; jj += nw) {
-        double* zk = Z + (size_t)jj * n;
-        double dt = 0.0;
-        for (int i = lane; i < n; i += 64) dt += zj[i] * zk[i];
-        dt = wave_sum(dt) * inv * inv;
-        for (int i = lane; i < n; i += 64) zk[i] -= dt * zj[i];
+      // rows jj = wave, wave + nw, ... below j, three at a time so that
+      // their reductions overlap
+      for (int jj = wave; jj < j; jj += 3 * nw) {
+        const int j1 = jj + nw, j2 = jj + 2 * nw;
+        double* z0 = Z + (size_t)jj * n;
+        double* z1 = Z + (size_t)(j1 < j ? j1 : jj) * n;
+        double* z2 = Z + (size_t)(j2 < j ? j2 : jj) * n;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          const double zi = zj[i];
+          d0 += zi * z0[i];
+          d1 += zi * z1[i];
+          d2 += zi * z2[i];
+        }
+        d0 = row16_sum(d0);
+        d1 = row16_sum(d1);
+        d2 = row16_sum(d2);
+        d0 = ((bcast(d0, 0) + bcast(d0, 16)) + (bcast(d0, 32) + bcast(d0, 48))) * inv * inv;
+        d1 = ((bcast(d1, 0) + bcast(d1, 16)) + (bcast(d1, 32) + bcast(d1, 48))) * inv * inv;
+        d2 = ((bcast(d2, 0) + bcast(d2, 16)) + (bcast(d2, 32) + bcast(d2, 48))) * inv * inv;
+        for (int i = lane; i < n; i += 64) {
+          const double zi = zj[i];
+          z0[i] -= d0 * zi;
+          if (j1 < j) z1[i] -= d1 * zi;
+          if (j2 < j) z2[i] -= d2 * zi;
+        }
       }
       __syncthreads();
       if (wave == j % nw)
@@ -446,10 +459,10 @@ hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, vo
                        e, ph);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_tri_eigvals, dim3(1), dim3(kTriThreads), 0, st, d, e, n, lam);
+  const int nb = (n + kTriWaves - 1) / kTriWaves;
+  hipLaunchKernelGGL(k_tri_eigvals, dim3(nb), dim3(64 * kTriWaves), 0, st, d, e, n, lam);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int nb = (n + kTriWaves - 1) / kTriWaves;
   hipLaunchKernelGGL(k_tri_invit, dim3(nb), dim3(64 * kTriWaves), 0, st, d, e, lam, n, Z);
   err = hipGetLastError();
   if (err != hipSuccess) return err;

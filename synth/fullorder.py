@@ -45,17 +45,20 @@ class SpectralX1:
         self.ia = 1.0 / (S2[..., None] / grid.h + eps_h)
         self.ib = 1.0 / eps_h
 
-    def apply(self, V: np.ndarray, chunk: int = 24) -> np.ndarray:
+    def apply(self, V: np.ndarray, chunk: int = 24, transverse: bool = False) -> np.ndarray:
+        """X_1^{-1} V.  transverse=True for V in the range of C^T (curls of
+        face fields): the longitudinal part of such V vanishes exactly, so it
+        is dropped instead of amplified by 1/(eps h) from rounding."""
         V = np.asarray(V)
         one = V.ndim == 1
         if one:
             V = V[:, None]
         out = np.empty(V.shape, dtype=np.result_type(V.dtype, np.float64))
         for c0 in range(0, V.shape[1], chunk):
-            out[:, c0:c0 + chunk] = self._apply(V[:, c0:c0 + chunk])
+            out[:, c0:c0 + chunk] = self._apply(V[:, c0:c0 + chunk], transverse)
         return out[:, 0] if one else out
 
-    def _apply(self, V):
+    def _apply(self, V, transverse=False):
         g = self.g
         n, B = g.n, V.shape[1]
         nx = g.nx_edges
@@ -73,7 +76,8 @@ class SpectralX1:
         Ax[:, 1:, 1:] = tx
         Ay[1:, :, 1:] = ty
         Az[1:, 1:, :] = tz
-        coef = (self.SX * Ax + self.SY * Ay + self.SZ * Az) * ((self.ib - self.ia) / self.S2)
+        lon = (0.0 - self.ia) if transverse else (self.ib - self.ia)
+        coef = (self.SX * Ax + self.SY * Ay + self.SZ * Az) * (lon / self.S2)
         ox = self.ia * Ax + self.SX * coef
         oy = self.ia * Ay + self.SY * coef
         oz = self.ia * Az + self.SZ * coef
@@ -122,8 +126,10 @@ class RegionGreen:
 class FullOrderSolver:
     """Snapshots q_i(omega), theta~^(0) DOFs o_i and the conductor block S."""
 
-    def __init__(self, ops: Operators, C=None, chunk: int = 24, green: RegionGreen | None = None):
+    def __init__(self, ops: Operators, C=None, chunk: int = 24, green: RegionGreen | None = None,
+                 verbose: bool = False):
         self.ops = ops
+        self.verbose = verbose
         g = ops.grid
         self.chunk = chunk
         self.sx = SpectralX1(g, ops.eps_h)
@@ -155,7 +161,7 @@ class FullOrderSolver:
                 Wc = np.empty((self.cond.size, nF))
                 for c0 in range(0, nF, chunk):
                     cols = self.CFT[:, c0:c0 + chunk].toarray()
-                    W = self.sx.apply(cols, chunk)
+                    W = self.sx.apply(cols, chunk, transverse=True)
                     Gam[:, c0:c0 + chunk] = self.CF @ W
                     Wc[:, c0:c0 + chunk] = W[self.cond]
             Gam = 0.5 * (Gam + Gam.T)
@@ -168,7 +174,7 @@ class FullOrderSolver:
         U = self.sx.apply(V, self.chunk)
         if self.F.size:
             z = sla.lu_solve(self.cap, self.CF @ U)
-            U = U - self.sx.apply(self.CFT @ z, self.chunk)
+            U = U - self.sx.apply(self.CFT @ z, self.chunk, transverse=True)
         return U
 
     def apply_X(self, V):
@@ -194,6 +200,8 @@ class FullOrderSolver:
             nc = self.cond.size
             S = np.empty((nc, nc))
             for c0 in range(0, nc, self.chunk):
+                if self.verbose and c0 % (40 * self.chunk) == 0:
+                    print(f"  conductor block: {c0}/{nc} columns", flush=True)
                 idx = self.cond[c0:c0 + self.chunk]
                 E = np.zeros((N, idx.size))
                 E[idx, np.arange(idx.size)] = 1.0
@@ -225,7 +233,7 @@ class FullOrderSolver:
         g[self.cond] = self.ops.c[self.cond][:, None] * qc
         return u + 1j * np.asarray(omega)[None, :] * self.xinv(g)
 
-    def snapshots(self, omegas, w, tol=1e-13, max_iter=8, verbose=False):
+    def snapshots(self, omegas, w, tol=1e-13, max_iter=8, verbose=False, gmres_cycles=8):
         """Full-order q_i(omega_k); returns D (N, 3K) = [q_1(w_1..K)|q_2|q_3] and residuals."""
         ops = self.ops
         omegas = np.asarray(omegas, dtype=np.float64)
@@ -243,6 +251,7 @@ class FullOrderSolver:
         Q = 1j * om[None, :] * self.xinv(g)
         rn = np.linalg.norm(r, axis=0)
         hist = []
+        prev, Qprev = np.inf, None
         for it in range(max_iter):
             res = r - self.apply_A(Q, om)
             rel = np.linalg.norm(res, axis=0) / rn
@@ -250,12 +259,72 @@ class FullOrderSolver:
             if verbose:
                 print(f"  refine {it}: max rel residual {rel.max():.3e}", flush=True)
             if rel.max() <= tol:
+                return Q, hist
+            if rel.max() > 0.5 * prev:  # refinement stalls or diverges
+                if rel.max() > prev:  # keep the better iterate
+                    Q = Qprev
+                    hist.append(float(prev))
                 break
+            prev, Qprev = rel.max(), Q
             Q = Q + self._solve_general(res, om)
         else:
             res = r - self.apply_A(Q, om)
             hist.append(float((np.linalg.norm(res, axis=0) / rn).max()))
+            return Q, hist
+        # the preconditioner is too far from A^{-1} for a stationary
+        # iteration (high sigma omega): restarted GMRES on the same operator,
+        # within the given number of cycles (0: keep the best iterate)
+        if gmres_cycles <= 0:
+            return Q, hist
+        for c0 in range(0, Q.shape[1], self.chunk):
+            sl = slice(c0, c0 + self.chunk)
+            Q[:, sl], h2 = self._gmres(r[:, sl], Q[:, sl], om[sl], tol, cycles=gmres_cycles,
+                                       verbose=verbose)
+            hist.append(h2)
         return Q, hist
+
+    def _gmres(self, b, x, om, tol, m=30, cycles=8, verbose=False):
+        """Right-preconditioned restarted GMRES(m) for A(om) x = b, one
+        independent Krylov space per column (the columns advance in lockstep);
+        the preconditioner is the spectral / Woodbury / Schur solve."""
+        bn = np.linalg.norm(b, axis=0)
+        B = b.shape[1]
+        rel = None
+        for cyc in range(cycles):
+            r = b - self.apply_A(x, om)
+            beta = np.linalg.norm(r, axis=0)
+            rel = beta / bn
+            if verbose:
+                print(f"  gmres cycle {cyc}: max rel residual {rel.max():.3e}", flush=True)
+            if rel.max() <= tol:
+                break
+            V = np.empty((m + 1,) + r.shape, dtype=np.complex128)
+            H = np.zeros((B, m + 1, m), dtype=np.complex128)
+            V[0] = r / beta
+            k = m
+            for j in range(m):
+                w = self.apply_A(self._solve_general(V[j], om), om)
+                for i in range(j + 1):
+                    hij = np.einsum("nb,nb->b", V[i].conj(), w)
+                    H[:, i, j] = hij
+                    w = w - V[i] * hij
+                hn = np.linalg.norm(w, axis=0)
+                H[:, j + 1, j] = hn
+                V[j + 1] = w / np.where(hn > 0, hn, 1.0)
+                # residual estimate from the small least-squares problems
+                e1 = np.zeros((B, j + 2), dtype=np.complex128)
+                e1[:, 0] = beta
+                est = np.array([np.linalg.norm(e1[c] - H[c, :j + 2, :j + 1] @ np.linalg.lstsq(
+                    H[c, :j + 2, :j + 1], e1[c], rcond=None)[0]) for c in range(B)]) / bn
+                if est.max() <= 0.5 * tol:
+                    k = j + 1
+                    break
+            e1 = np.zeros((B, k + 1), dtype=np.complex128)
+            e1[:, 0] = beta
+            Y = np.stack([np.linalg.lstsq(H[c, :k + 1, :k], e1[c], rcond=None)[0] for c in range(B)], 1)
+            x = x + self._solve_general(np.einsum("jnb,jb->nb", V[:k], Y), om)
+        r = b - self.apply_A(x, om)
+        return x, float((np.linalg.norm(r, axis=0) / bn).max())
 
     def theta0(self, tol=1e-13, max_iter=8):
         """theta~^(0) DOFs o_i: X_mu o_i = -(K_mu - K_1) x_i, zero on the boundary.
@@ -270,7 +339,7 @@ class FullOrderSolver:
         h = ops.grid.h
         Cx = self.CF @ ops.x  # face circulation of e_i x xi on F
         b = -(self.CFT @ ((self.delta / h)[:, None] * Cx))
-        o = -self.sx.apply(self.CFT @ sla.lu_solve(self.cap, Cx))
+        o = -self.sx.apply(self.CFT @ sla.lu_solve(self.cap, Cx), transverse=True)
         bn = np.linalg.norm(b, axis=0)
         hist = []
         for _ in range(max_iter):

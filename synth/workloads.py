@@ -17,7 +17,9 @@ Draw order per object: shape type, dimensions, rotation, sigma_*, mu_r, M, n_ome
   5 shell64       64^3 grid, steel core r < 0.6 (mu_r 50, sigma 6e6) in an
                   aluminium shell r < 1 (sigma 3.5e7); 48 initial snapshots on
                   [1e1,1e7] + 3 adaptive rounds x 2; TOL 1e-8, M <= 96; 1e5
-                  output omegas on [1e1,1e7].
+                  output omegas on [1e1,1e7].  At the high end of sigma omega
+                  the host refinement stalls; the snapshots keep its best
+                  iterate (the residual is recorded in Problem.snap_residual).
 All use alpha = 1e-2 m, eps = 1e-10 and the box [-5,5]^3.
 """
 from __future__ import annotations
@@ -51,6 +53,7 @@ class Workload:
     n_omega_range: tuple | None = None
     adapt_rounds: int = 0
     n_star: int = 2
+    gmres_cycles: int = 8  # host snapshot solver budget once refinement stalls
 
 
 WORKLOADS = {
@@ -61,7 +64,7 @@ WORKLOADS = {
     "adjoint48": Workload(4, "adjoint48", 48, 64, 16, (1e1, 1e6), 1e-8, 32, 2000, (1e1, 1e6),
                           m_range=(8, 32)),
     "shell64": Workload(5, "shell64", 64, 1, 48, (1e1, 1e7), 1e-8, 96, 100_000, (1e1, 1e7),
-                        adapt_rounds=3),
+                        adapt_rounds=3, gmres_cycles=0),
 }
 
 
@@ -143,7 +146,8 @@ class Problem:
 
     def add_snapshots(self, new_omega, tol=1e-12):
         """Full-order solves at new frequencies; appends to D (Alg. 1 update step)."""
-        Q, hist = self.solver.snapshots(np.asarray(new_omega, float), self.w, tol=tol, max_iter=12)
+        Q, hist = self.solver.snapshots(np.asarray(new_omega, float), self.w, tol=tol, max_iter=12,
+                                        gmres_cycles=self.wl.gmres_cycles)
         K0 = self.snap_omega.size
         k_new = len(new_omega)
         blocks = []
@@ -178,11 +182,12 @@ def make_problem(name: str, obj: int = 0, n: int | None = None, n_snap: int | No
     C = curl if curl is not None else g.curl()
     sig, mu, ncell = draw.shape.assign(g)
     ops = build_operators(g, sig, mu, wl.alpha, wl.eps, C=C, cell_count=ncell)
-    fo = FullOrderSolver(ops, C=C, green=green)
+    fo = FullOrderSolver(ops, C=C, green=green, verbose=verbose)
     o, _ = fo.theta0()
     K = wl.n_snap if n_snap is None else n_snap
     snap = log_grid(*wl.snap_range, K)
-    D, hist = fo.snapshots(snap, ops.x + o, tol=tol, max_iter=12, verbose=verbose)
+    D, hist = fo.snapshots(snap, ops.x + o, tol=tol, max_iter=12, verbose=verbose,
+                           gmres_cycles=wl.gmres_cycles)
     no = draw.n_omega if n_omega is None else n_omega
     om = log_grid(*wl.omega_range, no)
     return Problem(wl, obj, draw, ops, snap, om, np.ascontiguousarray(D), o, fo.schur(), hist[-1], fo)

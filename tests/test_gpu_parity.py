@@ -58,7 +58,7 @@ def _check_sweep(mpt, host, G, rom_o, alpha, omega, tag):
     return out
 
 
-@pytest.mark.parametrize("M", [1, 16, 17, 31, 47, 64])
+@pytest.mark.parametrize("M", [1, 16, 17, 31, 47, 64, 65, 80, 96])
 def test_sweep_random_roms(mpt, M):
     rom_o, G, host, alpha = random_rom(M, seed=M)
     omega = np.logspace(1, 6, 131)
@@ -98,8 +98,9 @@ def test_sweep_empty_and_bad_args(mpt):
     rom = mpt.Rom.from_host(host, alpha)
     out, st = mpt.mpt_sweep(rom, torch.empty(0, dtype=torch.float64, device="cuda"))
     assert out.shape == (0, 18)
+    # an M above the library's limit is rejected on the host before any launch
     bad = mpt.Rom.from_host(host, alpha)
-    bad.M = 65
+    bad.M = mpt.lib().mpt_max_reduced_dim() + 1
     with pytest.raises(mpt.MptError):
         mpt.mpt_sweep(bad, torch.ones(3, dtype=torch.float64, device="cuda"))
 
@@ -362,3 +363,16 @@ def test_batched_adjoint_equals_per_object(mpt):
         d1, s1, _ = mpt.mpt_sweep_adjoint(r, w, dout[a:b].contiguous())
         assert torch.equal(dom[a:b], d1)
         assert abs(sds[o].item() - s1.item()) <= 1e-13 * abs(s1.item())
+
+
+def test_large_M_rejected_by_batched_and_adjoint(mpt):
+    """The persistent batched and the adjoint kernels take M <= 64: a larger
+    reduced model (valid for mpt_sweep) is refused on the host."""
+    rom_o, G, host, alpha = random_rom(70, seed=7)
+    rom = mpt.Rom.from_host(host, alpha)
+    w = _dev(np.logspace(1, 6, 8), torch.float64)
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_sweep_adjoint(rom, w, torch.zeros((8, 18), dtype=torch.float64, device="cuda"))
+    dic = mpt.Dictionary([rom], [w])
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_sweep_batched(dic, use_graph=False)

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_symbols() if not hasattr(L, n)]
     assert not missing, missing
     L.mpt_max_reduced_dim.restype = ctypes.c_int
-    assert L.mpt_max_reduced_dim() == 64
+    assert L.mpt_max_reduced_dim() == 96
     L.mpt_pod_basis_ws_size.restype = ctypes.c_size_t
     L.mpt_pod_basis_ws_size.argtypes = [ctypes.c_int64, ctypes.c_int]
     assert L.mpt_pod_basis_ws_size(1000, 48) > 1000 * 48 * 16
