@@ -376,3 +376,64 @@ def test_large_M_rejected_by_batched_and_adjoint(mpt):
     dic = mpt.Dictionary([rom], [w])
     with pytest.raises(mpt.MptError):
         mpt.mpt_sweep_batched(dic, use_graph=False)
+
+
+def test_full_size_ellipsoid48_sampled(mpt):
+    """The 48^3 workload at its full size (N = 318,096, 96 snapshot columns,
+    M <= 48, 10^4 output frequencies) in the launch configuration the
+    benchmark times; the oracle (its own LAPACK SVD, projection and residual
+    Gram, per-frequency solves, mesh sums) checks a sample of the outputs."""
+    from synth import make_problem
+
+    p = make_problem("ellipsoid48")
+    ops = p.ops
+    tol, cap = p.wl.tol_sigma, p.wl.m_cap
+    print(f"ellipsoid48: N={ops.N} D={p.D.shape} residual={p.snap_residual:.1e}", flush=True)
+    U, sig, M = mpt.mpt_pod_basis(_dev(p.D, torch.complex128), tol, cap)
+    rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
+                          _dev(p.w, torch.float64), _dev(p.o, torch.float64),
+                          _dev(ops.vol, torch.float64), ops.alpha, U,
+                          _dev(ops.cond_idx, torch.int32), _dev(p.S, torch.float64))
+    omega_d = _dev(p.omega, torch.float64)
+    out, st = mpt.mpt_sweep(rom, omega_d)
+    new, lam, Lmax = mpt.mpt_select_snapshots(omega_d, out, _dev(np.sort(p.snap_omega),
+                                                                 torch.float64), 2)
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0
+    out = out.cpu().numpy()
+    # oracle
+    from oracle.grid import FullOrder
+    fo = FullOrder(ops.grid.n, ops.sigma_e, ops.mu_f, ops.alpha, ops.eps)
+    U_o, s_o, M_o = R.pod_basis(p.D, tol, cap)
+    assert M == M_o
+    s_g = sig.cpu().numpy()
+    k = int(np.sum(s_o / s_o[0] >= 1e-10))
+    assert np.all(np.abs(s_g[:k] - s_o[:k]) <= 1e-9 * s_o[:k])
+    rom_o, G, host = oracle_rom(fo, U_o, p.w, p.o, p.S, ops.cond_idx)
+    sel = np.arange(0, p.omega.size, 250)
+    ref, a_o = R.sweep(rom_o, p.omega[sel], G, ops.alpha)
+    sc = term_scales(ref, p.omega[sel], rom_o["N0"], rom_o["E"], ops.alpha)
+    eR, eI = tensor_errors(out[sel, :12], ref[:, :12], sc)
+    # the GPU and the oracle solve in two different (equally valid) bases of
+    # the same subspace, so where the reduced system is ill-conditioned their
+    # backward-stable solves agree to ~eps cond(A^M(w)) only
+    A0o = rom_o["KM"] + fo.eps_h * rom_o["UhU"]
+    kap = np.array([np.linalg.cond(A0o - 1j * w_ * rom_o["CM"]) for w_ in p.omega[sel]])
+    bound = 1e-10 + 64 * 2.2e-16 * kap
+    print(f"full size sampled: R~ {eR.max():.2e} I {eI.max():.2e}; cond max {kap.max():.2e}; "
+          f"worst R~ err / (eps cond) {np.max(eR / (2.2e-16 * kap)):.2e} at w={p.omega[sel][np.argmax(eR)]:.3e}",
+          flush=True)
+    assert np.all(eR <= bound) and np.all(eI <= bound)
+    # the integral-method analogue (explicit mesh sums) at a few of them
+    sub = sel[::8]
+    Rt, I = R.tensors_mesh(fo, U_o, R.reduced_solve(rom_o, p.omega[sub]), p.omega[sub], p.w,
+                           rom_o["N0"])
+    im = np.concatenate([R.pack(Rt), R.pack(I)], 1)
+    eR, eI = tensor_errors(out[sub, :12], im, term_scales(im, p.omega[sub], rom_o["N0"],
+                                                         rom_o["E"], ops.alpha))
+    assert np.all(eR <= bound[::8]) and np.all(eI <= bound[::8])
+    # certificates against the oracle's own, within the G-form rounding floor
+    fl = delta_floor(G, a_o, p.omega[sel], ops.alpha)
+    d = np.abs(out[sel, 12:] - ref[:, 12:])
+    print(f"full size Delta err / floor max {np.max(d / (2.2e-16 * fl)):.2e}", flush=True)
+    assert np.all(d <= 1e-8 * np.abs(ref[:, 12:]) + 64 * 2.2e-16 * fl)
