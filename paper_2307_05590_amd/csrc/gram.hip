@@ -24,33 +24,56 @@ __device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
 // One workgroup owns every output tile of its chunk of rows, so each row is
 // read from HBM once and shared by the waves through L1/L2.  The tiles (16x16)
 // of up to two products - P1 = A^H B (all tiles, or I <= J when A == B) and
-// P2 = A^H A (I <= J) - are split into contiguous runs over the waves; a wave
-// keeps its run in MFMA accumulators and reloads an A fragment only when the
-// tile row changes.  Per-chunk partials are summed in a fixed order
-// (deterministic).
+// P2 = A^H A (I <= J) - are grouped in register blocks of RI x RJ tiles; a
+// wave works one block at a time: per step of four rows it loads RI + RJ
+// fragments (clamped, branch-free) and issues 4 RI RJ MFMAs.  Blocks of a
+// Hermitian product that lie entirely below the diagonal are skipped; the
+// partial sums of every chunk are reduced in a fixed order (deterministic).
 constexpr int kGramMaxChunks = 512;
 
 struct GramPlan {
-  int TI, TJ, t1, t2, T;  // tile rows / cols of P1, tiles of P1, P2, total
+  int TI, TJ, RI, RJ, nb1, nb2, waves;
   bool herm1;
-  int waves, maxt;
   int64_t chunks, rows;
 };
 
-static int herm_tiles(int TI) { return TI * (TI + 1) / 2; }
+// blocks of a TI x TJ tile grid in RI x RJ blocks; herm: only blocks holding
+// a tile with I <= J
+__host__ __device__ inline int gram_blocks(int TI, int TJ, int RI, int RJ, bool herm) {
+  const int BI = (TI + RI - 1) / RI, BJ = (TJ + RJ - 1) / RJ;
+  int c = 0;
+  for (int bi = 0; bi < BI; ++bi)
+    for (int bj = 0; bj < BJ; ++bj)
+      if (!herm || bi * RI <= min(TJ - 1, bj * RJ + RJ - 1)) ++c;
+  return c;
+}
+__device__ inline void gram_block_of(int b, int TI, int TJ, int RI, int RJ, bool herm, int& bi,
+                                     int& bj) {
+  const int BI = (TI + RI - 1) / RI, BJ = (TJ + RJ - 1) / RJ;
+  for (bi = 0; bi < BI; ++bi)
+    for (bj = 0; bj < BJ; ++bj)
+      if (!herm || bi * RI <= min(TJ - 1, bj * RJ + RJ - 1)) {
+        if (b == 0) return;
+        --b;
+      }
+}
 
 static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
   GramPlan g;
   g.TI = (m + 15) / 16;
   g.TJ = (n + 15) / 16;
   g.herm1 = herm1;
-  g.t1 = herm1 ? herm_tiles(g.TI) : g.TI * g.TJ;
-  g.t2 = dual ? herm_tiles(g.TI) : 0;
-  g.T = g.t1 + g.t2;
-  // 4 waves with up to 8 tiles each, else 8 waves with up to 10 (m <= 192)
-  g.waves = g.T <= 32 ? 4 : 8;
-  const int per = (g.T + g.waves - 1) / g.waves;
-  g.maxt = g.waves == 8 ? 10 : (per <= 2 ? 2 : (per <= 4 ? 4 : (per <= 6 ? 6 : 8)));
+  if (g.TI <= 3 && g.TJ <= 3) {
+    g.RI = 1;
+    g.RJ = dual ? 3 : g.TJ;
+  } else {
+    g.RI = 2;
+    g.RJ = 2;
+  }
+  g.nb1 = gram_blocks(g.TI, g.TJ, g.RI, g.RJ, herm1);
+  g.nb2 = dual ? gram_blocks(g.TI, g.TI, g.RI, g.RJ, true) : 0;
+  const int nb = g.nb1 + g.nb2;
+  g.waves = nb < 16 ? nb : 16;  // one block per wave where possible
   int64_t ch = (N + 15) / 16;
   if (ch > kGramMaxChunks) ch = kGramMaxChunks;
   if (ch < 1) ch = 1;
@@ -59,111 +82,92 @@ static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
   return g;
 }
 
-// tile index t -> (I, J) of the list: t < t1: P1 tiles, else P2 tiles
-__device__ __forceinline__ void tile_of(int t, int TI, int TJ, int t1, bool herm1, int& I, int& J,
-                                        int& which) {
-  which = t < t1 ? 0 : 1;
-  int u = t < t1 ? t : t - t1;
-  if (which == 0 && !herm1) {
-    I = u / TJ;
-    J = u % TJ;
-    return;
-  }
-  // upper triangle, row-major: row I holds TI - I tiles
-  I = 0;
-  while (u >= TI - I) {
-    u -= TI - I;
-    ++I;
-  }
-  J = I + u;
-}
-
-template <int MAXT, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
+template <int RI, int RJ>
+__global__ __launch_bounds__(1024) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
                                                      const double2* __restrict__ B, int64_t ldb,
                                                      int64_t N, int m, int n, int64_t rows,
-                                                     int herm1, int t1, int T,
+                                                     int herm1, int nb1, int nb2,
                                                      double2* __restrict__ part1,
                                                      double2* __restrict__ part2) {
   const int lane = __lane_id();
-  // wave-uniform values in scalar registers, so the tile loop branches on SCC
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16;
-  const int tb = (wave * T) / nw, te = ((wave + 1) * T) / nw;  // this wave's run
-  const int nt = te - tb;
-  int tI[MAXT], tJ[MAXT], tw[MAXT];
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    tI[t] = tJ[t] = tw[t] = 0;
-    if (t < nt) tile_of(tb + t, TI, TJ, t1, herm1 != 0, tI[t], tJ[t], tw[t]);
-    tI[t] = __builtin_amdgcn_readfirstlane(tI[t]);
-    tJ[t] = __builtin_amdgcn_readfirstlane(tJ[t]);
-    tw[t] = __builtin_amdgcn_readfirstlane(tw[t]);
-  }
-  double4_t accr[MAXT], acci[MAXT];
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    accr[t] = double4_t{0, 0, 0, 0};
-    acci[t] = double4_t{0, 0, 0, 0};
-  }
   const int64_t r0 = (int64_t)blockIdx.x * rows;
   const int64_t r1 = min(N, r0 + rows);
   const int cl = lane & 15;
-  // loads are clamped into range and masked with selects (no branches), so
-  // the compiler can issue every fragment load of a step back to back
   const double2 z2 = make_double2(0.0, 0.0);
-  for (int64_t k0 = r0; k0 < r1; k0 += 4) {
-    const int64_t row = k0 + (lane >> 4);
-    const bool rok = row < r1;
-    const int64_t rowc = rok ? row : r1 - 1;
-    const double2* ar = A + rowc * lda;
-    const double2* br = B + rowc * ldb;
-    double2 fa[MAXT], fb[MAXT];
-#pragma unroll
-    for (int t = 0; t < MAXT; ++t) {  // all loads of the step first
-      fa[t] = fb[t] = z2;
-      if (t < nt) {
-        const int I = tI[t], J = tJ[t];
-        if (t == 0 || I != tI[t > 0 ? t - 1 : 0]) {  // wave-uniform
-          const int c = I * 16 + cl;
-          const double2 x = ar[c < m ? c : m - 1];
-          fa[t] = (rok && c < m) ? x : z2;
-        } else {
-          fa[t] = fa[t > 0 ? t - 1 : 0];
-        }
-        const int c = J * 16 + cl;
-        const bool self = tw[t] == 1 || herm1;
-        const int cmax = self ? m : n;
-        const double2* src = self ? ar : br;
-        const double2 y = src[c < cmax ? c : cmax - 1];
-        fb[t] = (rok && c < cmax) ? y : z2;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-      if (t < nt) {
-        const double2 a = fa[t], b = fb[t];
-        // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
-        accr[t] = mfma(a.x, b.x, accr[t]);
-        accr[t] = mfma(a.y, b.y, accr[t]);
-        acci[t] = mfma(a.x, b.y, acci[t]);
-        acci[t] = mfma(-a.y, b.x, acci[t]);
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    if (t >= nt) continue;
-    const int I = tI[t], J = tJ[t];
-    const bool second = tw[t] == 1;
+  for (int bk = wave; bk < nb1 + nb2; bk += nw) {
+    const bool second = bk >= nb1;  // wave-uniform
+    const bool self = second || herm1;
     const int ncol = second ? m : n;
-    double2* P = (second ? part2 + (size_t)blockIdx.x * m * m : part1 + (size_t)blockIdx.x * m * n);
-    const int col = J * 16 + cl;
+    const int tj = second ? TI : TJ;
+    int bi, bj;
+    gram_block_of(second ? bk - nb1 : bk, TI, tj, RI, RJ, second || herm1, bi, bj);
+    int ca[RI], cb[RJ];
+    bool va[RI], vb[RJ];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int rowo = I * 16 + (lane >> 4) + 4 * v;
-      if (rowo < m && col < ncol) P[(size_t)rowo * ncol + col] = make_double2(accr[t][v], acci[t][v]);
+    for (int r = 0; r < RI; ++r) {
+      const int c = (bi * RI + r) * 16 + cl;
+      va[r] = c < m;
+      ca[r] = va[r] ? c : m - 1;
     }
+#pragma unroll
+    for (int q = 0; q < RJ; ++q) {
+      const int c = (bj * RJ + q) * 16 + cl;
+      vb[q] = c < ncol;
+      cb[q] = vb[q] ? c : ncol - 1;
+    }
+    const double2* Bs = self ? A : B;
+    const int64_t ldbs = self ? lda : ldb;
+    double4_t accr[RI][RJ], acci[RI][RJ];
+#pragma unroll
+    for (int r = 0; r < RI; ++r)
+#pragma unroll
+      for (int q = 0; q < RJ; ++q) {
+        accr[r][q] = double4_t{0, 0, 0, 0};
+        acci[r][q] = double4_t{0, 0, 0, 0};
+      }
+    for (int64_t k0 = r0; k0 < r1; k0 += 4) {
+      const int64_t row = k0 + (lane >> 4);
+      const bool rok = row < r1;
+      const int64_t rowc = rok ? row : r1 - 1;
+      double2 fa[RI], fb[RJ];
+#pragma unroll
+      for (int r = 0; r < RI; ++r) {
+        const double2 x = A[rowc * lda + ca[r]];
+        fa[r] = (rok && va[r]) ? x : z2;
+      }
+#pragma unroll
+      for (int q = 0; q < RJ; ++q) {
+        const double2 y = Bs[rowc * ldbs + cb[q]];
+        fb[q] = (rok && vb[q]) ? y : z2;
+      }
+#pragma unroll
+      for (int r = 0; r < RI; ++r)
+#pragma unroll
+        for (int q = 0; q < RJ; ++q) {
+          // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
+          accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);
+          accr[r][q] = mfma(fa[r].y, fb[q].y, accr[r][q]);
+          acci[r][q] = mfma(fa[r].x, fb[q].y, acci[r][q]);
+          acci[r][q] = mfma(-fa[r].y, fb[q].x, acci[r][q]);
+        }
+    }
+    double2* P = second ? part2 + (size_t)blockIdx.x * m * m : part1 + (size_t)blockIdx.x * m * n;
+#pragma unroll
+    for (int r = 0; r < RI; ++r)
+#pragma unroll
+      for (int q = 0; q < RJ; ++q) {
+        const int I = bi * RI + r, J = bj * RJ + q;
+        if (I >= TI || J >= tj) continue;
+        const int col = J * 16 + cl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rowo = I * 16 + (lane >> 4) + 4 * v;
+          if (rowo < m && col < ncol)
+            P[(size_t)rowo * ncol + col] = make_double2(accr[r][q][v], acci[r][q][v]);
+        }
+      }
   }
 }
 
@@ -237,16 +241,13 @@ hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t l
     const dim3 grid((unsigned)g.chunks), block(64 * g.waves);
     const double2* Ac = reinterpret_cast<const double2*>(A);
     const double2* Bc = reinterpret_cast<const double2*>(B);
-#define MPT_GC(MT)                                                                               \
-  hipLaunchKernelGGL((k_gram_chunk<MT, (MT > 8 ? 8 : 4)>), grid, block, 0, st, Ac, lda, Bc, ldb, \
-                     N, m, n, g.rows, herm1 ? 1 : 0, g.t1, g.T, part1, part2)
-    switch (g.maxt) {
-      case 2: MPT_GC(2); break;
-      case 4: MPT_GC(4); break;
-      case 6: MPT_GC(6); break;
-      case 8: MPT_GC(8); break;
-      default: MPT_GC(10); break;
-    }
+#define MPT_GC(RI, RJ)                                                                      \
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ>), grid, block, 0, st, Ac, lda, Bc, ldb, N, m, n, \
+                     g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
+    if (g.RI == 2) MPT_GC(2, 2);
+    else if (g.RJ == 3) MPT_GC(1, 3);
+    else if (g.RJ == 2) MPT_GC(1, 2);
+    else MPT_GC(1, 1);
 #undef MPT_GC
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
