@@ -55,6 +55,8 @@ KERNEL_SOURCES = {
     "sweep": ["paper_2307_05590_amd/csrc/sweep_impl.h", "paper_2307_05590_amd/csrc/sweep.hip",
               "paper_2307_05590_amd/csrc/device_util.h"],
     "spmm": ["paper_2307_05590_amd/csrc/spmm.hip", "paper_2307_05590_amd/csrc/device_util.h"],
+    "sweep_pencil": ["paper_2307_05590_amd/csrc/pencil.hip",
+                     "paper_2307_05590_amd/csrc/device_util.h"],
 }
 
 
@@ -92,6 +94,16 @@ def sweep_flops(M):
     return 8.0 / 3.0 * M ** 3 + 4 * M ** 2 + 24 * M ** 2 + 96 * M ** 2 + 200 * M
 
 
+def pencil_sweep_flops(M):
+    """Algorithmic FP64 flops per (object, omega) of the sweep on the
+    Hessenberg-triangular pencil: column elimination with the interleaved back
+    substitution on three right-hand sides 16 M^2, the transformed reduced
+    products (four M x M matrices and six rows) on three vectors 96 M^2 +
+    144 M, the quadratic-form contractions 96 M, the column transforms of the
+    solution and the final formulas O(M)."""
+    return 16 * M ** 2 + 96 * M ** 2 + 144 * M + 96 * M + 24 * M + 200
+
+
 def spmm_bytes(N, nnz, M):
     """Algorithmic bytes of Y = K U: CSR (8 B value + 4 B index per nonzero,
     4 B per row pointer), U read once and Y written once (16 B per complex)."""
@@ -107,6 +119,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive"], default="plain")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
+    ap.add_argument("--sweep", choices=["lu", "pencil"], default="lu",
+                    help="per-frequency LU of the reduced system, or the Hessenberg-triangular "
+                         "pencil form (reduced once per step)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -148,20 +163,27 @@ def main():
     tol, cap = p.wl.tol_sigma, p.wl.m_cap
     torch.cuda.synchronize()
 
-    stages = ["pod", "project", "sweep", "select"]
+    pencil = args.sweep == "pencil"
+    stages = ["pod", "project", "pencil", "sweep", "select"] if pencil else \
+        ["pod", "project", "sweep", "select"]
     ev = {s: [] for s in stages}
 
     def step(record):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
         e[0].record()
         U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
         e[1].record()
         rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, S)
         e[2].record()
-        out, st = mpt.mpt_sweep(rom, omega)
-        e[3].record()
+        if pencil:
+            pen = mpt.mpt_pencil_reduce(rom)
+            e[3].record()
+            out, st = mpt.mpt_sweep_pencil(pen, omega)
+        else:
+            out, st = mpt.mpt_sweep(rom, omega)
+        e[len(stages) - 1].record()
         new, lam, Lmax = mpt.mpt_select_snapshots(omega, out, snap, 2)
-        e[4].record()
+        e[len(stages)].record()
         if record:
             for i, s in enumerate(stages):
                 ev[s].append((e[i], e[i + 1]))
@@ -185,7 +207,8 @@ def main():
     log(f"M={M}; ms/step {ms_step:.3f}; stages {ms}")
 
     # sweep kernel roofline (FP64 vector ALU) and the SpMM on its own (HBM)
-    sweep_tf = sweep_flops(M) * n_omega / (ms["sweep"] * 1e-3) / 1e12
+    fpu = pencil_sweep_flops(M) if pencil else sweep_flops(M)
+    sweep_tf = fpu * n_omega / (ms["sweep"] * 1e-3) / 1e12
     U, _, _ = mpt.mpt_pod_basis(D, tol, cap)
     for _ in range(3):
         mpt.mpt_spmm(K, U)
@@ -201,12 +224,21 @@ def main():
     spmm_gbs = spmm_bytes(ops.N, ops.K.nnz, M) / (spmm_ms * 1e-3) / 1e9
 
     dominant = max(stages, key=lambda s: ms[s])
-    roofline = {"kernel": "sweep (k_sweep: reduced LU + solves + tensors + certificates)",
-                "bound": "alu", "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF,
-                "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4),
-                "traffic": measured_traffic("sweep"),
-                "flops_per_unit": sweep_flops(M), "units_per_launch": n_omega,
-                "launch_ms": round(ms["sweep"], 4)}
+    if pencil:
+        roofline = {"kernel": "sweep on the Hessenberg-triangular pencil (k_sweep_pencil: "
+                              "Hessenberg solves + MFMA quadratic forms + tensors + certificates)",
+                    "bound": "mfma", "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF,
+                    "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4),
+                    "traffic": measured_traffic("sweep_pencil"),
+                    "flops_per_unit": fpu, "units_per_launch": n_omega,
+                    "launch_ms": round(ms["sweep"], 4)}
+    else:
+        roofline = {"kernel": "sweep (k_sweep: reduced LU + solves + tensors + certificates)",
+                    "bound": "alu", "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF,
+                    "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4),
+                    "traffic": measured_traffic("sweep"),
+                    "flops_per_unit": fpu, "units_per_launch": n_omega,
+                    "launch_ms": round(ms["sweep"], 4)}
 
     cpu = None
     if not args.no_cpu:
@@ -523,7 +555,8 @@ def bench_adaptive(args):
           enumerate(stages)}
     n_omega = omega.numel()
     value = n_omega / (elapsed / args.steps)
-    sweep_tf = sweep_flops(M) * n_omega / (ms["sweep"] * 1e-3) / 1e12
+    fpu = pencil_sweep_flops(M) if pencil else sweep_flops(M)
+    sweep_tf = fpu * n_omega / (ms["sweep"] * 1e-3) / 1e12
     log(f"final: {p.D.shape[1]} columns, M={M}, ms/step {1e3 * elapsed / args.steps:.3f}, {ms}")
     cpu = None if args.no_cpu else cpu_baseline(p, args.cpu_seconds)
     line = {

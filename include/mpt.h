@@ -218,6 +218,44 @@ mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
                                      const double* dout, double* dL_domega, double* sig_dsig,
                                      int32_t* status);
 
+/* ----------------------------------------------------------------------
+ * Pencil form of the sweep: the shifted-system method of Laub (IEEE TAC
+ * 1981) applied to eq. (ReducedA).
+ * mpt_pencil_reduce, once per object: unitary Q and Z with
+ *   Q^H A0 Z = H (upper Hessenberg),  Q^H C_M Z = T (upper triangular)
+ * (Householder QR of C_M, then Givens rotations from both sides), f_i =
+ * Q^H g_i, and the quadratic-form matrices of eqs. (podprealmpt),
+ * (podpimagmpt) and Lemma 4.1 transformed by Z.  buf (device, >=
+ * mpt_pencil_bytes(M) bytes, owned by the caller and kept alive while the
+ * pencil is used) receives all of it; *out (host struct) receives device
+ * pointers into buf.  The rom matrices are only read and may be freed after
+ * the stream has passed the call.  1 <= M <= 64.
+ * mpt_sweep_pencil: per frequency the Hessenberg system
+ *   (H - i w T) y_i = i w f_i,   a_i = Z y_i,
+ * solved by column elimination with pivoting between adjacent columns
+ * (O(M^2)), and the same outputs as mpt_sweep (out n x 18, a_out n x 3 x M
+ * when non-NULL, status per frequency: 0 or MPT_E_SINGULAR), equal to them up
+ * to rounding.  Asynchronous like mpt_sweep.
+ */
+typedef struct {
+  int32_t M;
+  int32_t pad_;
+  const double* H;   /* M x M complex, column-major */
+  const double* T;   /* M x M complex, column-major */
+  const double* f;   /* 3 x M complex */
+  const double* Z;   /* M x M complex, row-major */
+  const double* W;   /* stacked transformed matrices, MFMA fragment order */
+  const double* S;   /* 27 doubles: Re G_ee (3 x 3), E, N0 */
+  double alpha;
+  double alpha_lb;
+} mpt_pencil;
+
+size_t mpt_pencil_bytes(int M);
+mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf, size_t bytes,
+                             mpt_pencil* out);
+mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* omega,
+                            int64_t n_omega, double* out, double* a_out, int32_t* status);
+
 #ifdef __cplusplus
 }
 #endif

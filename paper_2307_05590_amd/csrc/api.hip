@@ -525,6 +525,53 @@ extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const 
   return MPT_OK;
 }
 
+// ------------------------------------------------------ pencil form sweep
+extern "C" size_t mpt_pencil_bytes(int M) {
+  if (M < 1 || M > 64) return 0;
+  return mpt::pencil_layout(M).total;
+}
+
+extern "C" mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf,
+                                        size_t bytes, mpt_pencil* out) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the pencil form takes M <= 64");
+  ARG(buf != nullptr && out != nullptr, "NULL buf/out");
+  const mpt::PencilLayout L = mpt::pencil_layout(rom->M);
+  if (bytes < L.total) return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(mpt::pencil_reduce_launch(rom->M, rom->A0, rom->CM, rom->KM, rom->G, rom->g, rom->E,
+                                   rom->N0, buf, h->stream));
+  char* b = static_cast<char*>(buf);
+  out->M = rom->M;
+  out->pad_ = 0;
+  out->H = reinterpret_cast<const double*>(b + L.H);
+  out->T = reinterpret_cast<const double*>(b + L.T);
+  out->f = reinterpret_cast<const double*>(b + L.f);
+  out->Z = reinterpret_cast<const double*>(b + L.Z);
+  out->W = reinterpret_cast<const double*>(b + L.W);
+  out->S = reinterpret_cast<const double*>(b + L.S);
+  out->alpha = rom->alpha;
+  out->alpha_lb = rom->alpha_lb;
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* omega,
+                                       int64_t n_omega, double* out, double* a_out,
+                                       int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  ARG(pen != nullptr, "pencil is NULL");
+  ARG(pen->M >= 1 && pen->M <= 64, "pencil M must be in [1, 64]");
+  ARG(pen->H && pen->T && pen->f && pen->Z && pen->W && pen->S, "pencil has a NULL part");
+  ARG(pen->alpha > 0.0 && pen->alpha_lb > 0.0, "pencil alpha and alpha_lb must be positive");
+  ARG(n_omega >= 0, "n_omega < 0");
+  ARG(n_omega == 0 || (omega && out && status), "NULL omega/out/status");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(mpt::pencil_sweep_launch(*pen, omega, n_omega, out, a_out, status, h->stream));
+  return MPT_OK;
+}
+
 // -------------------------------------------------------------- a5 select
 extern "C" mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n,
                                            const double* out, const double* snap, int n_snap,

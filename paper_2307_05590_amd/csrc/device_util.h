@@ -40,6 +40,13 @@ __device__ __forceinline__ double2 cfmac(double2 acc, double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// v_mfma_f64_16x16x4f64, operand layout for lane l (0..63):
+//   a: A[l % 16][l / 16]   b: B[l / 16][l % 16]   d: D[(l / 16) + 4 v][l % 16]
+typedef double double4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // 1 / z for a non-zero complex z
 __device__ __forceinline__ double2 crecip(double2 z) {
   const double d = z.x * z.x + z.y * z.y;

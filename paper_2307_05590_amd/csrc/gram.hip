@@ -14,12 +14,6 @@
 
 namespace mpt {
 
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double4_t mfma(double a, double b, double4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 // ---------------------------------------------------------------- Gram
 // One workgroup owns every output tile of its chunk of rows, so each row is
 // read from HBM once and shared by the waves through L1/L2.  The tiles (16x16)

@@ -66,4 +66,17 @@ hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, vo
 hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, void* ws,
                          int max_sweeps, double tol, double floor_rel, hipStream_t st);
 
+// pencil.hip : Hessenberg-triangular form of (A0, C_M) and the sweep on it.
+//   Byte offsets of the parts of one object's pencil buffer.
+struct PencilLayout {
+  size_t H, T, f, Z, Zf, W, S, rec, total;
+  int Mp, Kp, NT;  // M rounded up to 16 / to 4; MFMA row tiles of W
+};
+PencilLayout pencil_layout(int M);
+hipError_t pencil_reduce_launch(int M, const double* A0, const double* CM, const double* KM,
+                                const double* G, const double* g, const double* E,
+                                const double* N0, void* buf, hipStream_t st);
+hipError_t pencil_sweep_launch(const mpt_pencil& pen, const double* omega, int64_t n,
+                               double* out, double* a_out, int32_t* status, hipStream_t st);
+
 }  // namespace mpt

@@ -30,6 +30,12 @@ class _Rom(C.Structure):
                 ("N0", C.c_void_p), ("alpha", C.c_double), ("alpha_lb", C.c_double)]
 
 
+class _Pencil(C.Structure):
+    _fields_ = [("M", C.c_int32), ("pad_", C.c_int32), ("H", C.c_void_p), ("T", C.c_void_p),
+                ("f", C.c_void_p), ("Z", C.c_void_p), ("W", C.c_void_p), ("S", C.c_void_p),
+                ("alpha", C.c_double), ("alpha_lb", C.c_double)]
+
+
 class _Tuning(C.Structure):
     _fields_ = [("omegas_per_item", C.c_int32), ("waves_per_group", C.c_int32),
                 ("groups_per_cu", C.c_int32), ("reserved", C.c_int32)]
@@ -63,6 +69,9 @@ def lib():
             "mpt_sweep_batched": ([P, P, P, I32, P, P, P, P, P, I32], I32),
             "mpt_sweep_adjoint": ([P, P, P, I64, P, P, P, P], I32),
             "mpt_sweep_adjoint_batched": ([P, P, P, I32, P, P, P, P, P, P], I32),
+            "mpt_pencil_bytes": ([I32], S),
+            "mpt_pencil_reduce": ([P, P, P, S, P], I32),
+            "mpt_sweep_pencil": ([P, P, P, I64, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -241,6 +250,54 @@ def mpt_sweep(rom: Rom, omega: torch.Tensor, want_a: bool = False):
     a = torch.empty((n, 3, rom.M), dtype=torch.complex128, device=omega.device) if want_a else None
     r = rom.struct()
     h._check(lib().mpt_sweep(h.h, C.byref(r), _ptr(omega), n, _ptr(out), _ptr(a), _ptr(st)))
+    return (out, st, a) if want_a else (out, st)
+
+
+class Pencil:
+    """Hessenberg-triangular form of one object's reduced pencil (device buffer)."""
+
+    def __init__(self, buf, st: _Pencil, rom: Rom):
+        self.buf = buf  # keeps the device buffer alive
+        self.st = st
+        self.M = st.M
+        self.rom = rom
+
+    def parts(self):
+        """Views (H, T column-major as stored; f; Z) as complex tensors."""
+        M = self.M
+        base = self.buf.data_ptr()
+
+        def view(ptr, shape):
+            off = ptr - base
+            n = shape[0] * shape[1] * 16
+            return self.buf[off:off + n].view(torch.complex128).view(*shape)
+        return (view(self.st.H, (M, M)), view(self.st.T, (M, M)), view(self.st.f, (3, M)),
+                view(self.st.Z, (M, M)))
+
+
+def mpt_pencil_reduce(rom: Rom) -> Pencil:
+    """Reduce (A0, C_M) to Hessenberg-triangular form (asynchronous)."""
+    h = handle(rom.A0.device)
+    nb = lib().mpt_pencil_bytes(rom.M)
+    if nb == 0:
+        raise MptError(f"the pencil form takes 1 <= M <= 64 (M = {rom.M})")
+    buf = torch.empty(nb, dtype=torch.uint8, device=rom.A0.device)
+    r = rom.struct()
+    st = _Pencil()
+    h._check(lib().mpt_pencil_reduce(h.h, C.byref(r), _ptr(buf), nb, C.byref(st)))
+    return Pencil(buf, st, rom)
+
+
+def mpt_sweep_pencil(pen: Pencil, omega: torch.Tensor, want_a: bool = False):
+    """Sweep on the pencil form: same outputs as mpt_sweep."""
+    h = handle(omega.device)
+    _dev_check(omega)
+    n = omega.numel()
+    out = torch.empty((n, 18), dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    a = torch.empty((n, 3, pen.M), dtype=torch.complex128, device=omega.device) if want_a else None
+    h._check(lib().mpt_sweep_pencil(h.h, C.byref(pen.st), _ptr(omega), n, _ptr(out), _ptr(a),
+                                    _ptr(st)))
     return (out, st, a) if want_a else (out, st)
 
 

@@ -29,10 +29,15 @@ def _dev(a, dt=None):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
 
 
-def _check_sweep(mpt, host, G, rom_o, alpha, omega, tag):
+def _check_sweep(mpt, host, G, rom_o, alpha, omega, tag, form="lu"):
     rom = mpt.Rom.from_host(host, alpha)
     w = _dev(omega, torch.float64)
-    out, st, a_gpu = mpt.mpt_sweep(rom, w, want_a=True)
+    if form == "pencil":
+        pen = mpt.mpt_pencil_reduce(rom)
+        out, st, a_gpu = mpt.mpt_sweep_pencil(pen, w, want_a=True)
+        tag = f"{tag} (pencil)"
+    else:
+        out, st, a_gpu = mpt.mpt_sweep(rom, w, want_a=True)
     torch.cuda.synchronize()
     out = out.cpu().numpy()
     assert int(st.abs().max()) == 0, tag
@@ -123,6 +128,92 @@ def test_sweep_deterministic(mpt):
     w = _dev(np.logspace(1, 6, 500), torch.float64)
     o1, _ = mpt.mpt_sweep(rom, w)
     o2, _ = mpt.mpt_sweep(rom, w)
+    assert torch.equal(o1, o2)
+
+
+# ------------------------------------------------- pencil form of the sweep
+@pytest.mark.parametrize("M", [1, 2, 3, 16, 17, 31, 47, 48, 64])
+def test_pencil_random_roms(mpt, M):
+    rom_o, G, host, alpha = random_rom(M, seed=M)
+    omega = np.logspace(1, 6, 131)
+    rom_o["KM"] = host["KM"]
+    _check_sweep(mpt, host, G, rom_o, alpha, omega, f"random M={M}", form="pencil")
+
+
+@pytest.mark.parametrize("M", [10, 48])
+def test_pencil_ellipsoid_rom(mpt, M):
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    _check_sweep(mpt, host, G, rom_o, fo.alpha, np.logspace(1, 6, 257), f"ellipsoid16 M={M}",
+                 form="pencil")
+
+
+def test_pencil_magnetic_rom(mpt):
+    c = _cases.magnetic10()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :12]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    _check_sweep(mpt, host, G, rom_o, fo.alpha, np.logspace(1, 6, 65), "magnetic10 M=12",
+                 form="pencil")
+
+
+@pytest.mark.parametrize("M", [2, 17, 48, 64])
+def test_pencil_structure(mpt, M):
+    """H upper Hessenberg and T upper triangular (exact zeros), Z unitary, and
+    the generalised eigenvalues of (H, T) those of (A0, C_M)."""
+    import scipy.linalg as sl
+
+    rom_o, G, host, alpha = random_rom(M, seed=100 + M)
+    pen = mpt.mpt_pencil_reduce(mpt.Rom.from_host(host, alpha))
+    H, T, f, Z = (x.cpu().numpy() for x in pen.parts())
+    H, T = H.T, T.T  # stored column-major
+    assert np.all(np.tril(H, -2) == 0) and np.all(np.tril(T, -1) == 0)
+    assert np.abs(Z.conj().T @ Z - np.eye(M)).max() <= 64 * M * 2.2e-16
+    ev_ref = np.sort_complex(sl.eigvals(host["CM"], host["A0"]))
+    ev = np.sort_complex(sl.eigvals(T, H))
+    assert np.abs(ev - ev_ref).max() <= 1e-9 * np.abs(ev_ref).max()
+
+
+def test_pencil_matches_lu_sweep(mpt):
+    rom_o, G, host, alpha = random_rom(40, seed=7)
+    rom = mpt.Rom.from_host(host, alpha)
+    w = _dev(np.logspace(1, 6, 1000), torch.float64)
+    o1, s1 = mpt.mpt_sweep(rom, w)
+    o2, s2 = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(rom), w)
+    torch.cuda.synchronize()
+    assert int(s1.abs().max()) == 0 and int(s2.abs().max()) == 0
+    o1, o2 = o1.cpu().numpy(), o2.cpu().numpy()
+    for part in range(3):
+        a, b = o1[:, 6 * part:6 * part + 6], o2[:, 6 * part:6 * part + 6]
+        scale = np.abs(a).max(axis=1, keepdims=True)
+        assert np.all(np.abs(a - b) <= 1e-9 * scale), part
+
+
+def test_pencil_empty_bad_args_singular_deterministic(mpt):
+    rom_o, G, host, alpha = random_rom(5, seed=1)
+    pen = mpt.mpt_pencil_reduce(mpt.Rom.from_host(host, alpha))
+    out, st = mpt.mpt_sweep_pencil(pen, torch.empty(0, dtype=torch.float64, device="cuda"))
+    assert out.shape == (0, 18)
+    assert mpt.lib().mpt_pencil_bytes(65) == 0
+    rom_o, G, host65, alpha = random_rom(65, seed=65)
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_pencil_reduce(mpt.Rom.from_host(host65, alpha))
+    # a zero pencil is flagged
+    z = dict(host)
+    z["A0"] = np.zeros((5, 5))
+    z["CM"] = np.zeros((5, 5))
+    pz = mpt.mpt_pencil_reduce(mpt.Rom.from_host(z, alpha))
+    out, st = mpt.mpt_sweep_pencil(pz, _dev([1.0, 2.0], torch.float64))
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == mpt.MPT_E_SINGULAR)
+    # deterministic, ragged batch tail
+    rom_o, G, host, alpha = random_rom(40, seed=3)
+    pen = mpt.mpt_pencil_reduce(mpt.Rom.from_host(host, alpha))
+    w = _dev(np.logspace(1, 6, 501), torch.float64)
+    o1, _ = mpt.mpt_sweep_pencil(pen, w)
+    o2, _ = mpt.mpt_sweep_pencil(pen, w)
     assert torch.equal(o1, o2)
 
 
@@ -398,9 +489,11 @@ def test_full_size_ellipsoid48_sampled(mpt):
     out, st = mpt.mpt_sweep(rom, omega_d)
     new, lam, Lmax = mpt.mpt_select_snapshots(omega_d, out, _dev(np.sort(p.snap_omega),
                                                                  torch.float64), 2)
+    out_p, st_p = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(rom), omega_d)
     torch.cuda.synchronize()
-    assert int(st.abs().max()) == 0
+    assert int(st.abs().max()) == 0 and int(st_p.abs().max()) == 0
     out = out.cpu().numpy()
+    out_p = out_p.cpu().numpy()
     # oracle
     from oracle.grid import FullOrder
     fo = FullOrder(ops.grid.n, ops.sigma_e, ops.mu_f, ops.alpha, ops.eps)
@@ -413,17 +506,18 @@ def test_full_size_ellipsoid48_sampled(mpt):
     sel = np.arange(0, p.omega.size, 250)
     ref, a_o = R.sweep(rom_o, p.omega[sel], G, ops.alpha)
     sc = term_scales(ref, p.omega[sel], rom_o["N0"], rom_o["E"], ops.alpha)
-    eR, eI = tensor_errors(out[sel, :12], ref[:, :12], sc)
     # the GPU and the oracle solve in two different (equally valid) bases of
     # the same subspace, so where the reduced system is ill-conditioned their
     # backward-stable solves agree to ~eps cond(A^M(w)) only
     A0o = rom_o["KM"] + fo.eps_h * rom_o["UhU"]
     kap = np.array([np.linalg.cond(A0o - 1j * w_ * rom_o["CM"]) for w_ in p.omega[sel]])
     bound = 1e-10 + 64 * 2.2e-16 * kap
-    print(f"full size sampled: R~ {eR.max():.2e} I {eI.max():.2e}; cond max {kap.max():.2e}; "
-          f"worst R~ err / (eps cond) {np.max(eR / (2.2e-16 * kap)):.2e} at w={p.omega[sel][np.argmax(eR)]:.3e}",
-          flush=True)
-    assert np.all(eR <= bound) and np.all(eI <= bound)
+    for form, o in (("lu", out), ("pencil", out_p)):
+        eR, eI = tensor_errors(o[sel, :12], ref[:, :12], sc)
+        print(f"full size sampled ({form}): R~ {eR.max():.2e} I {eI.max():.2e}; cond max "
+              f"{kap.max():.2e}; worst R~ err / (eps cond) {np.max(eR / (2.2e-16 * kap)):.2e} "
+              f"at w={p.omega[sel][np.argmax(eR)]:.3e}", flush=True)
+        assert np.all(eR <= bound) and np.all(eI <= bound), form
     # the integral-method analogue (explicit mesh sums) at a few of them
     sub = sel[::8]
     Rt, I = R.tensors_mesh(fo, U_o, R.reduced_solve(rom_o, p.omega[sub]), p.omega[sub], p.w,
@@ -434,6 +528,8 @@ def test_full_size_ellipsoid48_sampled(mpt):
     assert np.all(eR <= bound[::8]) and np.all(eI <= bound[::8])
     # certificates against the oracle's own, within the G-form rounding floor
     fl = delta_floor(G, a_o, p.omega[sel], ops.alpha)
-    d = np.abs(out[sel, 12:] - ref[:, 12:])
-    print(f"full size Delta err / floor max {np.max(d / (2.2e-16 * fl)):.2e}", flush=True)
-    assert np.all(d <= 1e-8 * np.abs(ref[:, 12:]) + 64 * 2.2e-16 * fl)
+    for form, o in (("lu", out), ("pencil", out_p)):
+        d = np.abs(o[sel, 12:] - ref[:, 12:])
+        print(f"full size Delta err / floor max ({form}) {np.max(d / (2.2e-16 * fl)):.2e}",
+              flush=True)
+        assert np.all(d <= 1e-8 * np.abs(ref[:, 12:]) + 64 * 2.2e-16 * fl), form
