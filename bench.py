@@ -351,8 +351,16 @@ def bench_dictionary(args):
         out = torch.empty((n_units, 18), dtype=torch.float64, device=dev)
         st = torch.empty(n_units, dtype=torch.int32, device=dev)
 
-        def step():
+        def lu_step():
             mpt.mpt_sweep_batched(dic, tune=best, use_graph=True, out=out, status=st)
+
+        pbuf = [None]
+
+        def pencil_step():
+            # every object's pencil reduction, then the batched pencil sweep
+            _, _, pbuf[0] = mpt.mpt_sweep_pencil_batched(dic, out=out, status=st, buf=pbuf[0])
+
+        step, alt_step = (pencil_step, lu_step) if args.sweep == "pencil" else (lu_step, pencil_step)
 
         def plain():
             for r, w in zip(roms, omegas):
@@ -367,6 +375,7 @@ def bench_dictionary(args):
         out = torch.empty((n_units, 18), dtype=torch.float64, device=dev)
         st = torch.empty(n_units, dtype=torch.int32, device=dev)
         best = (8, 2, 2)
+        alt_step = None
 
         def step():
             mpt.mpt_sweep_batched(dic, tune=best, use_graph=True, out=out, status=st)
@@ -408,8 +417,25 @@ def bench_dictionary(args):
     plain_ms = p0.elapsed_time(p1)
     value = n_units / (elapsed / args.steps)
     kernel_ms = e0.elapsed_time(e1) / args.steps
+    alt = None
+    if alt_step is not None:
+        for _ in range(args.warmup):
+            alt_step()
+        torch.cuda.synchronize()
+        a0, a1 = ev(), ev()
+        a0.record()
+        for _ in range(args.steps):
+            alt_step()
+        a1.record()
+        torch.cuda.synchronize()
+        alt_ms = a0.elapsed_time(a1) / args.steps
+        alt = {"path": "lu batched" if args.sweep == "pencil" else "pencil batched",
+               "value": round(n_units / (alt_ms * 1e-3), 1), "ms": round(alt_ms, 4)}
     # the adjoint kernel recomputes the forward work and adds the three A^H
     # solves (24 M^2) and the gradient dots (~24 M^2)
+    pencil_form = args.form == "batched" and args.sweep == "pencil"
+    if pencil_form:
+        flops = float(sum(pencil_sweep_flops(r.M) * w.numel() for r, w in zip(roms, omegas)))
     fl = flops if args.form == "batched" else float(
         sum((2 * sweep_flops(r.M) + 48 * r.M ** 2) * w.numel() for r, w in zip(roms, omegas)))
     achieved = fl / (kernel_ms * 1e-3) / 1e12
@@ -429,8 +455,12 @@ def bench_dictionary(args):
                    "schedule": tune_info},
         "plain_path": {"value": round(n_units / (plain_ms * 1e-3), 1), "ms": round(plain_ms, 4),
                        "speedup": round(plain_ms / kernel_ms, 3)},
-        "roofline": {"kernel": "persistent batched sweep" + (" + adjoint" if args.form == "adjoint" else ""),
-                     "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_PEAK_TF,
+        "alt_path": alt,
+        "roofline": {"kernel": ("pencil reductions + batched pencil sweep" if pencil_form else
+                                "persistent batched sweep" + (" + adjoint" if args.form == "adjoint"
+                                                              else "")),
+                     "bound": "mfma" if pencil_form else "alu", "achieved": round(achieved, 3),
+                     "peak": FP64_VALU_PEAK_TF,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TF, 4),
                      "traffic": None, "launch_ms": round(kernel_ms, 4)},
         "cpu_baseline": cpu,

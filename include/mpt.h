@@ -256,6 +256,21 @@ mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf, size_t
 mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* omega,
                             int64_t n_omega, double* out, double* a_out, int32_t* status);
 
+/* Pencil form for a dictionary: one call reduces every object (one
+ * workgroup per object and stage) and sweeps all objects' frequencies (work
+ * items of 16 frequencies of one object, one launch per segment width).
+ * roms_host: n_obj host structs (device pointers), 1 <= M <= 64 each;
+ * omega_off (n_obj + 1, host, omega_off[0] = 0) indexes omega / out / status
+ * as in mpt_sweep_batched; buf (device, >= mpt_pencil_batched_bytes) holds
+ * the objects' pencils, packed in order.  The work-item plan is uploaded once
+ * and reused while the arguments stay the same (the call synchronises the
+ * stream when it uploads a new plan).  Results equal mpt_sweep_pencil object
+ * by object. */
+size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj);
+mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms_host, int n_obj,
+                                    const int64_t* omega_off, const double* omega, void* buf,
+                                    size_t bytes, double* out, int32_t* status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,13 @@ struct mpt_handle_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
   hipStream_t cap = nullptr;  // private stream used only to record graphs
+  // uploaded plan of the last batched pencil call (jobs, per-object arguments,
+  // work items) and the key it was built for
+  void* pbuf = nullptr;
+  size_t pbuf_bytes = 0;
+  std::vector<int64_t> pkey;
+  int pn[3] = {0, 0, 0};
+  int pmaxM = 0;
 };
 
 namespace {
@@ -279,6 +286,7 @@ extern "C" mpt_status mpt_destroy(mpt_handle h) {
   if (h->cap) hipStreamDestroy(h->cap);
   if (h->buf) hipFree(h->buf);
   if (h->scr) hipFree(h->scr);
+  if (h->pbuf) hipFree(h->pbuf);
   if (h->host_M) hipHostFree(h->host_M);
   delete h;
   return MPT_OK;
@@ -541,8 +549,9 @@ extern "C" mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* 
   const mpt::PencilLayout L = mpt::pencil_layout(rom->M);
   if (bytes < L.total) return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
   HIP_OK(hipSetDevice(h->device));
-  HIP_OK(mpt::pencil_reduce_launch(rom->M, rom->A0, rom->CM, rom->KM, rom->G, rom->g, rom->E,
-                                   rom->N0, buf, h->stream));
+  mpt::PencilJob job{rom->M, 0, rom->A0, rom->CM, rom->KM, rom->G, rom->g, rom->E, rom->N0,
+                     static_cast<char*>(buf)};
+  HIP_OK(mpt::pencil_reduce_launch(job, nullptr, 1, rom->M, h->stream));
   char* b = static_cast<char*>(buf);
   out->M = rom->M;
   out->pad_ = 0;
@@ -568,7 +577,118 @@ extern "C" mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, cons
   ARG(n_omega >= 0, "n_omega < 0");
   ARG(n_omega == 0 || (omega && out && status), "NULL omega/out/status");
   HIP_OK(hipSetDevice(h->device));
-  HIP_OK(mpt::pencil_sweep_launch(*pen, omega, n_omega, out, a_out, status, h->stream));
+  HIP_OK(mpt::pencil_sweep_launch(mpt::pencil_args(*pen), omega, n_omega, out, a_out, status,
+                                  h->stream));
+  return MPT_OK;
+}
+
+// ------------------------------------------ pencil form for a dictionary
+extern "C" size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj) {
+  if (!roms_host || n_obj < 1) return 0;
+  size_t tot = 0;
+  for (int o = 0; o < n_obj; ++o) {
+    const int M = roms_host[o].M;
+    if (M < 1 || M > 64) return 0;
+    tot += mpt::pencil_layout(M).total;
+  }
+  return tot;
+}
+
+extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms_host, int n_obj,
+                                               const int64_t* omega_off, const double* omega,
+                                               void* buf, size_t bytes, double* out,
+                                               int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  ARG(roms_host && omega_off && omega && buf && out && status && n_obj >= 1, "NULL or empty");
+  for (int o = 0; o < n_obj; ++o) {
+    mpt_status s = check_rom(h, &roms_host[o]);
+    if (s != MPT_OK) return s;
+    if (roms_host[o].M > 64) return fail(h, MPT_E_UNSUPPORTED, "the pencil form takes M <= 64");
+    ARG(omega_off[o + 1] >= omega_off[o], "omega_off must be non-decreasing");
+  }
+  ARG(omega_off[0] == 0, "omega_off[0] must be 0");
+  if (bytes < mpt_pencil_batched_bytes(roms_host, n_obj))
+    return fail(h, MPT_E_NOMEM, "buffer smaller than mpt_pencil_batched_bytes");
+  HIP_OK(hipSetDevice(h->device));
+  std::vector<int64_t> key = {(int64_t)buf, (int64_t)omega, (int64_t)out, (int64_t)status, n_obj};
+  for (int o = 0; o <= n_obj; ++o) key.push_back(omega_off[o]);
+  for (int o = 0; o < n_obj; ++o) {
+    const mpt_rom& r = roms_host[o];
+    int64_t a, b;
+    std::memcpy(&a, &r.alpha, 8);
+    std::memcpy(&b, &r.alpha_lb, 8);
+    for (int64_t v : {(int64_t)r.M, (int64_t)r.KM, (int64_t)r.A0, (int64_t)r.CM, (int64_t)r.g,
+                      (int64_t)r.G, (int64_t)r.E, (int64_t)r.N0, a, b})
+      key.push_back(v);
+  }
+  if (key != h->pkey) {
+    std::vector<mpt::PencilJob> jobs(n_obj);
+    std::vector<mpt::PencilArgs> args(n_obj);
+    std::vector<int4> items[3];
+    char* base = static_cast<char*>(buf);
+    int maxM = 1;
+    for (int o = 0; o < n_obj; ++o) {
+      const mpt_rom& r = roms_host[o];
+      jobs[o] = mpt::PencilJob{r.M, 0, r.A0, r.CM, r.KM, r.G, r.g, r.E, r.N0, base};
+      mpt_pencil pen{};
+      pen.M = r.M;
+      pen.H = reinterpret_cast<const double*>(base);
+      pen.alpha = r.alpha;
+      pen.alpha_lb = r.alpha_lb;
+      args[o] = mpt::pencil_args(pen);
+      base += mpt::pencil_layout(r.M).total;
+      maxM = std::max(maxM, r.M);
+      const int bi = r.M <= 16 ? 0 : (r.M <= 32 ? 1 : 2);
+      for (int64_t k = omega_off[o]; k < omega_off[o + 1]; k += 16) {
+        const int cnt = (int)std::min<int64_t>(16, omega_off[o + 1] - k);
+        items[bi].push_back(make_int4(o, (int)k, cnt, 0));
+      }
+    }
+    const size_t jb = align256(n_obj * sizeof(mpt::PencilJob));
+    const size_t ab = align256(n_obj * sizeof(mpt::PencilArgs));
+    const size_t ni = items[0].size() + items[1].size() + items[2].size();
+    const size_t need = jb + ab + align256(ni * sizeof(int4));
+    if (h->pbuf_bytes < need) {
+      if (h->pbuf) {
+        HIP_OK(hipStreamSynchronize(h->stream));
+        HIP_OK(hipFree(h->pbuf));
+        h->pbuf = nullptr;
+        h->pbuf_bytes = 0;
+      }
+      HIP_OK(hipMalloc(&h->pbuf, need));
+      h->pbuf_bytes = need;
+    }
+    std::vector<int4> all;
+    all.reserve(ni);
+    for (auto& v : items) all.insert(all.end(), v.begin(), v.end());
+    char* pb = static_cast<char*>(h->pbuf);
+    HIP_OK(hipMemcpyAsync(pb, jobs.data(), n_obj * sizeof(mpt::PencilJob), hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipMemcpyAsync(pb + jb, args.data(), n_obj * sizeof(mpt::PencilArgs),
+                          hipMemcpyHostToDevice, h->stream));
+    if (ni)
+      HIP_OK(hipMemcpyAsync(pb + jb + ab, all.data(), ni * sizeof(int4), hipMemcpyHostToDevice,
+                            h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
+    for (int b = 0; b < 3; ++b) h->pn[b] = (int)items[b].size();
+    h->pmaxM = maxM;
+    h->pkey = key;
+  }
+  char* pb = static_cast<char*>(h->pbuf);
+  const size_t jb = align256(n_obj * sizeof(mpt::PencilJob));
+  const size_t ab = align256(n_obj * sizeof(mpt::PencilArgs));
+  const auto* jobs = reinterpret_cast<const mpt::PencilJob*>(pb);
+  const auto* args = reinterpret_cast<const mpt::PencilArgs*>(pb + jb);
+  const int4* items = reinterpret_cast<const int4*>(pb + jb + ab);
+  mpt::PencilJob none{};
+  HIP_OK(mpt::pencil_reduce_launch(none, jobs, n_obj, h->pmaxM, h->stream));
+  const int Ls[3] = {16, 32, 64};
+  int at = 0;
+  for (int b = 0; b < 3; ++b) {
+    HIP_OK(mpt::pencil_sweep_items_launch(Ls[b], args, items + at, h->pn[b], omega, out, status,
+                                          h->stream));
+    at += h->pn[b];
+  }
   return MPT_OK;
 }
 

@@ -72,11 +72,65 @@ struct PencilLayout {
   size_t H, T, f, Z, Zf, W, S, rec, total;
   int Mp, Kp, NT;  // M rounded up to 16 / to 4; MFMA row tiles of W
 };
-PencilLayout pencil_layout(int M);
-hipError_t pencil_reduce_launch(int M, const double* A0, const double* CM, const double* KM,
-                                const double* G, const double* g, const double* E,
-                                const double* N0, void* buf, hipStream_t st);
-hipError_t pencil_sweep_launch(const mpt_pencil& pen, const double* omega, int64_t n,
-                               double* out, double* a_out, int32_t* status, hipStream_t st);
+__host__ __device__ inline PencilLayout pencil_layout(int M) {
+  PencilLayout L;
+  L.Mp = (M + 15) / 16 * 16;
+  L.Kp = (M + 3) / 4 * 4;
+  L.NT = 4 * (L.Mp / 16) + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  const size_t mm = (size_t)M * M * 16;
+  L.H = take(mm);
+  L.T = take(mm);
+  L.f = take((size_t)3 * M * 16);
+  L.Z = take(mm);
+  L.Zf = take((size_t)(L.Mp / 16) * (L.Kp / 4) * 64 * 16);
+  L.W = take((size_t)L.NT * (L.Kp / 4) * 64 * 16);
+  L.S = take(27 * 8);
+  const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 1;
+  L.rec = take(nrot * 3 * 8);
+  L.total = o;
+  return L;
+}
+// one object of a pencil reduction: the reduced model's matrices and the
+// pencil buffer (laid out by pencil_layout(M))
+struct PencilJob {
+  int M, pad_;
+  const double* A0;
+  const double* CM;
+  const double* KM;
+  const double* G;
+  const double* g;
+  const double* E;
+  const double* N0;
+  char* base;
+};
+// per-object arguments of the pencil sweep
+struct PencilArgs {
+  int M, Mp, Kp, NT;
+  const double2* H;
+  const double2* T;
+  const double2* f;
+  const double2* Zf;
+  const double2* W;
+  const double* S;
+  double alpha, alpha_lb;
+};
+PencilArgs pencil_args(const mpt_pencil& pen);
+// jobs == nullptr: the single job `one`; else n_jobs jobs from the device
+// array (maxM bounds their M)
+hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
+                                hipStream_t st);
+// items == nullptr: one object (P) over omega[0, n); else n_items work items
+// (object, first omega, count <= 16, -) of objects with segment width L
+hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,
+                               double* a_out, int32_t* status, hipStream_t st);
+hipError_t pencil_sweep_items_launch(int L, const PencilArgs* objs, const int4* items,
+                                     int n_items, const double* omega, double* out,
+                                     int32_t* status, hipStream_t st);
 
 }  // namespace mpt

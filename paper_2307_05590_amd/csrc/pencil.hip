@@ -32,75 +32,116 @@ namespace mpt {
 
 constexpr int kPenBatch = 16;  // frequencies per workgroup batch
 
-PencilLayout pencil_layout(int M) {
-  PencilLayout L;
-  L.Mp = (M + 15) / 16 * 16;
-  L.Kp = (M + 3) / 4 * 4;
-  L.NT = 4 * (L.Mp / 16) + 1;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    const size_t r = o;
-    o += (bytes + 255) & ~size_t(255);
-    return r;
-  };
-  const size_t mm = (size_t)M * M * 16;
-  L.H = take(mm);
-  L.T = take(mm);
-  L.f = take((size_t)3 * M * 16);
-  L.Z = take(mm);
-  L.Zf = take((size_t)(L.Mp / 16) * (L.Kp / 4) * 64 * 16);
-  L.W = take((size_t)L.NT * (L.Kp / 4) * 64 * 16);
-  L.S = take(27 * 8);
-  const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 1;
-  L.rec = take(nrot * 3 * 8);
-  L.total = o;
-  return L;
-}
-
 namespace {
 
+// 1 / sqrt(x) for a positive normal x: v_rsq_f64 and two Newton steps
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);  // 1 - x y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Givens rotation [[c, s], [-conj(s), c]] (c real) with
-//   [[c, s], [-conj(s), c]] [x; y] = [*; 0]
+//   [[c, s], [-conj(s), c]] [x; y] = [*; 0]:
+//   c = |x| / r,  s = (x / |x|) conj(y) / r,  r^2 = |x|^2 + |y|^2;
+// with t = 1 / (|x| r):  c = |x|^2 t,  s = x conj(y) t
 __device__ __forceinline__ void givens_left(double2 x, double2 y, double& c, double2& s) {
-  const double ax = sqrt(x.x * x.x + x.y * x.y);
+  const double ax2 = x.x * x.x + x.y * x.y;
   const double ay2 = y.x * y.x + y.y * y.y;
   if (ay2 == 0.0) {
     c = 1.0;
     s = make_double2(0.0, 0.0);
     return;
   }
-  if (ax == 0.0) {
+  if (ax2 == 0.0) {
     c = 0.0;
     s = make_double2(1.0, 0.0);
     return;
   }
-  const double r = sqrt(ax * ax + ay2);
-  c = ax / r;
-  // s = (x / |x|) conj(y) / r
-  const double2 u = make_double2(x.x / ax, x.y / ax);
-  const double2 sy = cmul(u, cconj(y));
-  s = make_double2(sy.x / r, sy.y / r);
+  const double t = rsqrt_d(ax2 * (ax2 + ay2));
+  c = ax2 * t;
+  const double2 sy = cmul(x, cconj(y));
+  s = make_double2(sy.x * t, sy.y * t);
 }
 
-// column rotation S = [[c, s], [-conj(s), c]] with [w, u] S = [0, *]
+// column rotation S = [[c, s], [-conj(s), c]] with [w, u] S = [0, *]:
+//   c = |u| / r,  s = conj(w) (u / |u|) / r;  with t = 1 / (|u| r):
+//   c = |u|^2 t,  s = conj(w) u t
 __device__ __forceinline__ void givens_right(double2 w, double2 u, double& c, double2& s) {
-  const double au = sqrt(u.x * u.x + u.y * u.y);
+  const double au2 = u.x * u.x + u.y * u.y;
   const double aw2 = w.x * w.x + w.y * w.y;
   if (aw2 == 0.0) {
     c = 1.0;
     s = make_double2(0.0, 0.0);
     return;
   }
-  if (au == 0.0) {
+  if (au2 == 0.0) {
     c = 0.0;
     s = make_double2(1.0, 0.0);
     return;
   }
-  const double r = sqrt(au * au + aw2);
-  c = au / r;
-  // s = conj(w) (u / |u|) / r
-  const double2 sw = cmul(cconj(w), make_double2(u.x / au, u.y / au));
-  s = make_double2(sw.x / r, sw.y / r);
+  const double t = rsqrt_d(au2 * (au2 + aw2));
+  c = au2 * t;
+  const double2 sw = cmul(cconj(w), u);
+  s = make_double2(sw.x * t, sw.y * t);
+}
+
+// Applies the rotations i = M-1 down to j+2 of one sweep to a vector p
+// (entries j+1 .. M-1, stride `stride`) with the shared entry carried in
+// registers:
+//   LEFT:  [p_{i-1}; p_i] <- [[c, s], [-conj(s), c]] [p_{i-1}; p_i]
+//   RIGHT: [p_{i-1}, p_i] <- [p_{i-1}, p_i] [[c, s], [-conj(s), c]]
+// Four entries are loaded per LDS round trip.  rot(i, c, s) supplies the
+// parameters; entries with index < zero_below are written as exact zeros.
+template <bool LEFT, class Rot>
+__device__ __forceinline__ void rot_chain(double2* p, int stride, int M, int j, Rot rot,
+                                          int zero_below) {
+  double2 carry = p[(M - 1) * stride];
+  int i = M - 1;
+  while (i >= j + 2) {
+    const int cnt = min(4, i - (j + 1));
+    double2 x[4], o[4], sv[4];
+    double cv[4];
+    // all loads of the group first: one LDS round trip per four rotations
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < cnt) {
+        x[t] = p[(i - 1 - t) * stride];
+        rot(i - t, cv[t], sv[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < cnt) {
+        const double c = cv[t];
+        const double2 s = sv[t];
+        const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
+        double2 n1, n2;
+        if (LEFT) {
+          n1 = cmul(s, carry);
+          n2 = cmul(ms, x[t]);
+        } else {
+          n1 = cmul(ms, carry);
+          n2 = cmul(s, x[t]);
+        }
+        n1.x = fma(c, x[t].x, n1.x);
+        n1.y = fma(c, x[t].y, n1.y);
+        n2.x = fma(c, carry.x, n2.x);
+        n2.y = fma(c, carry.y, n2.y);
+        o[t] = n2;
+        carry = n1;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < cnt) p[(i - t) * stride] = (i - t < zero_below) ? make_double2(0.0, 0.0) : o[t];
+    i -= cnt;
+  }
+  p[(j + 1) * stride] = (j + 1 < zero_below) ? make_double2(0.0, 0.0) : carry;
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -116,13 +157,18 @@ __device__ __forceinline__ void wave_sync_lds() {
 // rows), F (3 x M), v (M), beta.  The Givens chain runs in wave 0 (rotations
 // are sequential; each is applied by up to 64 lanes at once); the right
 // rotations are recorded for the accumulation of Z.
-__global__ __launch_bounds__(256) void k_pencil_reduce(int M, const double2* __restrict__ A0,
-                                                       const double2* __restrict__ CM,
-                                                       const double2* __restrict__ g,
-                                                       double2* __restrict__ H,
-                                                       double2* __restrict__ T,
-                                                       double2* __restrict__ f,
-                                                       double* __restrict__ rec) {
+__global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
+                                                       const PencilJob* __restrict__ jobs) {
+  const PencilJob J = jobs ? jobs[blockIdx.x] : one;
+  const int M = J.M;
+  const PencilLayout Lo = pencil_layout(M);
+  const double2* A0 = reinterpret_cast<const double2*>(J.A0);
+  const double2* CM = reinterpret_cast<const double2*>(J.CM);
+  const double2* g = reinterpret_cast<const double2*>(J.g);
+  double2* H = reinterpret_cast<double2*>(J.base + Lo.H);
+  double2* T = reinterpret_cast<double2*>(J.base + Lo.T);
+  double2* f = reinterpret_cast<double2*>(J.base + Lo.f);
+  double* rec = reinterpret_cast<double*>(J.base + Lo.rec);
   extern __shared__ double2 lds[];
   const int ld = M + 1;
   double2* sA = lds;
@@ -130,6 +176,7 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(int M, const double2* __r
   double2* sF = sB + M * ld;
   double2* sV = sF + 3 * M;
   __shared__ double sBeta;
+  __shared__ double2 sAlpha;
   const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   for (int e = tid; e < M * M; e += blockDim.x) {
     const int r = e / M, c = e % M;
@@ -154,13 +201,22 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(int M, const double2* __r
       const double2 v0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
       const double vn2 = nrm2 - ax0 * ax0 + (v0.x * v0.x + v0.y * v0.y);
       if (lane < len) sV[lane] = lane == 0 ? v0 : x;
-      if (lane == 0) sBeta = (nrm2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+      if (lane == 0) {
+        const bool refl = nrm2 > 0.0 && vn2 > 0.0;
+        sBeta = refl ? 2.0 / vn2 : 0.0;
+        sAlpha = refl ? alpha : x0;
+      }
     }
     __syncthreads();
     const double beta = sBeta;
     const int ncol = len + M + 3;
     if (beta != 0.0) {
       for (int t = tid; t < ncol; t += blockDim.x) {
+        if (t == 0) {  // the column being reduced: alpha e_1
+          sB[k * ld + k] = sAlpha;
+          for (int u = 1; u < len; ++u) sB[(k + u) * ld + k] = make_double2(0.0, 0.0);
+          continue;
+        }
         double2* col;
         int stride;
         if (t < len) {
@@ -173,103 +229,167 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(int M, const double2* __r
           col = sF + (t - len - M) * M + k;
           stride = 1;
         }
-        double2 s = make_double2(0.0, 0.0);
-        for (int u = 0; u < len; ++u) s = cfmac(s, sV[u], col[u * stride]);
-        s.x *= beta;
-        s.y *= beta;
-        for (int u = 0; u < len; ++u) col[u * stride] = cfms(col[u * stride], sV[u], s);
+        // v^H col with four independent partial sums
+        double2 p0 = make_double2(0.0, 0.0), p1 = p0, p2 = p0, p3 = p0;
+        int u = 0;
+        for (; u + 3 < len; u += 4) {
+          p0 = cfmac(p0, sV[u], col[u * stride]);
+          p1 = cfmac(p1, sV[u + 1], col[(u + 1) * stride]);
+          p2 = cfmac(p2, sV[u + 2], col[(u + 2) * stride]);
+          p3 = cfmac(p3, sV[u + 3], col[(u + 3) * stride]);
+        }
+        for (; u < len; ++u) p0 = cfmac(p0, sV[u], col[u * stride]);
+        double2 sdot = make_double2((p0.x + p1.x) + (p2.x + p3.x), (p0.y + p1.y) + (p2.y + p3.y));
+        sdot.x *= beta;
+        sdot.y *= beta;
+        for (u = 0; u < len; ++u) col[u * stride] = cfms(col[u * stride], sV[u], sdot);
       }
     }
-    __syncthreads();
-    for (int u = 1 + tid; u < len; u += blockDim.x) sB[(k + u) * ld + k] = make_double2(0.0, 0.0);
     __syncthreads();
   }
 
-  // ---- Givens chain: A to Hessenberg form, B kept triangular ------------
-  if (wave == 0) {
-    int nrec = 0;
-    for (int j = 0; j + 2 < M; ++j) {
+  // ---- Givens sweeps: A to Hessenberg form, B kept triangular ------------
+  // Sweep j zeroes A[j+2.., j] by left rotations of rows (i-1, i), i = M-1
+  // down to j+2; each fills B[i][i-1], which the right rotation of columns
+  // (i-1, i) removes.  Left and right rotations commute as operators, so a
+  // sweep is (1) its rotation parameters, then (2) A <- L A R, B <- L B R and
+  // F <- L F in bulk.  The parameters need little: the left ones follow from
+  // column j of A alone, and the right one of step i from three entries of B
+  // as the sweep has left them,
+  //   B[i-1][i-1] (untouched so far), B[i-1][i] = (B R)[i-1][i] (row i-1 is
+  //   untouched by the left rotations before step i) and B[i][i], which a
+  //   short scalar recursion carries from step to step;
+  // so wave 0 holds, per lane r, row r of B times the right rotations so far
+  // at the current column (the rows' carries), and everything moves between
+  // lanes by v_readlane: no LDS round trip on the sequential path.
+  // The right rotations are recorded in order for the accumulation of Z.
+  double* sRot = reinterpret_cast<double*>(sV);  // recL (3 x M) then recR (3 x M)
+  int nrec = 0;
+  for (int j = 0; j + 2 < M; ++j) {
+    double myc = 1.0, myc2 = 1.0;
+    double2 mys = make_double2(0.0, 0.0), mys2 = make_double2(0.0, 0.0);
+    if (wave == 0) {
+      const bool act = lane < M;
+      const double2 colj = act ? sA[lane * ld + j] : make_double2(0.0, 0.0);
+      const double2 bd = act ? sB[lane * ld + lane] : make_double2(0.0, 0.0);  // diagonal of B
+      double2 carry = act ? sB[lane * ld + M - 1] : make_double2(0.0, 0.0);
+      double2 nx = act ? sB[lane * ld + M - 2] : make_double2(0.0, 0.0);
+      double2 y = bcast2(colj, M - 1);
+      double c1 = 1.0, c21 = 1.0;
+      double2 s1 = make_double2(0.0, 0.0), s21 = make_double2(0.0, 0.0);
+      double2 e_prev = make_double2(0.0, 0.0), b_prev = make_double2(0.0, 0.0);
       for (int i = M - 1; i >= j + 2; --i) {
-        // left rotation of rows i-1, i: zero A[i][j]
+        // left rotation i (rows i-1, i) from column j
+        const double2 x = bcast2(colj, i - 1);
         double c;
         double2 s;
-        givens_left(sA[(i - 1) * ld + j], sA[i * ld + j], c, s);
-        const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
+        givens_left(x, y, c, s);
         {
-          const int col = j + lane;
-          if (col < M) {
-            const double2 x1 = sA[(i - 1) * ld + col], x2 = sA[i * ld + col];
-            double2 n1 = cmul(s, x2), n2 = cmul(ms, x1);
-            n1.x = fma(c, x1.x, n1.x);
-            n1.y = fma(c, x1.y, n1.y);
-            n2.x = fma(c, x2.x, n2.x);
-            n2.y = fma(c, x2.y, n2.y);
-            sA[(i - 1) * ld + col] = n1;
-            sA[i * ld + col] = col == j ? make_double2(0.0, 0.0) : n2;
-          }
-          const int cb = i - 1 + lane;
-          if (cb < M) {
-            const double2 x1 = sB[(i - 1) * ld + cb], x2 = sB[i * ld + cb];
-            double2 n1 = cmul(s, x2), n2 = cmul(ms, x1);
-            n1.x = fma(c, x1.x, n1.x);
-            n1.y = fma(c, x1.y, n1.y);
-            n2.x = fma(c, x2.x, n2.x);
-            n2.y = fma(c, x2.y, n2.y);
-            sB[(i - 1) * ld + cb] = n1;
-            sB[i * ld + cb] = n2;
-          }
-          if (lane < 3) {
-            const double2 x1 = sF[lane * M + i - 1], x2 = sF[lane * M + i];
-            double2 n1 = cmul(s, x2), n2 = cmul(ms, x1);
-            n1.x = fma(c, x1.x, n1.x);
-            n1.y = fma(c, x1.y, n1.y);
-            n2.x = fma(c, x2.x, n2.x);
-            n2.y = fma(c, x2.y, n2.y);
-            sF[lane * M + i - 1] = n1;
-            sF[lane * M + i] = n2;
-          }
+          double2 ny = cmul(s, y);
+          ny.x = fma(c, x.x, ny.x);
+          ny.y = fma(c, x.y, ny.y);
+          y = ny;
         }
-        wave_sync_lds();
-        // right rotation of columns i-1, i: zero the fill B[i][i-1]
+        // B[i][i] before step i
+        const double2 bii = bcast2(bd, i);
+        double2 b_i;
+        if (i == M - 1) {
+          b_i = bii;
+        } else {
+          // after left i+1: B[i][i] = c1 Bo[i][i], B[i][i+1] = c1 e_prev + s1 b_prev;
+          // after right i+1: B[i][i] = c21 B[i][i] - conj(s21) B[i][i+1]
+          double2 t = cmul(s1, b_prev);
+          t.x = fma(c1, e_prev.x, t.x);
+          t.y = fma(c1, e_prev.y, t.y);
+          b_i = cmul(make_double2(-s21.x, s21.y), t);
+          b_i.x = fma(c21 * c1, bii.x, b_i.x);
+          b_i.y = fma(c21 * c1, bii.y, b_i.y);
+        }
+        const double2 F = bcast2(carry, i - 1);  // B[i-1][i] before step i
+        // after left i: fill w = B[i][i-1] = -conj(s) B[i-1][i-1], u = B[i][i]
+        const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
+        const double2 w = cmul(ms, bcast2(bd, i - 1));
+        double2 u = cmul(ms, F);
+        u.x = fma(c, b_i.x, u.x);
+        u.y = fma(c, b_i.y, u.y);
         double c2;
         double2 s2;
-        givens_right(sB[i * ld + i - 1], sB[i * ld + i], c2, s2);
-        const double2 ms2 = make_double2(-s2.x, s2.y);  // -conj(s2)
-        if (lane < M) {
-          const int r = lane;
-          {
-            const double2 x1 = sA[r * ld + i - 1], x2 = sA[r * ld + i];
-            // [x1, x2] S = [c x1 - conj(s) x2, s x1 + c x2]
-            double2 n1 = cmul(ms2, x2), n2 = cmul(s2, x1);
-            n1.x = fma(c2, x1.x, n1.x);
-            n1.y = fma(c2, x1.y, n1.y);
-            n2.x = fma(c2, x2.x, n2.x);
-            n2.y = fma(c2, x2.y, n2.y);
-            sA[r * ld + i - 1] = n1;
-            sA[r * ld + i] = n2;
-          }
-          if (r <= i) {
-            const double2 x1 = sB[r * ld + i - 1], x2 = sB[r * ld + i];
-            double2 n1 = cmul(ms2, x2), n2 = cmul(s2, x1);
-            n1.x = fma(c2, x1.x, n1.x);
-            n1.y = fma(c2, x1.y, n1.y);
-            n2.x = fma(c2, x2.x, n2.x);
-            n2.y = fma(c2, x2.y, n2.y);
-            sB[r * ld + i - 1] = r == i ? make_double2(0.0, 0.0) : n1;
-            sB[r * ld + i] = n2;
-          }
+        givens_right(w, u, c2, s2);
+        if (lane == i) {
+          myc = c;
+          mys = s;
+          myc2 = c2;
+          mys2 = s2;
         }
-        if (lane == 0) {
-          rec[3 * nrec + 0] = c2;
-          rec[3 * nrec + 1] = s2.x;
-          rec[3 * nrec + 2] = s2.y;
-        }
-        ++nrec;
-        wave_sync_lds();
+        c1 = c;
+        s1 = s;
+        c21 = c2;
+        s21 = s2;
+        e_prev = F;
+        b_prev = b_i;
+        // the rows' carries: right rotation i on columns (i-1, i)
+        const double2 x1 = nx;
+        if (act && i - 2 >= 0) nx = sB[lane * ld + i - 2];
+        double2 nc = cmul(make_double2(-s2.x, s2.y), carry);
+        nc.x = fma(c2, x1.x, nc.x);
+        nc.y = fma(c2, x1.y, nc.y);
+        carry = nc;
+      }
+      // column j done: A[j+1][j] = y, zeros below
+      if (lane == j + 1) sA[(j + 1) * ld + j] = y;
+      if (lane >= j + 2 && lane < M) sA[lane * ld + j] = make_double2(0.0, 0.0);
+      // publish the rotations of this sweep (lane i holds rotation i)
+      if (lane >= j + 2 && lane < M) {
+        sRot[3 * lane] = myc;
+        sRot[3 * lane + 1] = mys.x;
+        sRot[3 * lane + 2] = mys.y;
+        sRot[3 * M + 3 * lane] = myc2;
+        sRot[3 * M + 3 * lane + 1] = mys2.x;
+        sRot[3 * M + 3 * lane + 2] = mys2.y;
+        const int k = nrec + (M - 1 - lane);  // recorded in the order applied
+        rec[3 * k] = myc2;
+        rec[3 * k + 1] = mys2.x;
+        rec[3 * k + 2] = mys2.y;
       }
     }
+    nrec += M - 2 - j;
+    __syncthreads();
+    // ---- left rotations: columns j+1.. of A (wave 0), of B (wave 1), F (wave 2)
+    auto regL = [&](int i, double& c, double2& s) {
+      c = bcast(myc, i);
+      s = bcast2(mys, i);
+    };
+    auto regR = [&](int i, double& c, double2& s) {
+      c = bcast(myc2, i);
+      s = bcast2(mys2, i);
+    };
+    auto ldsL = [&](int i, double& c, double2& s) {
+      c = sRot[3 * i];
+      s = make_double2(sRot[3 * i + 1], sRot[3 * i + 2]);
+    };
+    auto ldsR = [&](int i, double& c, double2& s) {
+      c = sRot[3 * M + 3 * i];
+      s = make_double2(sRot[3 * M + 3 * i + 1], sRot[3 * M + 3 * i + 2]);
+    };
+    if (wave == 0) {
+      if (j + 1 + lane < M) rot_chain<true>(sA + (j + 1 + lane), ld, M, j, regL, -1);
+    } else if (wave == 1) {
+      if (j + 1 + lane < M) rot_chain<true>(sB + (j + 1 + lane), ld, M, j, ldsL, -1);
+    } else if (wave == 2) {
+      if (lane < 3) rot_chain<true>(sF + lane * M, 1, M, j, ldsL, -1);
+    }
+    __syncthreads();
+    // ---- right rotations: rows of A (wave 0) and of B (wave 1), columns j+1..;
+    // B stays upper triangular: entries below the diagonal are written as
+    // exact zeros (the fills, cancelled to rounding by the bulk products)
+    if (wave == 0) {
+      if (lane < M) rot_chain<false>(sA + lane * ld, 1, M, j, regR, -1);
+    } else if (wave == 1) {
+      if (lane < M) rot_chain<false>(sB + lane * ld, 1, M, j, ldsR, lane);
+    }
+    __syncthreads();
   }
-  __syncthreads();
+
   // H and T column-major with exact zeros below the (sub)diagonal
   for (int e = tid; e < M * M; e += blockDim.x) {
     const int c = e / M, r = e % M;
@@ -285,32 +405,32 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(int M, const double2* __r
 // they share is carried in registers.
 __device__ __forceinline__ size_t wfrag_index(int row, int col, int Kp);
 
-__global__ __launch_bounds__(64) void k_pencil_z(int M, int Mp, int Kp,
-                                                 const double* __restrict__ rec,
-                                                 double2* __restrict__ Z,
-                                                 double2* __restrict__ Zf) {
+__global__ __launch_bounds__(64) void k_pencil_z(PencilJob one, const PencilJob* __restrict__ jobs) {
+  const PencilJob J = jobs ? jobs[blockIdx.x] : one;
+  const int M = J.M;
+  const PencilLayout Lo = pencil_layout(M);
+  const int Mp = Lo.Mp, Kp = Lo.Kp;
+  const double* rec = reinterpret_cast<const double*>(J.base + Lo.rec);
+  double2* Z = reinterpret_cast<double2*>(J.base + Lo.Z);
+  double2* Zf = reinterpret_cast<double2*>(J.base + Lo.Zf);
   extern __shared__ double2 sZ[];
   const int ld = M + 1;
   const int r = threadIdx.x;
+  const int nrot = M >= 3 ? (M - 1) * (M - 2) / 2 : 0;
+  double* sRec = reinterpret_cast<double*>(sZ + M * ld);
+  for (int e = r; e < 3 * nrot; e += blockDim.x) sRec[e] = rec[e];
+  __syncthreads();
   if (r < M) {
     for (int c = 0; c < M; ++c) sZ[r * ld + c] = make_double2(c == r ? 1.0 : 0.0, 0.0);
-    int idx = 0;
+    int idx0 = 0;
     for (int j = 0; j + 2 < M; ++j) {
-      double2 carry = sZ[r * ld + M - 1];
-      for (int i = M - 1; i >= j + 2; --i) {
-        const double c = rec[3 * idx], sx = rec[3 * idx + 1], sy = rec[3 * idx + 2];
-        ++idx;
-        const double2 s = make_double2(sx, sy), ms = make_double2(-sx, sy);
-        const double2 x1 = sZ[r * ld + i - 1], x2 = carry;
-        double2 n1 = cmul(ms, x2), n2 = cmul(s, x1);
-        n1.x = fma(c, x1.x, n1.x);
-        n1.y = fma(c, x1.y, n1.y);
-        n2.x = fma(c, x2.x, n2.x);
-        n2.y = fma(c, x2.y, n2.y);
-        sZ[r * ld + i] = n2;
-        carry = n1;
-      }
-      sZ[r * ld + j + 1] = carry;
+      auto rotz = [&](int i, double& c, double2& s) {
+        const int k = idx0 + (M - 1 - i);
+        c = sRec[3 * k];
+        s = make_double2(sRec[3 * k + 1], sRec[3 * k + 2]);
+      };
+      rot_chain<false>(sZ + r * ld, 1, M, j, rotz, -1);
+      idx0 += M - 2 - j;
     }
     for (int c = 0; c < M; ++c) Z[(size_t)r * M + c] = sZ[r * ld + c];
   }
@@ -333,11 +453,21 @@ __device__ __forceinline__ size_t wfrag_index(int row, int col, int Kp) {
   return ((size_t)rt * (Kp / 4) + kk) * 64 + l;
 }
 
-__global__ __launch_bounds__(256) void k_pencil_layout(
-    int M, int Mp, int Kp, const double2* __restrict__ KM, const double2* __restrict__ CM,
-    const double2* __restrict__ A0, const double2* __restrict__ G, const double2* __restrict__ g,
-    const double* __restrict__ E, const double* __restrict__ N0, double2* __restrict__ W,
-    double* __restrict__ S) {
+__global__ __launch_bounds__(256) void k_pencil_layout(PencilJob one,
+                                                       const PencilJob* __restrict__ jobs) {
+  const PencilJob J = jobs ? jobs[blockIdx.y] : one;
+  const int M = J.M;
+  const PencilLayout Lo = pencil_layout(M);
+  const int Mp = Lo.Mp, Kp = Lo.Kp;
+  const double2* KM = reinterpret_cast<const double2*>(J.KM);
+  const double2* CM = reinterpret_cast<const double2*>(J.CM);
+  const double2* A0 = reinterpret_cast<const double2*>(J.A0);
+  const double2* G = reinterpret_cast<const double2*>(J.G);
+  const double2* g = reinterpret_cast<const double2*>(J.g);
+  const double* E = J.E;
+  const double* N0 = J.N0;
+  double2* W = reinterpret_cast<double2*>(J.base + Lo.W);
+  double* S = reinterpret_cast<double*>(J.base + Lo.S);
   const int tid = threadIdx.x, b = blockIdx.x;
   const int ldG = 2 * M + 3;
   if (b < 4) {
@@ -370,33 +500,19 @@ __global__ __launch_bounds__(256) void k_pencil_layout(
   }
 }
 
-hipError_t pencil_reduce_launch(int M, const double* A0, const double* CM, const double* KM,
-                                const double* G, const double* g, const double* E,
-                                const double* N0, void* buf, hipStream_t st) {
-  const PencilLayout L = pencil_layout(M);
-  char* base = static_cast<char*>(buf);
-  double2* H = reinterpret_cast<double2*>(base + L.H);
-  double2* T = reinterpret_cast<double2*>(base + L.T);
-  double2* f = reinterpret_cast<double2*>(base + L.f);
-  double2* Z = reinterpret_cast<double2*>(base + L.Z);
-  double2* Zf = reinterpret_cast<double2*>(base + L.Zf);
-  double2* W = reinterpret_cast<double2*>(base + L.W);
-  double* S = reinterpret_cast<double*>(base + L.S);
-  double* rec = reinterpret_cast<double*>(base + L.rec);
-  const size_t lds1 = ((size_t)2 * M * (M + 1) + 4 * M) * sizeof(double2);
-  hipLaunchKernelGGL(k_pencil_reduce, dim3(1), dim3(256), lds1, st, M,
-                     reinterpret_cast<const double2*>(A0), reinterpret_cast<const double2*>(CM),
-                     reinterpret_cast<const double2*>(g), H, T, f, rec);
+hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
+                                hipStream_t st) {
+  const int M = maxM;
+  const size_t lds1 = ((size_t)2 * M * (M + 1) + 6 * M) * sizeof(double2);
+  hipLaunchKernelGGL(k_pencil_reduce, dim3(n_jobs), dim3(256), lds1, st, one, jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds2 = (size_t)M * (M + 1) * sizeof(double2);
-  hipLaunchKernelGGL(k_pencil_z, dim3(1), dim3(64), lds2, st, M, L.Mp, L.Kp, rec, Z, Zf);
+  const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 0;
+  const size_t lds2 = (size_t)M * (M + 1) * sizeof(double2) + nrot * 3 * sizeof(double);
+  hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(64), lds2, st, one, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pencil_layout, dim3(5), dim3(256), 0, st, M, L.Mp, L.Kp,
-                     reinterpret_cast<const double2*>(KM), reinterpret_cast<const double2*>(CM),
-                     reinterpret_cast<const double2*>(A0), reinterpret_cast<const double2*>(G),
-                     reinterpret_cast<const double2*>(g), E, N0, W, S);
+  hipLaunchKernelGGL(k_pencil_layout, dim3(5, n_jobs), dim3(256), 0, st, one, jobs);
   return hipGetLastError();
 }
 
@@ -438,23 +554,29 @@ __device__ __forceinline__ int pair_of(int i, int j) {
 
 }  // namespace
 
-struct PencilArgs {
-  int M, Mp, Kp, NT;
-  const double2* H;
-  const double2* T;
-  const double2* f;
-  const double2* Zf;
-  const double2* W;
-  const double* S;
-  double alpha, alpha_lb;
-};
 
 template <int L>
-__global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs P, const double* __restrict__ omega,
-                                                      int64_t n, double* __restrict__ out,
+__global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
+                                                      const PencilArgs* __restrict__ objs,
+                                                      const int4* __restrict__ items,
+                                                      const double* __restrict__ omega, int64_t n,
+                                                      double* __restrict__ out,
                                                       double* __restrict__ a_out,
                                                       int32_t* __restrict__ status) {
   extern __shared__ double2 lds[];
+  int64_t b0;
+  int cnt;
+  PencilArgs P;
+  if (items) {
+    const int4 it = items[blockIdx.x];
+    P = objs[it.x];
+    b0 = it.y;
+    cnt = it.z;
+  } else {
+    P = one;
+    b0 = (int64_t)blockIdx.x * kPenBatch;
+    cnt = (int)(n - b0 < kPenBatch ? n - b0 : kPenBatch);
+  }
   const int M = P.M, Kp = P.Kp, NT = P.NT;
   double2* sY = lds;                                                  // [3][Kp][16]
   double2* sEt = sY + 3 * Kp * kPenBatch;                             // [3][6][16]
@@ -463,13 +585,12 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs P, const double
   const int tid = threadIdx.x, wl = __lane_id(), wave = tid >> 6;
   const int ll = wl & (L - 1), base = wl - ll;
   constexpr int kSegs = 64 / L;
-  const int64_t b0 = (int64_t)blockIdx.x * kPenBatch;
 
   // ---- 1. Hessenberg solves, one frequency per segment ------------------
   for (int rnd = 0; rnd < L / 16; ++rnd) {
     const int wloc = rnd * 4 * kSegs + wave * kSegs + wl / L;
     const int64_t gi = b0 + wloc;
-    const bool valid = gi < n;
+    const bool valid = wloc < cnt;
     const double om = valid ? omega[gi] : 0.0;
     const bool act = ll < M;
     auto colval = [&](int k) -> double2 {  // (H - i w T)[ll][k]
@@ -678,7 +799,7 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs P, const double
   __syncthreads();
 
   // ---- 3. tensors and certificates, one thread per frequency ---------------
-  if (tid < kPenBatch && b0 + tid < n) {
+  if (tid < cnt) {
     const int w = tid;
     const int64_t gi = b0 + w;
     const double om = omega[gi];
@@ -720,39 +841,73 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs P, const double
     for (int it = tid; it < kPenBatch * 3 * M; it += blockDim.x) {
       const int w = it / (3 * M), rem = it % (3 * M), i = rem / M, r = rem % M;
       const int64_t gi = b0 + w;
-      if (gi < n)
+      if (w < cnt)
         reinterpret_cast<double2*>(a_out)[(gi * 3 + i) * M + r] = sY[(i * Kp + r) * kPenBatch + w];
     }
   }
 }
 
-hipError_t pencil_sweep_launch(const mpt_pencil& pen, const double* omega, int64_t n,
-                               double* out, double* a_out, int32_t* status, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int M = pen.M;
-  const PencilLayout Lo = pencil_layout(M);
+PencilArgs pencil_args(const mpt_pencil& pen) {
+  const PencilLayout Lo = pencil_layout(pen.M);
+  const char* base = reinterpret_cast<const char*>(pen.H);  // the buffer starts with H
   PencilArgs P;
-  P.M = M;
+  P.M = pen.M;
   P.Mp = Lo.Mp;
   P.Kp = Lo.Kp;
   P.NT = Lo.NT;
-  P.H = reinterpret_cast<const double2*>(pen.H);
-  P.T = reinterpret_cast<const double2*>(pen.T);
-  P.f = reinterpret_cast<const double2*>(pen.f);
-  P.Zf = reinterpret_cast<const double2*>(pen.Z) + (Lo.Zf - Lo.Z) / sizeof(double2);
-  P.W = reinterpret_cast<const double2*>(pen.W);
-  P.S = pen.S;
+  P.H = reinterpret_cast<const double2*>(base + Lo.H);
+  P.T = reinterpret_cast<const double2*>(base + Lo.T);
+  P.f = reinterpret_cast<const double2*>(base + Lo.f);
+  P.Zf = reinterpret_cast<const double2*>(base + Lo.Zf);
+  P.W = reinterpret_cast<const double2*>(base + Lo.W);
+  P.S = reinterpret_cast<const double*>(base + Lo.S);
   P.alpha = pen.alpha;
   P.alpha_lb = pen.alpha_lb;
-  const size_t lds = ((size_t)3 * Lo.Kp * kPenBatch + 18 * kPenBatch) * sizeof(double2) +
-                     (size_t)Lo.NT * 6 * kPenBatch * sizeof(double) + kPenBatch * sizeof(int);
+  return P;
+}
+
+static size_t sweep_lds(int Kp, int NT) {
+  return ((size_t)3 * Kp * kPenBatch + 18 * kPenBatch) * sizeof(double2) +
+         (size_t)NT * 6 * kPenBatch * sizeof(double) + kPenBatch * sizeof(int);
+}
+
+hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,
+                               double* a_out, int32_t* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = sweep_lds(P.Kp, P.NT);
   const dim3 grid((unsigned)((n + kPenBatch - 1) / kPenBatch)), block(256);
-  if (M <= 16)
-    hipLaunchKernelGGL((k_sweep_pencil<16>), grid, block, lds, st, P, omega, n, out, a_out, status);
-  else if (M <= 32)
-    hipLaunchKernelGGL((k_sweep_pencil<32>), grid, block, lds, st, P, omega, n, out, a_out, status);
+  const PencilArgs* no = nullptr;
+  const int4* ni = nullptr;
+  if (P.M <= 16)
+    hipLaunchKernelGGL((k_sweep_pencil<16>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
+                       status);
+  else if (P.M <= 32)
+    hipLaunchKernelGGL((k_sweep_pencil<32>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
+                       status);
   else
-    hipLaunchKernelGGL((k_sweep_pencil<64>), grid, block, lds, st, P, omega, n, out, a_out, status);
+    hipLaunchKernelGGL((k_sweep_pencil<64>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
+                       status);
+  return hipGetLastError();
+}
+
+hipError_t pencil_sweep_items_launch(int L, const PencilArgs* objs, const int4* items,
+                                     int n_items, const double* omega, double* out,
+                                     int32_t* status, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  // LDS for the largest object of the bucket: Kp <= L, NT <= L / 4 + 1
+  const size_t lds = sweep_lds(L, L / 4 + 1);
+  const dim3 grid((unsigned)n_items), block(256);
+  PencilArgs none{};
+  double* no_a = nullptr;
+  if (L == 16)
+    hipLaunchKernelGGL((k_sweep_pencil<16>), grid, block, lds, st, none, objs, items, omega,
+                       (int64_t)0, out, no_a, status);
+  else if (L == 32)
+    hipLaunchKernelGGL((k_sweep_pencil<32>), grid, block, lds, st, none, objs, items, omega,
+                       (int64_t)0, out, no_a, status);
+  else
+    hipLaunchKernelGGL((k_sweep_pencil<64>), grid, block, lds, st, none, objs, items, omega,
+                       (int64_t)0, out, no_a, status);
   return hipGetLastError();
 }
 

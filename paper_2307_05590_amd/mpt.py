@@ -72,6 +72,8 @@ def lib():
             "mpt_pencil_bytes": ([I32], S),
             "mpt_pencil_reduce": ([P, P, P, S, P], I32),
             "mpt_sweep_pencil": ([P, P, P, I64, P, P, P], I32),
+            "mpt_pencil_batched_bytes": ([P, I32], S),
+            "mpt_sweep_pencil_batched": ([P, P, I32, P, P, P, S, P, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -346,6 +348,27 @@ def mpt_sweep_batched(dic: Dictionary, tune=None, use_graph=True, out=None, stat
                                      _ptr(dic.omega), _ptr(out), _ptr(status),
                                      C.byref(t) if t is not None else None, int(bool(use_graph))))
     return out, status
+
+
+def mpt_sweep_pencil_batched(dic: Dictionary, out=None, status=None, buf=None):
+    """Pencil form for a dictionary: every object reduced and swept in one call
+    (equal to mpt_sweep_pencil object by object).  Returns (out, status, buf);
+    pass buf back to reuse the pencil storage."""
+    h = handle(dic.omega.device)
+    n = dic.omega.numel()
+    dev = dic.omega.device
+    if out is None:
+        out = torch.empty((n, 18), dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+    nb = lib().mpt_pencil_batched_bytes(dic._structs, dic.n_obj)
+    if nb == 0:
+        raise MptError("the pencil form takes 1 <= M <= 64 for every object")
+    if buf is None or buf.numel() < nb:
+        buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    h._check(lib().mpt_sweep_pencil_batched(h.h, dic._structs, dic.n_obj, dic.off, _ptr(dic.omega),
+                                            _ptr(buf), buf.numel(), _ptr(out), _ptr(status)))
+    return out, status, buf
 
 
 def mpt_sweep_adjoint(rom: Rom, omega, dout):

@@ -442,6 +442,20 @@ def test_batched_equals_per_object(mpt, use_graph):
             assert torch.equal(out[a:b], ref), o
 
 
+def test_pencil_batched_equals_per_object(mpt):
+    roms, omegas = _dictionary(mpt)
+    dic = mpt.Dictionary(roms, omegas)
+    out, st, buf = mpt.mpt_sweep_pencil_batched(dic)
+    out2, st2, _ = mpt.mpt_sweep_pencil_batched(dic, buf=buf)  # cached plan
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0
+    assert torch.equal(out, out2)
+    for o, (r, w) in enumerate(zip(roms, omegas)):
+        ref, s1 = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(r), w)
+        a, b = dic.offsets[o], dic.offsets[o + 1]
+        assert torch.equal(out[a:b], ref), o
+
+
 def test_batched_adjoint_equals_per_object(mpt):
     roms, omegas = _dictionary(mpt, 5)
     dic = mpt.Dictionary(roms, omegas)
