@@ -119,12 +119,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive"], default="plain")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
-    ap.add_argument("--sweep", choices=["lu", "pencil"], default="lu",
+    ap.add_argument("--sweep", choices=["lu", "pencil"], default=None,
                     help="per-frequency LU of the reduced system, or the Hessenberg-triangular "
-                         "pencil form (reduced once per step)")
+                         "pencil form (reduced once per step); default: lu for one object, "
+                         "pencil for the dictionary")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.sweep is None:
+        args.sweep = "pencil" if args.form == "batched" else "lu"
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
