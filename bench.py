@@ -117,7 +117,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive", "fmm"],
+                    default="plain")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
     ap.add_argument("--sweep", choices=["lu", "pencil"], default=None,
                     help="per-frequency LU of the reduced system, or the Hessenberg-triangular "
@@ -144,6 +145,8 @@ def main():
         copy_calibration(dev)
     if args.form == "adaptive":
         return bench_adaptive(args)
+    if args.form == "fmm":
+        return bench_fmm(args)
     if args.form != "plain":
         return bench_dictionary(args)
     t0 = time.time()
@@ -467,6 +470,90 @@ def bench_dictionary(args):
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TF, 4),
                      "traffic": None, "launch_ms": round(kernel_ms, 4)},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def fmm_bytes(N, nnz, M, n_omega):
+    """Algorithmic HBM bytes of the full matrix method over n_omega frequencies
+    in batches of 16: per batch U read once (16 N M), the CSR once, the N x 48
+    panels Q = U A and Y = K Q each written once and read once by the SpMM /
+    the dot pass (Q twice)."""
+    batches = (n_omega + 15) // 16
+    return batches * (16 * N * M + 12 * nnz + 4 * (N + 1) + 5 * 16 * N * 48)
+
+
+def bench_fmm(args):
+    """Full matrix method (tensors from the reconstructed field q = U a with
+    the full-order K and C_sigma) on the 48^3 workload, next to the reduced
+    matrix method (the sweep) on the same frequencies: the comparison of
+    methods the paper makes, on the stand-in."""
+    import torch
+
+    from paper_2307_05590_amd import mpt
+    from synth import make_problem
+
+    dev = torch.device("cuda:0")
+    log("generating the ellipsoid48 workload (full-order snapshots on the host) ...")
+    p = make_problem("ellipsoid48", verbose=True)
+    ops = p.ops
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    K = mpt.Csr.from_scipy(ops.K, dev)
+    c = T(ops.c, torch.float64)
+    w = T(p.w, torch.float64)
+    o = T(p.o, torch.float64) if np.any(p.o) else None
+    cond = T(ops.cond_idx, torch.int32)
+    n_fmm = 2000
+    omega = T(p.omega[:: p.omega.size // n_fmm][:n_fmm], torch.float64)
+    U, sig, M = mpt.mpt_pod_basis(T(p.D, torch.complex128), p.wl.tol_sigma, p.wl.m_cap)
+    rom = mpt.mpt_project(K, c, ops.eps_h, w, o, T(ops.vol, torch.float64), ops.alpha, U, cond,
+                          T(p.S, torch.float64))
+    out_mm, st, a = mpt.mpt_sweep(rom, omega, want_a=True)
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0
+    ws = None
+    for _ in range(args.warmup):
+        out, ws = mpt.mpt_tensors_fmm(K, c, w, U, cond, a, omega, rom.N0, ops.alpha, ws)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    e0, e1 = ev(), ev()
+    t1 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        out, ws = mpt.mpt_tensors_fmm(K, c, w, U, cond, a, omega, rom.N0, ops.alpha, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    ms = e0.elapsed_time(e1) / args.steps
+    m0, m1 = ev(), ev()
+    m0.record()
+    for _ in range(args.steps):
+        mpt.mpt_sweep(rom, omega)
+    m1.record()
+    torch.cuda.synchronize()
+    mm_ms = m0.elapsed_time(m1) / args.steps
+    # the two methods agree (normwise, per frequency and part)
+    o1, o2 = out.cpu().numpy(), out_mm.cpu().numpy()[:, :12]
+    agree = max(float(np.max(np.abs(o1[:, 6 * q:6 * q + 6] - o2[:, 6 * q:6 * q + 6]) /
+                             np.abs(o2[:, 6 * q:6 * q + 6]).max(1, keepdims=True))) for q in range(2))
+    n = omega.numel()
+    nbytes = fmm_bytes(ops.N, ops.K.nnz, M, n)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "MPT tensors/sec, full matrix method on q = U a (comparison method)",
+        "value": round(n / (elapsed / args.steps), 1), "unit": "tensors/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ellipsoid48: N={ops.N}, M={M}, {n} of the 1e4 output frequencies",
+                   "N": int(ops.N), "M": int(M), "n_omega": int(n)},
+        "reduced_matrix_method": {"ms": round(mm_ms, 4), "value": round(n / (mm_ms * 1e-3), 1),
+                                  "fmm_over_mm_time": round(ms / mm_ms, 1),
+                                  "max_rel_difference": agree},
+        "roofline": {"kernel": "full matrix method (U A on MFMA, K Q SpMM, row reductions)",
+                     "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": int(nbytes), "launch_ms": round(ms, 4)},
     }
     print(json.dumps(line), flush=True)
 

@@ -271,6 +271,25 @@ mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms_host, int 
                                     const int64_t* omega_off, const double* omega, void* buf,
                                     size_t bytes, double* out, int32_t* status);
 
+/* ----------------------------------------------------------------------
+ * Full matrix method (eqs. (Rmatrixmeth), (I_tensor_coeffs)) on the field
+ * reconstructed from reduced solutions, q_i = U a_i (§4): per frequency
+ *   R~_ij = N0_ij - a^3/4 Re(q_i^H K q_j),
+ *   I_ij  = w a^3/4 Re((q_i + w_i)^H C_sigma (q_j + w_j)),
+ * with the full-order K (CSR) and C_sigma = diag(c) (nonzero on the n_c
+ * conductor edges listed in cond).  Equal to the reduced matrix method of
+ * mpt_sweep up to rounding; its cost grows with N (the comparison method).
+ * K, c (N), w (N x 3 real, the sources w_i), U (N x M complex, ldU >= M),
+ * cond (n_c), a (n x 3 x M complex, e.g. mpt_sweep's a_out), omega (n),
+ * N0 (3 x 3) are device pointers; out (n x 12): R~ (11 12 13 22 23 33) then
+ * I.  ws: mpt_tensors_fmm_ws_size(N, M) bytes.  Asynchronous.
+ */
+size_t mpt_tensors_fmm_ws_size(int64_t N, int M);
+mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const double* c, const double* w,
+                           const double* U, int64_t ldU, int M, const int32_t* cond, int64_t n_c,
+                           const double* a, const double* omega, int64_t n, const double* N0,
+                           double alpha, double* out, void* ws, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -692,6 +692,32 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
   return MPT_OK;
 }
 
+// --------------------------------------------------- full matrix method
+extern "C" size_t mpt_tensors_fmm_ws_size(int64_t N, int M) {
+  if (N < 1 || M < 1) return 0;
+  return mpt::fmm_ws_size(N, M);
+}
+
+extern "C" mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const double* c,
+                                      const double* w, const double* U, int64_t ldU, int M,
+                                      const int32_t* cond, int64_t n_c, const double* a,
+                                      const double* omega, int64_t n, const double* N0,
+                                      double alpha, double* out, void* ws, size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(K && K->rowptr && K->colind && K->val && K->n >= 1, "bad K");
+  ARG(c && w && U && N0 && out && a && omega, "NULL pointer");
+  ARG(M >= 1 && ldU >= M, "bad M / ldU");
+  ARG(n_c >= 0 && (n_c == 0 || cond), "bad conductor list");
+  ARG(n >= 0 && alpha > 0.0, "bad n / alpha");
+  if (n == 0) return MPT_OK;
+  if (!ws || ws_bytes < mpt::fmm_ws_size(K->n, M))
+    return fail(h, MPT_E_NOMEM, "workspace smaller than mpt_tensors_fmm_ws_size");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(mpt::fmm_launch(*K, c, w, U, ldU, M, cond, n_c, a, omega, n, N0, alpha, out, ws,
+                         h->stream));
+  return MPT_OK;
+}
+
 // -------------------------------------------------------------- a5 select
 extern "C" mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n,
                                            const double* out, const double* snap, int n_snap,

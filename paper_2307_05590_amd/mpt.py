@@ -73,6 +73,8 @@ def lib():
             "mpt_pencil_reduce": ([P, P, P, S, P], I32),
             "mpt_sweep_pencil": ([P, P, P, I64, P, P, P], I32),
             "mpt_pencil_batched_bytes": ([P, I32], S),
+            "mpt_tensors_fmm_ws_size": ([I64, I32], S),
+            "mpt_tensors_fmm": ([P, P, P, P, P, I64, I32, P, I64, P, P, I64, P, D, P, P, S], I32),
             "mpt_sweep_pencil_batched": ([P, P, I32, P, P, P, S, P, P], I32),
         }
         for name, (args, res) in sig.items():
@@ -301,6 +303,23 @@ def mpt_sweep_pencil(pen: Pencil, omega: torch.Tensor, want_a: bool = False):
     h._check(lib().mpt_sweep_pencil(h.h, C.byref(pen.st), _ptr(omega), n, _ptr(out), _ptr(a),
                                     _ptr(st)))
     return (out, st, a) if want_a else (out, st)
+
+
+def mpt_tensors_fmm(K: Csr, c, w, U, cond, a, omega, N0, alpha, ws=None):
+    """Full matrix method on q = U a: (n x 12 [R~ | I], ws)."""
+    h = handle(U.device)
+    _dev_check(c, w, U, cond, a, omega, N0)
+    N, M = U.shape
+    n = omega.numel()
+    out = torch.empty((n, 12), dtype=torch.float64, device=U.device)
+    nb = lib().mpt_tensors_fmm_ws_size(N, M)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=U.device)
+    k = K.struct()
+    h._check(lib().mpt_tensors_fmm(h.h, C.byref(k), _ptr(c), _ptr(w), _ptr(U), M, M, _ptr(cond),
+                                   cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0), float(alpha),
+                                   _ptr(out), _ptr(ws), ws.numel()))
+    return out, ws
 
 
 def mpt_select_snapshots(omega, out, snap, n_star):

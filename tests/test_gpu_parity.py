@@ -217,6 +217,42 @@ def test_pencil_empty_bad_args_singular_deterministic(mpt):
     assert torch.equal(o1, o2)
 
 
+# ------------------------------------------- full matrix method on q = U a
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("ellipsoid16", 48), ("magnetic10", 12)])
+def test_fmm_matches_oracle_and_reduced_sweep(mpt, case, M):
+    """GPU FMM vs the oracle's FMM on the same reduced solutions, and vs the
+    reduced matrix method of the sweep (equal up to rounding)."""
+    c = getattr(_cases, case)()
+    fo = c.oracle_fo()
+    ops = c.ops
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, ops.cond_idx)
+    omega = np.logspace(1, 6, 37)  # three batches of 16 with a ragged tail
+    a = R.reduced_solve(rom_o, omega)  # (n, M, 3)
+    out, _ = mpt.mpt_tensors_fmm(mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64),
+                                 _dev(c.w, torch.float64), _dev(U, torch.complex128),
+                                 _dev(ops.cond_idx, torch.int32),
+                                 _dev(np.swapaxes(a, 1, 2), torch.complex128),
+                                 _dev(omega, torch.float64), _dev(rom_o["N0"], torch.float64),
+                                 fo.alpha)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    ref = np.empty((omega.size, 12))
+    for k, w_ in enumerate(omega):
+        Rt, I = R.tensors_fmm(fo, U @ a[k], w_, c.w, rom_o["N0"])
+        ref[k, :6], ref[k, 6:] = R.pack(Rt[None])[0], R.pack(I[None])[0]
+    sc = term_scales(ref, omega, rom_o["N0"], rom_o["E"], fo.alpha)
+    eR, eI = tensor_errors(out, ref, sc)
+    print(f"{case} M={M} FMM vs oracle: R~ {eR.max():.2e} I {eI.max():.2e}", flush=True)
+    assert eR.max() <= 1e-10 and eI.max() <= 1e-10
+    # the reduced matrix method (the GPU sweep) reaches the same tensors
+    sw, st = mpt.mpt_sweep(mpt.Rom.from_host(host, fo.alpha), _dev(omega, torch.float64))
+    torch.cuda.synchronize()
+    eR, eI = tensor_errors(sw.cpu().numpy()[:, :12], ref, sc)
+    print(f"{case} M={M} MM (GPU sweep) vs FMM: R~ {eR.max():.2e} I {eI.max():.2e}", flush=True)
+    assert eR.max() <= 1e-10 and eI.max() <= 1e-10
+
+
 # ------------------------------------------------------------ selection (a5)
 def test_select_matches_oracle(mpt):
     c = _cases.ellipsoid16()
