@@ -675,8 +675,7 @@ def bench_adaptive(args):
           enumerate(stages)}
     n_omega = omega.numel()
     value = n_omega / (elapsed / args.steps)
-    fpu = pencil_sweep_flops(M) if pencil else sweep_flops(M)
-    sweep_tf = fpu * n_omega / (ms["sweep"] * 1e-3) / 1e12
+    sweep_tf = sweep_flops(M) * n_omega / (ms["sweep"] * 1e-3) / 1e12
     log(f"final: {p.D.shape[1]} columns, M={M}, ms/step {1e3 * elapsed / args.steps:.3f}, {ms}")
     cpu = None if args.no_cpu else cpu_baseline(p, args.cpu_seconds)
     line = {
