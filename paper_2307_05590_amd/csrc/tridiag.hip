@@ -304,81 +304,57 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
   for (int i = lane; i < n; i += 64) Z[(size_t)j * n + i] = b[i];
 }
 
-// 5. two passes of block Gram-Schmidt over the rows of Z in decreasing
-// eigenvalue order (lam ascending, so row n-1 first): blocks of kMgsBlk rows
-// are first projected against every earlier block (coefficients, then the
-// update, each one parallel phase), then orthonormalised among themselves by
-// modified Gram-Schmidt.  Two passes ("twice is enough").
-constexpr int kMgsBlk = 16;
-
+// 5. two passes of modified Gram-Schmidt over the rows of Z in decreasing
+// eigenvalue order (lam ascending, so row n-1 first)
 template <bool SHARED>
 __global__ __launch_bounds__(kTriThreads) void k_tri_mgs(double* __restrict__ Zg, int n) {
   extern __shared__ double zs[];
-  __shared__ double cb[kMgsBlk * kTriMaxN];
   double* Z = SHARED ? zs : Zg;
   const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   const int nw = blockDim.x >> 6;
   if (SHARED)
     for (int i = tid; i < n * n; i += blockDim.x) Z[i] = Zg[i];
   __syncthreads();
-  // row of the vector at position s of the processing order
-  auto row = [&](int s) { return Z + (size_t)(n - 1 - s) * n; };
   for (int pass = 0; pass < 2; ++pass) {
-    for (int s0 = 0; s0 < n; s0 += kMgsBlk) {
-      const int bs = min(kMgsBlk, n - s0);
-      if (s0 > 0) {
-        // coefficients c[t][q] = <z_q, z_t> against the earlier rows q < s0
-        for (int e = tid; e < bs * s0; e += blockDim.x) {
-          const int t = e / s0, q = e % s0;
-          const double* zt = row(s0 + t);
-          const double* zq = row(q);
-          double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-          int i = 0;
-          for (; i + 3 < n; i += 4) {
-            d0 = fma(zq[i], zt[i], d0);
-            d1 = fma(zq[i + 1], zt[i + 1], d1);
-            d2 = fma(zq[i + 2], zt[i + 2], d2);
-            d3 = fma(zq[i + 3], zt[i + 3], d3);
-          }
-          for (; i < n; ++i) d0 = fma(zq[i], zt[i], d0);
-          cb[t * s0 + q] = (d0 + d1) + (d2 + d3);
+    for (int s = 0; s < n; ++s) {
+      const int j = n - 1 - s;
+      const double* zj = Z + (size_t)j * n;
+      double nr = 0.0;
+      for (int i = lane; i < n; i += 64) nr += zj[i] * zj[i];
+      const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
+      // rows jj = wave, wave + nw, ... below j, three at a time so that
+      // their reductions overlap
+      for (int jj = wave; jj < j; jj += 3 * nw) {
+        const int j1 = jj + nw, j2 = jj + 2 * nw;
+        double* z0 = Z + (size_t)jj * n;
+        double* z1 = Z + (size_t)(j1 < j ? j1 : jj) * n;
+        double* z2 = Z + (size_t)(j2 < j ? j2 : jj) * n;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          const double zi = zj[i];
+          d0 += zi * z0[i];
+          d1 += zi * z1[i];
+          d2 += zi * z2[i];
         }
-        __syncthreads();
-        // z_t -= sum_q c[t][q] z_q
-        for (int e = tid; e < bs * n; e += blockDim.x) {
-          const int t = e / n, i = e % n;
-          const double* ct = cb + t * s0;
-          double a0 = 0.0, a1 = 0.0;
-          int q = 0;
-          for (; q + 1 < s0; q += 2) {
-            a0 = fma(ct[q], row(q)[i], a0);
-            a1 = fma(ct[q + 1], row(q + 1)[i], a1);
-          }
-          if (q < s0) a0 = fma(ct[q], row(q)[i], a0);
-          row(s0 + t)[i] -= a0 + a1;
+        d0 = row16_sum(d0);
+        d1 = row16_sum(d1);
+        d2 = row16_sum(d2);
+        d0 = ((bcast(d0, 0) + bcast(d0, 16)) + (bcast(d0, 32) + bcast(d0, 48))) * inv * inv;
+        d1 = ((bcast(d1, 0) + bcast(d1, 16)) + (bcast(d1, 32) + bcast(d1, 48))) * inv * inv;
+        d2 = ((bcast(d2, 0) + bcast(d2, 16)) + (bcast(d2, 32) + bcast(d2, 48))) * inv * inv;
+        for (int i = lane; i < n; i += 64) {
+          const double zi = zj[i];
+          z0[i] -= d0 * zi;
+          if (j1 < j) z1[i] -= d1 * zi;
+          if (j2 < j) z2[i] -= d2 * zi;
         }
-        __syncthreads();
-      }
-      // modified Gram-Schmidt inside the block
-      for (int t = 0; t < bs; ++t) {
-        const double* zj = row(s0 + t);
-        double nr = 0.0;
-        for (int i = lane; i < n; i += 64) nr += zj[i] * zj[i];
-        const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
-        for (int u = t + 1 + wave; u < bs; u += nw) {
-          double* zu = row(s0 + u);
-          double d = 0.0;
-          for (int i = lane; i < n; i += 64) d += zj[i] * zu[i];
-          d = wave_sum(d) * inv * inv;
-          for (int i = lane; i < n; i += 64) zu[i] -= d * zj[i];
-        }
-        __syncthreads();
-        if (wave == t % nw)
-          for (int i = lane; i < n; i += 64) row(s0 + t)[i] *= inv;
-        // the scaled row is read again only after the next barrier
       }
       __syncthreads();
+      if (wave == j % nw)
+        for (int i = lane; i < n; i += 64) Z[(size_t)j * n + i] *= inv;
+      // the scaled row j is read again only after the next barrier
     }
+    __syncthreads();
   }
   if (SHARED)
     for (int i = tid; i < n * n; i += blockDim.x) Zg[i] = Z[i];
@@ -491,8 +467,7 @@ hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, vo
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   const size_t lds_z = (size_t)n * n * sizeof(double);
-  // the block coefficients take kMgsBlk * kTriMaxN doubles of static LDS
-  if (lds_z + (size_t)kMgsBlk * kTriMaxN * sizeof(double) <= kTriLdsBudget)
+  if (lds_z <= kTriLdsBudget)
     hipLaunchKernelGGL((k_tri_mgs<true>), dim3(1), dim3(kTriThreads), lds_z, st, Z, n);
   else
     hipLaunchKernelGGL((k_tri_mgs<false>), dim3(1), dim3(kTriThreads), 0, st, Z, n);
