@@ -532,6 +532,20 @@ def bench_fmm(args):
     m1.record()
     torch.cuda.synchronize()
     mm_ms = m0.elapsed_time(m1) / args.steps
+    # the integration-method analogue: sums over faces of the curl of q
+    curl = mpt.Csr.from_scipy(ops.grid.curl(), dev)
+    fw = T(1.0 / (ops.mu_f * ops.grid.h), torch.float64)
+    wsi = None
+    for _ in range(args.warmup):
+        out_im, wsi = mpt.mpt_tensors_im(curl, fw, c, w, U, cond, a, omega, rom.N0, ops.alpha, wsi)
+    torch.cuda.synchronize()
+    i0, i1 = ev(), ev()
+    i0.record()
+    for _ in range(args.steps):
+        out_im, wsi = mpt.mpt_tensors_im(curl, fw, c, w, U, cond, a, omega, rom.N0, ops.alpha, wsi)
+    i1.record()
+    torch.cuda.synchronize()
+    im_ms = i0.elapsed_time(i1) / args.steps
     # the two methods agree (normwise, per frequency and part)
     o1, o2 = out.cpu().numpy(), out_mm.cpu().numpy()[:, :12]
     agree = max(float(np.max(np.abs(o1[:, 6 * q:6 * q + 6] - o2[:, 6 * q:6 * q + 6]) /
@@ -550,6 +564,12 @@ def bench_fmm(args):
         "reduced_matrix_method": {"ms": round(mm_ms, 4), "value": round(n / (mm_ms * 1e-3), 1),
                                   "fmm_over_mm_time": round(ms / mm_ms, 1),
                                   "max_rel_difference": agree},
+        "integration_method": {"ms": round(im_ms, 4), "value": round(n / (im_ms * 1e-3), 1),
+                               "im_over_mm_time": round(im_ms / mm_ms, 1),
+                               "max_rel_difference_vs_mm": max(float(np.max(np.abs(
+                                   out_im.cpu().numpy()[:, 6 * q:6 * q + 6] - o2[:, 6 * q:6 * q + 6]) /
+                                   np.abs(o2[:, 6 * q:6 * q + 6]).max(1, keepdims=True)))
+                                   for q in range(2))},
         "roofline": {"kernel": "full matrix method (U A on MFMA, K Q SpMM, row reductions)",
                      "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,

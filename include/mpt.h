@@ -290,6 +290,18 @@ mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const double* c, cons
                            const double* a, const double* omega, int64_t n, const double* N0,
                            double alpha, double* out, void* ws, size_t ws_bytes);
 
+/* Integration-method analogue of eq. (NRI) on this grid: the same outputs,
+ * with R_ij = -a^3/4 Re sum_f face_w[f] conj((C q_i)_f) (C q_j)_f over the
+ * faces (curl: n_faces x N face-edge incidence, CSR with curl->n = n_faces
+ * rows; face_w = 1/(mu_f h)) and I as in mpt_tensors_fmm.  N is the number of
+ * edges (rows of U).  ws: mpt_tensors_im_ws_size(N, n_faces, M) bytes. */
+size_t mpt_tensors_im_ws_size(int64_t N, int64_t n_faces, int M);
+mpt_status mpt_tensors_im(mpt_handle h, const mpt_csr* curl, const double* face_w,
+                          const double* c, const double* w, const double* U, int64_t N,
+                          int64_t ldU, int M, const int32_t* cond, int64_t n_c, const double* a,
+                          const double* omega, int64_t n, const double* N0, double alpha,
+                          double* out, void* ws, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

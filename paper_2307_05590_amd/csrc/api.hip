@@ -695,7 +695,33 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
 // --------------------------------------------------- full matrix method
 extern "C" size_t mpt_tensors_fmm_ws_size(int64_t N, int M) {
   if (N < 1 || M < 1) return 0;
-  return mpt::fmm_ws_size(N, M);
+  return mpt::fmm_ws_size(N, N, M);
+}
+
+extern "C" size_t mpt_tensors_im_ws_size(int64_t N, int64_t n_faces, int M) {
+  if (N < 1 || n_faces < 1 || M < 1) return 0;
+  return mpt::fmm_ws_size(N, n_faces, M);
+}
+
+extern "C" mpt_status mpt_tensors_im(mpt_handle h, const mpt_csr* curl, const double* face_w,
+                                     const double* c, const double* w, const double* U,
+                                     int64_t N, int64_t ldU, int M, const int32_t* cond,
+                                     int64_t n_c, const double* a, const double* omega, int64_t n,
+                                     const double* N0, double alpha, double* out, void* ws,
+                                     size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(curl && curl->rowptr && curl->colind && curl->val && curl->n >= 1, "bad curl");
+  ARG(face_w && c && w && U && N0 && out && a && omega, "NULL pointer");
+  ARG(N >= 1 && M >= 1 && ldU >= M, "bad N / M / ldU");
+  ARG(n_c >= 0 && (n_c == 0 || cond), "bad conductor list");
+  ARG(n >= 0 && alpha > 0.0, "bad n / alpha");
+  if (n == 0) return MPT_OK;
+  if (!ws || ws_bytes < mpt::fmm_ws_size(N, curl->n, M))
+    return fail(h, MPT_E_NOMEM, "workspace smaller than mpt_tensors_im_ws_size");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(mpt::fmm_launch(*curl, face_w, c, w, U, N, ldU, M, cond, n_c, a, omega, n, N0, alpha,
+                         out, ws, h->stream));
+  return MPT_OK;
 }
 
 extern "C" mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const double* c,
@@ -710,11 +736,11 @@ extern "C" mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const doub
   ARG(n_c >= 0 && (n_c == 0 || cond), "bad conductor list");
   ARG(n >= 0 && alpha > 0.0, "bad n / alpha");
   if (n == 0) return MPT_OK;
-  if (!ws || ws_bytes < mpt::fmm_ws_size(K->n, M))
+  if (!ws || ws_bytes < mpt::fmm_ws_size(K->n, K->n, M))
     return fail(h, MPT_E_NOMEM, "workspace smaller than mpt_tensors_fmm_ws_size");
   HIP_OK(hipSetDevice(h->device));
-  HIP_OK(mpt::fmm_launch(*K, c, w, U, ldU, M, cond, n_c, a, omega, n, N0, alpha, out, ws,
-                         h->stream));
+  HIP_OK(mpt::fmm_launch(*K, nullptr, c, w, U, K->n, ldU, M, cond, n_c, a, omega, n, N0, alpha,
+                         out, ws, h->stream));
   return MPT_OK;
 }
 

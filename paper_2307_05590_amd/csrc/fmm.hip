@@ -2,7 +2,9 @@
 // (I_tensor_coeffs) evaluated with the full-order operators on the field
 // reconstructed from the reduced solutions, q_i = U a_i (§4).  Up to rounding
 // it equals the reduced matrix method; it is the comparison point whose cost
-// grows with N instead of M.
+// grows with N instead of M.  The integration-method analogue on this grid
+// (sums over faces, eq. (NRI)) takes the same path with the curl: R from
+// sum_f w_f Re(conj((C q_i)_f) (C q_j)_f), w_f = 1/(mu_f h).
 //
 // Per batch of kFmmBatch frequencies (3 kFmmBatch columns):
 //   V = the batch's a vectors as an M x 3B matrix (transpose of the n x 3 x M
@@ -36,10 +38,12 @@ __global__ void k_fmm_gather(const double2* __restrict__ a, int64_t w0, int nb, 
   V[e] = b < nb ? a[((w0 + b) * 3 + i) * M + m] : make_double2(0.0, 0.0);
 }
 
-// partial[chunk][b][p] = sum over the chunk's rows of Re(conj(Q[r][3b+i]) Y[r][3b+j]);
+// partial[chunk][b][p] = sum over the chunk's rows of
+//   wt[r] Re(conj(Q[r][3b+i]) Y[r][3b+j])   (wt == nullptr: weight 1);
 // 256 threads: 16 frequencies x 16 row lanes
 __global__ __launch_bounds__(256) void k_fmm_dots(const double2* __restrict__ Q,
-                                                  const double2* __restrict__ Y, int64_t N,
+                                                  const double2* __restrict__ Y,
+                                                  const double* __restrict__ wt, int64_t N,
                                                   int64_t rows_per_chunk,
                                                   double* __restrict__ partial) {
   __shared__ double red[6][256];
@@ -58,11 +62,11 @@ __global__ __launch_bounds__(256) void k_fmm_dots(const double2* __restrict__ Q,
       qv[i] = q[i];
       yv[i] = y[i];
     }
+    const double f = wt ? wt[r] : 1.0;
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       const double2 x = qv[kPi6[p]], z = yv[kPj6[p]];
-      acc[p] = fma(x.x, z.x, acc[p]);
-      acc[p] = fma(x.y, z.y, acc[p]);
+      acc[p] = fma(f, fma(x.x, z.x, x.y * z.y), acc[p]);
     }
   }
 #pragma unroll
@@ -131,27 +135,33 @@ __global__ void k_fmm_finish(const double* __restrict__ partial, int chunks,
   out[(w0 + b) * 12 + 6 + p] = 0.25 * a3 * om * cpart[b * 6 + p];
 }
 
-size_t fmm_ws_size(int64_t N, int M) {
-  const size_t panel = (size_t)N * kFmmCols * sizeof(double2);
-  return 2 * ((panel + 255) & ~size_t(255)) + (((size_t)M * kFmmCols * 16 + 255) & ~size_t(255)) +
+size_t fmm_ws_size(int64_t N, int64_t rows_R, int M) {
+  const size_t panel_q = (((size_t)N * kFmmCols * sizeof(double2)) + 255) & ~size_t(255);
+  const size_t panel_y = (((size_t)rows_R * kFmmCols * sizeof(double2)) + 255) & ~size_t(255);
+  return panel_q + panel_y + (((size_t)M * kFmmCols * 16 + 255) & ~size_t(255)) +
          (size_t)kFmmChunks * kFmmBatch * 6 * 8 + 256 + kFmmBatch * 6 * 8;
 }
 
-hipError_t fmm_launch(const mpt_csr& K, const double* c, const double* w, const double* U,
-                      int64_t ldU, int M, const int32_t* cond, int64_t nc, const double* a,
-                      const double* omega, int64_t n, const double* N0, double alpha,
-                      double* out, void* ws, hipStream_t st) {
-  const int64_t N = K.n;
-  const size_t panel = ((size_t)N * kFmmCols * sizeof(double2) + 255) & ~size_t(255);
+// R from Y = Op q: the FMM (Op = K, N x N, rows reduced with q) or the
+// integration-method analogue (Op = the curl, faces x N, rows weighted by wf
+// and reduced with Y itself)
+hipError_t fmm_launch(const mpt_csr& Op, const double* wf, const double* c, const double* w,
+                      const double* U, int64_t N, int64_t ldU, int M, const int32_t* cond,
+                      int64_t nc, const double* a, const double* omega, int64_t n,
+                      const double* N0, double alpha, double* out, void* ws, hipStream_t st) {
+  const int64_t rows_R = Op.n;
+  const size_t panel_q = (((size_t)N * kFmmCols * sizeof(double2)) + 255) & ~size_t(255);
+  const size_t panel_y = (((size_t)rows_R * kFmmCols * sizeof(double2)) + 255) & ~size_t(255);
   char* p = static_cast<char*>(ws);
   double2* Q = reinterpret_cast<double2*>(p);
-  double2* Y = reinterpret_cast<double2*>(p + panel);
-  double2* V = reinterpret_cast<double2*>(p + 2 * panel);
-  double* partial = reinterpret_cast<double*>(p + 2 * panel +
+  double2* Y = reinterpret_cast<double2*>(p + panel_q);
+  double2* V = reinterpret_cast<double2*>(p + panel_q + panel_y);
+  double* partial = reinterpret_cast<double*>(p + panel_q + panel_y +
                                               (((size_t)M * kFmmCols * 16 + 255) & ~size_t(255)));
   double* cpart = partial + (size_t)kFmmChunks * kFmmBatch * 6;
-  const int64_t rpc = (N + kFmmChunks - 1) / kFmmChunks;
-  const int chunks = (int)((N + rpc - 1) / rpc);
+  const int64_t rpc = (rows_R + kFmmChunks - 1) / kFmmChunks;
+  const int chunks = (int)((rows_R + rpc - 1) / rpc);
+  const double2* left = wf ? Y : Q;  // IM: |C q|^2 weighted; FMM: q^H (K q)
   const double a3 = alpha * alpha * alpha;
   for (int64_t w0 = 0; w0 < n; w0 += kFmmBatch) {
     const int nb = (int)(n - w0 < kFmmBatch ? n - w0 : kFmmBatch);
@@ -162,10 +172,11 @@ hipError_t fmm_launch(const mpt_csr& K, const double* c, const double* w, const 
     e = rotate_launch(U, ldU, N, M, reinterpret_cast<const double*>(V), kFmmCols, kFmmCols,
                       reinterpret_cast<double*>(Q), kFmmCols, st);
     if (e != hipSuccess) return e;
-    e = spmm_launch(K, reinterpret_cast<const double*>(Q), kFmmCols, kFmmCols,
+    e = spmm_launch(Op, reinterpret_cast<const double*>(Q), kFmmCols, kFmmCols,
                     reinterpret_cast<double*>(Y), kFmmCols, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fmm_dots, dim3(chunks), dim3(256), 0, st, Q, Y, N, rpc, partial);
+    hipLaunchKernelGGL(k_fmm_dots, dim3(chunks), dim3(256), 0, st, left, Y, wf, rows_R, rpc,
+                       partial);
     hipLaunchKernelGGL(k_fmm_cond, dim3(kFmmBatch), dim3(256), 0, st, Q, w, c, cond, nc, cpart);
     hipLaunchKernelGGL(k_fmm_finish, dim3(1), dim3(kFmmBatch * 6), 0, st, partial, chunks, cpart,
                        omega, N0, a3, w0, nb, out);

@@ -67,11 +67,12 @@ hipError_t jacobi_launch(double* A, int n, double* V, double* lam, int* info, vo
                          int max_sweeps, double tol, double floor_rel, hipStream_t st);
 
 // fmm.hip : full matrix method on the reconstructed field q = U a
-size_t fmm_ws_size(int64_t N, int M);
-hipError_t fmm_launch(const mpt_csr& K, const double* c, const double* w, const double* U,
-                      int64_t ldU, int M, const int32_t* cond, int64_t nc, const double* a,
-                      const double* omega, int64_t n, const double* N0, double alpha,
-                      double* out, void* ws, hipStream_t st);
+//   Op: K (N x N; wf == nullptr) or the curl (faces x N) with face weights wf
+size_t fmm_ws_size(int64_t N, int64_t rows_R, int M);
+hipError_t fmm_launch(const mpt_csr& Op, const double* wf, const double* c, const double* w,
+                      const double* U, int64_t N, int64_t ldU, int M, const int32_t* cond,
+                      int64_t nc, const double* a, const double* omega, int64_t n,
+                      const double* N0, double alpha, double* out, void* ws, hipStream_t st);
 
 // pencil.hip : Hessenberg-triangular form of (A0, C_M) and the sweep on it.
 //   Byte offsets of the parts of one object's pencil buffer.

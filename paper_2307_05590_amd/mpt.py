@@ -75,6 +75,9 @@ def lib():
             "mpt_pencil_batched_bytes": ([P, I32], S),
             "mpt_tensors_fmm_ws_size": ([I64, I32], S),
             "mpt_tensors_fmm": ([P, P, P, P, P, I64, I32, P, I64, P, P, I64, P, D, P, P, S], I32),
+            "mpt_tensors_im_ws_size": ([I64, I64, I32], S),
+            "mpt_tensors_im": ([P, P, P, P, P, P, I64, I64, I32, P, I64, P, P, I64, P, D, P, P, S],
+                               I32),
             "mpt_sweep_pencil_batched": ([P, P, I32, P, P, P, S, P, P], I32),
         }
         for name, (args, res) in sig.items():
@@ -319,6 +322,23 @@ def mpt_tensors_fmm(K: Csr, c, w, U, cond, a, omega, N0, alpha, ws=None):
     h._check(lib().mpt_tensors_fmm(h.h, C.byref(k), _ptr(c), _ptr(w), _ptr(U), M, M, _ptr(cond),
                                    cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0), float(alpha),
                                    _ptr(out), _ptr(ws), ws.numel()))
+    return out, ws
+
+
+def mpt_tensors_im(curl: Csr, face_w, c, w, U, cond, a, omega, N0, alpha, ws=None):
+    """Integration-method analogue (sums over faces of the curl): (n x 12, ws)."""
+    h = handle(U.device)
+    _dev_check(face_w, c, w, U, cond, a, omega, N0)
+    N, M = U.shape
+    n = omega.numel()
+    out = torch.empty((n, 12), dtype=torch.float64, device=U.device)
+    nb = lib().mpt_tensors_im_ws_size(N, curl.n, M)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=U.device)
+    k = curl.struct()
+    h._check(lib().mpt_tensors_im(h.h, C.byref(k), _ptr(face_w), _ptr(c), _ptr(w), _ptr(U), N, M,
+                                  M, _ptr(cond), cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0),
+                                  float(alpha), _ptr(out), _ptr(ws), ws.numel()))
     return out, ws
 
 

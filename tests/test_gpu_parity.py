@@ -253,6 +253,34 @@ def test_fmm_matches_oracle_and_reduced_sweep(mpt, case, M):
     assert eR.max() <= 1e-10 and eI.max() <= 1e-10
 
 
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("magnetic10", 12)])
+def test_im_matches_oracle_mesh_sums(mpt, case, M):
+    """Integration-method analogue on the GPU (sums over faces of the curl of
+    q = U a) vs the oracle's explicit mesh sums on the same reduced solutions."""
+    c = getattr(_cases, case)()
+    fo = c.oracle_fo()
+    ops = c.ops
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, ops.cond_idx)
+    omega = np.logspace(1, 6, 21)
+    a = R.reduced_solve(rom_o, omega)
+    curl = ops.grid.curl()
+    fw = 1.0 / (ops.mu_f * ops.grid.h)
+    out, _ = mpt.mpt_tensors_im(mpt.Csr.from_scipy(curl), _dev(fw, torch.float64),
+                                _dev(ops.c, torch.float64), _dev(c.w, torch.float64),
+                                _dev(U, torch.complex128), _dev(ops.cond_idx, torch.int32),
+                                _dev(np.swapaxes(a, 1, 2), torch.complex128),
+                                _dev(omega, torch.float64), _dev(rom_o["N0"], torch.float64),
+                                fo.alpha)
+    torch.cuda.synchronize()
+    Rt, I = R.tensors_mesh(fo, U, a, omega, c.w, rom_o["N0"])
+    ref = np.concatenate([R.pack(Rt), R.pack(I)], 1)
+    sc = term_scales(ref, omega, rom_o["N0"], rom_o["E"], fo.alpha)
+    eR, eI = tensor_errors(out.cpu().numpy(), ref, sc)
+    print(f"{case} M={M} IM vs oracle mesh sums: R~ {eR.max():.2e} I {eI.max():.2e}", flush=True)
+    assert eR.max() <= 1e-10 and eI.max() <= 1e-10
+
+
 # ------------------------------------------------------------ selection (a5)
 def test_select_matches_oracle(mpt):
     c = _cases.ellipsoid16()
