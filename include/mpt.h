@@ -174,6 +174,17 @@ mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n, co
                                 const double* snap, int n_snap, int n_star,
                                 double* new_omega, double* lambda, double* Lambda_max);
 
+/* Threshold variant of the selection (the alternative to a fixed N_* that
+ * §4.3 names, after Hesthaven et al.): every interval whose maximum reaches
+ * theta * Lambda (0 < theta <= 1) gives its argmax, at most one per interval,
+ * in the rank order of mpt_select_snapshots.  new_omega (n_snap - 1, device;
+ * NaN after the last chosen), n_new (1 int32, device) the number chosen;
+ * lambda and Lambda_max as in mpt_select_snapshots. */
+mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double* omega, int64_t n,
+                                          const double* out, const double* snap, int n_snap,
+                                          double theta, double* new_omega, int32_t* n_new,
+                                          double* lambda, double* Lambda_max);
+
 /* ----------------------------------------------------------------------
  * a6  Batched dictionary sweep: one persistent launch (captured in a HIP
  * graph when use_graph != 0) over many objects with their own M, omega

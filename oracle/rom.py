@@ -240,6 +240,20 @@ def select_snapshots(omega, delta, snap_omega, n_star):
     return omega[arg[chosen]], float(np.max(lam)), lam
 
 
+def select_snapshots_threshold(omega, delta, snap_omega, theta):
+    """Threshold variant of the selection step (§4.3, after Hesthaven et al.):
+    instead of a fixed N_*, every interval whose maximum certificate reaches
+    theta * Lambda (0 < theta <= 1) contributes one new snapshot at the omega
+    attaining its maximum, at most one per interval as in Algorithm 1.  The
+    intervals, ties and rank order are those of select_snapshots.
+    Returns (new omegas in rank order, Lambda, Lambda_n per interval)."""
+    omega = np.asarray(omega, float)
+    _, lam_max, lam = select_snapshots(omega, delta, snap_omega, 0)
+    keep = [n for n in range(lam.size) if np.isfinite(lam[n]) and lam[n] >= theta * lam_max]
+    new, _, _ = select_snapshots(omega, delta, snap_omega, len(keep))
+    return new, lam_max, lam
+
+
 # ---------------------------------------------------- sensitivities (a7)
 def forward_sensitivity(rom, omega, alpha, wR, wI):
     """dL/domega_k and dL/dsigma for L = sum_k sum_pairs wR R~ + wI I (weights per

@@ -760,6 +760,23 @@ extern "C" mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, in
   return MPT_OK;
 }
 
+extern "C" mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double* omega, int64_t n,
+                                                     const double* out, const double* snap,
+                                                     int n_snap, double theta, double* new_omega,
+                                                     int32_t* n_new, double* lambda,
+                                                     double* Lambda_max) {
+  if (!h) return MPT_E_ARG;
+  ARG(omega && out && snap && new_omega && n_new && lambda && Lambda_max, "NULL pointer");
+  ARG(n >= 1 && n_snap >= 2, "bad sizes");
+  ARG(theta > 0.0 && theta <= 1.0, "theta must be in (0, 1]");
+  HIP_OK(hipSetDevice(h->device));
+  mpt_status s = ensure_scr(h, align256((size_t)n_snap * 8));
+  if (s != MPT_OK) return s;
+  HIP_OK(select_threshold_launch(omega, n, out, snap, n_snap, theta, new_omega, n_new, lambda,
+                                 Lambda_max, reinterpret_cast<int64_t*>(h->scr), h->stream));
+  return MPT_OK;
+}
+
 // -------------------------------------------------- a6/a7 batched launches
 namespace {
 

@@ -26,6 +26,11 @@ hipError_t select_launch(const double* omega, int64_t n, const double* out, cons
                          int n_snap, int n_star, double* new_omega, double* lambda,
                          double* Lambda_max, int64_t* arg_ws, hipStream_t st);
 
+hipError_t select_threshold_launch(const double* omega, int64_t n, const double* out,
+                                   const double* snap, int n_snap, double theta,
+                                   double* new_omega, int32_t* n_new, double* lambda,
+                                   double* Lambda_max, int64_t* arg_ws, hipStream_t st);
+
 // spmm.hip
 hipError_t spmm_launch(const mpt_csr& K, const double* U, int64_t ldU, int M, double* Y,
                        int64_t ldY, hipStream_t st);

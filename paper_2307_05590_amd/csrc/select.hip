@@ -88,6 +88,60 @@ __global__ __launch_bounds__(64) void k_rank(const double* __restrict__ omega,
   }
 }
 
+// threshold variant: every interval j with lambda[j] >= theta * Lambda gives
+// omega[arg[j]] at its rank (descending lambda, ties lower j); one thread per
+// interval; new_omega has n_int entries, NaN after the last chosen
+__global__ __launch_bounds__(256) void k_rank_threshold(const double* __restrict__ omega,
+                                                        const double* __restrict__ lambda,
+                                                        const int64_t* __restrict__ arg,
+                                                        int n_int, double theta,
+                                                        double* __restrict__ new_omega,
+                                                        int32_t* __restrict__ n_new,
+                                                        double* __restrict__ Lmax) {
+  __shared__ double gmax_s;
+  __shared__ int count_s;
+  if (threadIdx.x == 0) {
+    double gmax = -INFINITY;
+    for (int j = 0; j < n_int; ++j)
+      if (arg[j] >= 0 && lambda[j] > gmax) gmax = lambda[j];
+    gmax_s = gmax;
+    int cnt = 0;
+    for (int j = 0; j < n_int; ++j)
+      if (arg[j] >= 0 && lambda[j] >= theta * gmax) ++cnt;
+    count_s = cnt;
+    *Lmax = gmax;
+    *n_new = cnt;
+  }
+  __syncthreads();
+  const double thr = theta * gmax_s;
+  for (int j = threadIdx.x; j < n_int; j += blockDim.x) {
+    const bool q = arg[j] >= 0 && lambda[j] >= thr;
+    if (q) {
+      int rank = 0;
+      for (int k = 0; k < n_int; ++k)
+        if (arg[k] >= 0 && lambda[k] >= thr &&
+            (lambda[k] > lambda[j] || (lambda[k] == lambda[j] && k < j)))
+          ++rank;
+      new_omega[rank] = omega[arg[j]];
+    }
+  }
+  for (int r = count_s + threadIdx.x; r < n_int; r += blockDim.x) new_omega[r] = NAN;
+}
+
+hipError_t select_threshold_launch(const double* omega, int64_t n, const double* out,
+                                   const double* snap, int n_snap, double theta,
+                                   double* new_omega, int32_t* n_new, double* lambda,
+                                   double* Lambda_max, int64_t* arg_ws, hipStream_t st) {
+  const int n_int = n_snap - 1;
+  hipLaunchKernelGGL(k_interval_max, dim3(n_int), dim3(256), 0, st, omega, n, out, snap, n_snap,
+                     lambda, arg_ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_threshold, dim3(1), dim3(256), 0, st, omega, lambda, arg_ws, n_int,
+                     theta, new_omega, n_new, Lambda_max);
+  return hipGetLastError();
+}
+
 hipError_t select_launch(const double* omega, int64_t n, const double* out, const double* snap,
                          int n_snap, int n_star, double* new_omega, double* lambda,
                          double* Lambda_max, int64_t* arg_ws, hipStream_t st) {

@@ -75,6 +75,7 @@ def lib():
             "mpt_pencil_batched_bytes": ([P, I32], S),
             "mpt_tensors_fmm_ws_size": ([I64, I32], S),
             "mpt_tensors_fmm": ([P, P, P, P, P, I64, I32, P, I64, P, P, I64, P, D, P, P, S], I32),
+            "mpt_select_snapshots_threshold": ([P, P, I64, P, P, I32, D, P, P, P, P], I32),
             "mpt_tensors_im_ws_size": ([I64, I64, I32], S),
             "mpt_tensors_im": ([P, P, P, P, P, P, I64, I64, I32, P, I64, P, P, I64, P, D, P, P, S],
                                I32),
@@ -353,6 +354,23 @@ def mpt_select_snapshots(omega, out, snap, n_star):
     h._check(lib().mpt_select_snapshots(h.h, _ptr(omega), omega.numel(), _ptr(out), _ptr(snap),
                                         snap.numel(), n_star, _ptr(new), _ptr(lam), _ptr(Lmax)))
     return new, lam, Lmax
+
+
+def mpt_select_snapshots_threshold(omega, out, snap, theta):
+    """Threshold variant: (new omegas (n_snap - 1, NaN-padded), count, per-interval
+    Lambda_n, Lambda)."""
+    h = handle(omega.device)
+    _dev_check(omega, out, snap)
+    dev = omega.device
+    ni = snap.numel() - 1
+    new = torch.empty(ni, dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    lam = torch.empty(ni, dtype=torch.float64, device=dev)
+    Lmax = torch.empty(1, dtype=torch.float64, device=dev)
+    h._check(lib().mpt_select_snapshots_threshold(h.h, _ptr(omega), omega.numel(), _ptr(out),
+                                                  _ptr(snap), snap.numel(), float(theta), _ptr(new),
+                                                  _ptr(cnt), _ptr(lam), _ptr(Lmax)))
+    return new, cnt, lam, Lmax
 
 
 class Dictionary:

@@ -300,6 +300,27 @@ def test_select_matches_oracle(mpt):
     assert np.array_equal(lam.cpu().numpy(), ref_lam)
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.7, 0.3, 1e-6])
+def test_select_threshold_matches_oracle(mpt, theta):
+    rng = np.random.default_rng(int(theta * 1000) + 5)
+    n = 3000
+    om = np.sort(rng.uniform(10.0, 1e6, n))
+    out = np.zeros((n, 18))
+    out[:, 12:] = rng.uniform(0.0, 1.0, (n, 6))
+    out[100:140, 12:] = 2.0  # a tie block across an interval
+    snaps = np.sort(np.r_[rng.uniform(10.0, 1e6, 9), 5.0, 2e6])
+    new, cnt, lam, L = mpt.mpt_select_snapshots_threshold(_dev(om, torch.float64),
+                                                          _dev(out, torch.float64),
+                                                          _dev(snaps, torch.float64), theta)
+    torch.cuda.synchronize()
+    ref, Lr, lam_r = R.select_snapshots_threshold(om, out[:, 12:], snaps, theta)
+    k = int(cnt.item())
+    assert k == ref.size and float(L.item()) == Lr
+    assert np.array_equal(new.cpu().numpy()[:k], ref)
+    assert np.all(np.isnan(new.cpu().numpy()[k:]))
+    assert np.array_equal(lam.cpu().numpy(), lam_r)
+
+
 def test_select_ties_and_empty_intervals(mpt):
     omega = np.arange(1.0, 11.0)
     out = np.zeros((10, 18))

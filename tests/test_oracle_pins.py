@@ -343,3 +343,35 @@ def test_forward_sensitivity_matches_central_differences():
     fd_s = (L(om, 1 + 1e-6) - L(om, 1 - 1e-6)) / 2e-6
     assert abs(fd_s - ds) <= 1e-6 * abs(ds)
     assert abs(ds - np.sum(om * dw)) <= 1e-10 * abs(ds)
+
+
+def test_select_threshold_variant_limits():
+    """theta = 1 keeps exactly the interval of the global maximum of Delta
+    over all frequencies; theta -> 0 keeps every non-empty interval, in the
+    rank order of the fixed-N_* selection with N_* = number of intervals;
+    in between, the kept intervals are exactly those whose maximum reaches
+    theta * Lambda (checked by brute force over the output frequencies)."""
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        om = np.sort(rng.uniform(1.0, 100.0, 60))
+        d = rng.uniform(0.0, 1.0, (60, 6))
+        snaps = np.sort(rng.uniform(0.5, 101.0, 6))
+        dm = d.max(1)
+        inside = (om >= snaps[0]) & (om <= snaps[-1])
+        new1, L, lam_n = R.select_snapshots_threshold(om, d, snaps, 1.0)
+        gk = np.flatnonzero(inside)[np.argmax(dm[inside])]
+        assert new1.size == 1 and new1[0] == om[gk] and L == dm[gk]
+        new0, _, _ = R.select_snapshots_threshold(om, d, snaps, 1e-300)
+        nonempty = int(np.sum(np.isfinite(lam_n)))
+        ref0, _, _ = R.select_snapshots(om, d, snaps, nonempty)
+        assert np.array_equal(new0, ref0)
+        theta = 0.8
+        newt, _, _ = R.select_snapshots_threshold(om, d, snaps, theta)
+        # brute force: for every interval, its maximum and whether it reaches theta * L
+        expect = set()
+        for n in range(snaps.size - 1):
+            last = n == snaps.size - 2
+            m = (om >= snaps[n]) & ((om <= snaps[n + 1]) if last else (om < snaps[n + 1]))
+            if m.any() and dm[m].max() >= theta * L:
+                expect.add(float(om[np.flatnonzero(m)[np.argmax(dm[m])]]))
+        assert set(newt.tolist()) == expect
