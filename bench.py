@@ -128,7 +128,7 @@ def main():
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.sweep is None:
-        args.sweep = "pencil" if args.form == "batched" else "lu"
+        args.sweep = "pencil" if args.form in ("batched", "adaptive") else "lu"
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -644,14 +644,17 @@ def bench_adaptive(args):
     tol, cap, nstar = p.wl.tol_sigma, p.wl.m_cap, p.wl.n_star
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def step(D, snap, record=None):
+    def step(D, snap, record=None, form=None):
         e = [ev() for _ in range(5)]
         e[0].record()
         U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
         e[1].record()
         rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, S)
         e[2].record()
-        out, st = mpt.mpt_sweep(rom, omega)
+        if (form or args.sweep) == "pencil":
+            out, st = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(rom), omega)
+        else:
+            out, st = mpt.mpt_sweep(rom, omega)
         e[3].record()
         new, lam, Lmax = mpt.mpt_select_snapshots(omega, out, snap, nstar)
         e[4].record()
@@ -695,8 +698,20 @@ def bench_adaptive(args):
           enumerate(stages)}
     n_omega = omega.numel()
     value = n_omega / (elapsed / args.steps)
-    sweep_tf = sweep_flops(M) * n_omega / (ms["sweep"] * 1e-3) / 1e12
+    pencil = args.sweep == "pencil"
+    fpu = pencil_sweep_flops(M) if pencil else sweep_flops(M)
+    sweep_tf = fpu * n_omega / (ms["sweep"] * 1e-3) / 1e12
     log(f"final: {p.D.shape[1]} columns, M={M}, ms/step {1e3 * elapsed / args.steps:.3f}, {ms}")
+    # the other sweep form on the same final snapshot set, for comparison
+    alt_form = "lu" if pencil else "pencil"
+    step(D, snap, form=alt_form)
+    torch.cuda.synchronize()
+    arec = []
+    for _ in range(args.steps):
+        step(D, snap, arec, form=alt_form)
+    torch.cuda.synchronize()
+    alt_sweep = float(np.mean([e[2].elapsed_time(e[3]) for e in arec]))
+    alt_step = float(np.mean([e[0].elapsed_time(e[4]) for e in arec]))
     cpu = None if args.no_cpu else cpu_baseline(p, args.cpu_seconds)
     line = {
         "metric": "MPT tensors/sec (3x3 + error cert per omega per object)",
@@ -710,11 +725,17 @@ def bench_adaptive(args):
                    "N": int(ops.N), "nnz": int(ops.K.nnz), "n_snap": int(p.snap_omega.size),
                    "M": int(M), "n_omega": int(n_omega), "rounds": rounds},
         "stages_ms": {k: round(v, 4) for k, v in ms.items()},
-        "roofline": {"kernel": "sweep (M > 64: LDS-resident system, one workgroup per omega)"
-                     if M > 64 else "sweep (k_sweep)", "bound": "alu",
+        "sweep_form": args.sweep,
+        "alt_path": {"sweep_form": alt_form, "sweep_ms": round(alt_sweep, 4),
+                     "step_ms_gpu": round(alt_step, 4)},
+        "roofline": {"kernel": ("pencil reduction + sweep on the Hessenberg-triangular pencil"
+                                if pencil else
+                                "sweep (M > 64: LDS-resident system, one workgroup per omega)"
+                                if M > 64 else "sweep (k_sweep)"),
+                     "bound": "mfma" if pencil else "alu",
                      "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF, "unit": "TFLOP/s",
                      "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4), "traffic": None,
-                     "flops_per_unit": sweep_flops(M), "units_per_launch": int(n_omega),
+                     "flops_per_unit": fpu, "units_per_launch": int(n_omega),
                      "launch_ms": round(ms["sweep"], 4)},
         "cpu_baseline": cpu,
     }

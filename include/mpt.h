@@ -240,7 +240,8 @@ mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
  * mpt_pencil_bytes(M) bytes, owned by the caller and kept alive while the
  * pencil is used) receives all of it; *out (host struct) receives device
  * pointers into buf.  The rom matrices are only read and may be freed after
- * the stream has passed the call.  1 <= M <= 64.
+ * the stream has passed the call.  1 <= M <= 96 (above 64 the reduction
+ * keeps its working copy of A in buf and the sweep holds two rows per lane).
  * mpt_sweep_pencil: per frequency the Hessenberg system
  *   (H - i w T) y_i = i w f_i,   a_i = Z y_i,
  * solved by column elimination with pivoting between adjacent columns
@@ -270,7 +271,7 @@ mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* o
 /* Pencil form for a dictionary: one call reduces every object (one
  * workgroup per object and stage) and sweeps all objects' frequencies (work
  * items of 16 frequencies of one object, one launch per segment width).
- * roms_host: n_obj host structs (device pointers), 1 <= M <= 64 each;
+ * roms_host: n_obj host structs (device pointers), 1 <= M <= 96 each;
  * omega_off (n_obj + 1, host, omega_off[0] = 0) indexes omega / out / status
  * as in mpt_sweep_batched; buf (device, >= mpt_pencil_batched_bytes) holds
  * the objects' pencils, packed in order.  The work-item plan is uploaded once

@@ -33,7 +33,7 @@ struct mpt_handle_s {
   void* pbuf = nullptr;
   size_t pbuf_bytes = 0;
   std::vector<int64_t> pkey;
-  int pn[3] = {0, 0, 0};
+  int pn[4] = {0, 0, 0, 0};
   int pmaxM = 0;
 };
 
@@ -535,7 +535,7 @@ extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const 
 
 // ------------------------------------------------------ pencil form sweep
 extern "C" size_t mpt_pencil_bytes(int M) {
-  if (M < 1 || M > 64) return 0;
+  if (M < 1 || M > 96) return 0;
   return mpt::pencil_layout(M).total;
 }
 
@@ -544,7 +544,6 @@ extern "C" mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* 
   if (!h) return MPT_E_ARG;
   mpt_status s = check_rom(h, rom);
   if (s != MPT_OK) return s;
-  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the pencil form takes M <= 64");
   ARG(buf != nullptr && out != nullptr, "NULL buf/out");
   const mpt::PencilLayout L = mpt::pencil_layout(rom->M);
   if (bytes < L.total) return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
@@ -571,7 +570,7 @@ extern "C" mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, cons
                                        int32_t* status) {
   if (!h) return MPT_E_ARG;
   ARG(pen != nullptr, "pencil is NULL");
-  ARG(pen->M >= 1 && pen->M <= 64, "pencil M must be in [1, 64]");
+  ARG(pen->M >= 1 && pen->M <= 96, "pencil M must be in [1, 96]");
   ARG(pen->H && pen->T && pen->f && pen->Z && pen->W && pen->S, "pencil has a NULL part");
   ARG(pen->alpha > 0.0 && pen->alpha_lb > 0.0, "pencil alpha and alpha_lb must be positive");
   ARG(n_omega >= 0, "n_omega < 0");
@@ -588,7 +587,7 @@ extern "C" size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj) 
   size_t tot = 0;
   for (int o = 0; o < n_obj; ++o) {
     const int M = roms_host[o].M;
-    if (M < 1 || M > 64) return 0;
+    if (M < 1 || M > 96) return 0;
     tot += mpt::pencil_layout(M).total;
   }
   return tot;
@@ -603,7 +602,6 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
   for (int o = 0; o < n_obj; ++o) {
     mpt_status s = check_rom(h, &roms_host[o]);
     if (s != MPT_OK) return s;
-    if (roms_host[o].M > 64) return fail(h, MPT_E_UNSUPPORTED, "the pencil form takes M <= 64");
     ARG(omega_off[o + 1] >= omega_off[o], "omega_off must be non-decreasing");
   }
   ARG(omega_off[0] == 0, "omega_off[0] must be 0");
@@ -624,7 +622,7 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
   if (key != h->pkey) {
     std::vector<mpt::PencilJob> jobs(n_obj);
     std::vector<mpt::PencilArgs> args(n_obj);
-    std::vector<int4> items[3];
+    std::vector<int4> items[4];
     char* base = static_cast<char*>(buf);
     int maxM = 1;
     for (int o = 0; o < n_obj; ++o) {
@@ -638,7 +636,7 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
       args[o] = mpt::pencil_args(pen);
       base += mpt::pencil_layout(r.M).total;
       maxM = std::max(maxM, r.M);
-      const int bi = r.M <= 16 ? 0 : (r.M <= 32 ? 1 : 2);
+      const int bi = r.M <= 16 ? 0 : (r.M <= 32 ? 1 : (r.M <= 64 ? 2 : 3));
       for (int64_t k = omega_off[o]; k < omega_off[o + 1]; k += 16) {
         const int cnt = (int)std::min<int64_t>(16, omega_off[o + 1] - k);
         items[bi].push_back(make_int4(o, (int)k, cnt, 0));
@@ -646,7 +644,7 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     }
     const size_t jb = align256(n_obj * sizeof(mpt::PencilJob));
     const size_t ab = align256(n_obj * sizeof(mpt::PencilArgs));
-    const size_t ni = items[0].size() + items[1].size() + items[2].size();
+    const size_t ni = items[0].size() + items[1].size() + items[2].size() + items[3].size();
     const size_t need = jb + ab + align256(ni * sizeof(int4));
     if (h->pbuf_bytes < need) {
       if (h->pbuf) {
@@ -670,7 +668,7 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
       HIP_OK(hipMemcpyAsync(pb + jb + ab, all.data(), ni * sizeof(int4), hipMemcpyHostToDevice,
                             h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
-    for (int b = 0; b < 3; ++b) h->pn[b] = (int)items[b].size();
+    for (int b = 0; b < 4; ++b) h->pn[b] = (int)items[b].size();
     h->pmaxM = maxM;
     h->pkey = key;
   }
@@ -682,9 +680,9 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
   const int4* items = reinterpret_cast<const int4*>(pb + jb + ab);
   mpt::PencilJob none{};
   HIP_OK(mpt::pencil_reduce_launch(none, jobs, n_obj, h->pmaxM, h->stream));
-  const int Ls[3] = {16, 32, 64};
+  const int Ls[4] = {16, 32, 64, 96};
   int at = 0;
-  for (int b = 0; b < 3; ++b) {
+  for (int b = 0; b < 4; ++b) {
     HIP_OK(mpt::pencil_sweep_items_launch(Ls[b], args, items + at, h->pn[b], omega, out, status,
                                           h->stream));
     at += h->pn[b];

@@ -82,7 +82,7 @@ hipError_t fmm_launch(const mpt_csr& Op, const double* wf, const double* c, cons
 // pencil.hip : Hessenberg-triangular form of (A0, C_M) and the sweep on it.
 //   Byte offsets of the parts of one object's pencil buffer.
 struct PencilLayout {
-  size_t H, T, f, Z, Zf, W, S, rec, total;
+  size_t H, T, f, Z, Zf, W, S, rec, Aw, total;
   int Mp, Kp, NT;  // M rounded up to 16 / to 4; MFMA row tiles of W
 };
 __host__ __device__ inline PencilLayout pencil_layout(int M) {
@@ -106,6 +106,7 @@ __host__ __device__ inline PencilLayout pencil_layout(int M) {
   L.S = take(27 * 8);
   const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 1;
   L.rec = take(nrot * 3 * 8);
+  L.Aw = take(M > 64 ? (size_t)M * (M + 1) * 16 : 16);  // reduction work copy of A (M > 64)
   L.total = o;
   return L;
 }

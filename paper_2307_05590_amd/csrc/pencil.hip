@@ -31,6 +31,7 @@
 namespace mpt {
 
 constexpr int kPenBatch = 16;  // frequencies per workgroup batch
+constexpr int kPenLdsM = 64;   // above this M the reduction keeps A in global memory
 
 namespace {
 
@@ -171,8 +172,12 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
   double* rec = reinterpret_cast<double*>(J.base + Lo.rec);
   extern __shared__ double2 lds[];
   const int ld = M + 1;
-  double2* sA = lds;
-  double2* sB = sA + M * ld;
+  // above M = 64 the two working matrices do not both fit in LDS: A is kept
+  // in the pencil buffer (global memory, visible across the workgroup's
+  // barriers), B in LDS
+  const bool a_global = M > kPenLdsM;
+  double2* sA = a_global ? reinterpret_cast<double2*>(J.base + Lo.Aw) : lds;
+  double2* sB = a_global ? lds : sA + M * ld;
   double2* sF = sB + M * ld;
   double2* sV = sF + 3 * M;
   __shared__ double sBeta;
@@ -417,8 +422,11 @@ __global__ __launch_bounds__(64) void k_pencil_z(PencilJob one, const PencilJob*
   const int ld = M + 1;
   const int r = threadIdx.x;
   const int nrot = M >= 3 ? (M - 1) * (M - 2) / 2 : 0;
+  // the rotation record in LDS when it fits beside Z, else read from global
   double* sRec = reinterpret_cast<double*>(sZ + M * ld);
-  for (int e = r; e < 3 * nrot; e += blockDim.x) sRec[e] = rec[e];
+  if (M <= kPenLdsM)
+    for (int e = r; e < 3 * nrot; e += blockDim.x) sRec[e] = rec[e];
+  const double* rsrc = M <= kPenLdsM ? sRec : rec;
   __syncthreads();
   if (r < M) {
     for (int c = 0; c < M; ++c) sZ[r * ld + c] = make_double2(c == r ? 1.0 : 0.0, 0.0);
@@ -426,8 +434,8 @@ __global__ __launch_bounds__(64) void k_pencil_z(PencilJob one, const PencilJob*
     for (int j = 0; j + 2 < M; ++j) {
       auto rotz = [&](int i, double& c, double2& s) {
         const int k = idx0 + (M - 1 - i);
-        c = sRec[3 * k];
-        s = make_double2(sRec[3 * k + 1], sRec[3 * k + 2]);
+        c = rsrc[3 * k];
+        s = make_double2(rsrc[3 * k + 1], rsrc[3 * k + 2]);
       };
       rot_chain<false>(sZ + r * ld, 1, M, j, rotz, -1);
       idx0 += M - 2 - j;
@@ -500,15 +508,27 @@ __global__ __launch_bounds__(256) void k_pencil_layout(PencilJob one,
   }
 }
 
+static size_t reduce_lds(int M) {
+  const size_t mats = M > kPenLdsM ? 1 : 2;  // B only, or A and B
+  return (mats * M * (M + 1) + 6 * (size_t)M) * sizeof(double2);
+}
+static size_t z_lds(int M) {
+  const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 0;
+  return (size_t)M * (M + 1) * sizeof(double2) + (M > kPenLdsM ? 0 : nrot * 3 * sizeof(double));
+}
+
 hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
                                 hipStream_t st) {
-  const int M = maxM;
-  const size_t lds1 = ((size_t)2 * M * (M + 1) + 6 * M) * sizeof(double2);
+  // LDS for the largest requirement among M <= maxM (not monotonic at kPenLdsM)
+  const int Ml = maxM < kPenLdsM ? maxM : kPenLdsM;
+  size_t lds1 = reduce_lds(Ml), lds2 = z_lds(Ml);
+  if (maxM > kPenLdsM) {
+    lds1 = lds1 > reduce_lds(maxM) ? lds1 : reduce_lds(maxM);
+    lds2 = lds2 > z_lds(maxM) ? lds2 : z_lds(maxM);
+  }
   hipLaunchKernelGGL(k_pencil_reduce, dim3(n_jobs), dim3(256), lds1, st, one, jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 0;
-  const size_t lds2 = (size_t)M * (M + 1) * sizeof(double2) + nrot * 3 * sizeof(double);
   hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(64), lds2, st, one, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -555,7 +575,7 @@ __device__ __forceinline__ int pair_of(int i, int j) {
 }  // namespace
 
 
-template <int L>
+template <int L, int R>
 __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
                                                       const PencilArgs* __restrict__ objs,
                                                       const int4* __restrict__ items,
@@ -586,112 +606,171 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
   const int ll = wl & (L - 1), base = wl - ll;
   constexpr int kSegs = 64 / L;
 
-  // ---- 1. Hessenberg solves, one frequency per segment ------------------
+  // ---- 1. Hessenberg solves, one frequency per segment of L lanes; lane ll
+  //         holds rows ll + L s, s < R (R = 2 only with L = 64) -------------
   for (int rnd = 0; rnd < L / 16; ++rnd) {
     const int wloc = rnd * 4 * kSegs + wave * kSegs + wl / L;
     const int64_t gi = b0 + wloc;
     const bool valid = wloc < cnt;
     const double om = valid ? omega[gi] : 0.0;
-    const bool act = ll < M;
-    auto colval = [&](int k) -> double2 {  // (H - i w T)[ll][k]
-      if (!act) return make_double2(0.0, 0.0);
-      const double2 h = P.H[(size_t)k * M + ll], t = P.T[(size_t)k * M + ll];
+    auto colval = [&](int k, int sl) -> double2 {  // (H - i w T)[row][k]
+      const int row = ll + L * sl;
+      if (row >= M) return make_double2(0.0, 0.0);
+      const double2 h = P.H[(size_t)k * M + row], t = P.T[(size_t)k * M + row];
       return make_double2(fma(om, t.y, h.x), fma(-om, t.x, h.y));
     };
-    double2 c = colval(M - 1);
-    double2 b[3];
+    double2 c[R], b[R][3], my_l[R], my_z[R][3], a1[R], a2[R];
+    bool my_sw[R];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double2 fi = act ? P.f[i * M + ll] : make_double2(0.0, 0.0);
-      b[i] = make_double2(-om * fi.y, om * fi.x);  // i w f_i
+    for (int sl = 0; sl < R; ++sl) {
+      const int row = ll + L * sl;
+      c[sl] = colval(M - 1, sl);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 fi = row < M ? P.f[i * M + row] : make_double2(0.0, 0.0);
+        b[sl][i] = make_double2(-om * fi.y, om * fi.x);  // i w f_i
+        my_z[sl][i] = make_double2(0.0, 0.0);
+      }
+      my_l[sl] = make_double2(0.0, 0.0);
+      my_sw[sl] = false;
+      a1[sl] = M >= 2 ? colval(M - 2, sl) : make_double2(0.0, 0.0);
+      a2[sl] = M >= 3 ? colval(M - 3, sl) : make_double2(0.0, 0.0);
     }
-    double2 my_l = make_double2(0.0, 0.0), my_z[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) my_z[i] = make_double2(0.0, 0.0);
-    bool my_sw = false;
     bool bad = false;
-    double2 a1 = M >= 2 ? colval(M - 2) : make_double2(0.0, 0.0);
-    double2 a2 = M >= 3 ? colval(M - 3) : make_double2(0.0, 0.0);
     for (int k = M - 2; k >= 0; --k) {
-      const double2 a = a1;
-      a1 = a2;
-      if (k >= 2) a2 = colval(k - 2);
-      const int q = k + 1;
+      double2 a[R];
+#pragma unroll
+      for (int sl = 0; sl < R; ++sl) {
+        a[sl] = a1[sl];
+        a1[sl] = a2[sl];
+        if (k >= 2) a2[sl] = colval(k - 2, sl);
+      }
+      const int q = k + 1, qs = q / L, ql = q % L;  // row q: lane ql, slot qs
       double code = 0.0;
       double2 l = make_double2(0.0, 0.0), z[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) z[i] = make_double2(0.0, 0.0);
-      if (ll == q) {
+      if (ll == ql) {
+        double2 aq = a[0], cq = c[0], bq[3] = {b[0][0], b[0][1], b[0][2]};
+        if (R == 2 && qs == 1) {
+          aq = a[R - 1];
+          cq = c[R - 1];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) bq[i] = b[R - 1][i];
+        }
         // pivot between column k (a) and the carried column k+1 (c) on row
         // k+1: the larger |re| + |im| (the carried column on ties)
-        const bool sw = fabs(a.x) + fabs(a.y) > fabs(c.x) + fabs(c.y);
-        const double2 p = sw ? a : c, o = sw ? c : a;
+        const bool sw = fabs(aq.x) + fabs(aq.y) > fabs(cq.x) + fabs(cq.y);
+        const double2 p = sw ? aq : cq, o = sw ? cq : aq;
         const double d = p.x * p.x + p.y * p.y;
         const bool bd = !(d > 0.0) || !isfinite(d);
         const double2 inv = crecip(p);
         l = cmul(o, inv);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) z[i] = cmul(b[i], inv);
+        for (int i = 0; i < 3; ++i) z[i] = cmul(bq[i], inv);
         code = (sw ? 1.0 : 0.0) + (bd ? 2.0 : 0.0);
-        my_sw = sw;
-        my_l = l;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) my_z[i] = z[i];
+        for (int sl = 0; sl < R; ++sl) {
+          if (sl == qs) {
+            my_sw[sl] = sw;
+            my_l[sl] = l;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) my_z[sl][i] = z[i];
+          }
+        }
       }
-      const int src = base + q;
+      const int src = base + ql;
       code = seg_bc<L>(code, src);
       l = seg_bc2<L>(l, src);
 #pragma unroll
       for (int i = 0; i < 3; ++i) z[i] = seg_bc2<L>(z[i], src);
       const bool sw = code == 1.0 || code == 3.0;
       bad = bad || code >= 2.0;
-      if (ll < q) {
-        const double2 p = sw ? a : c, o = sw ? c : a;
-        c = cfms(o, l, p);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] = cfms(b[i], p, z[i]);
-      }
-    }
-    // z_0 in lane 0, then y = (column transforms) z by a chain over the lanes
-    double2 t[3];
-    {
-      double code = 0.0;
-      if (ll == 0) {
-        const double d = c.x * c.x + c.y * c.y;
-        code = (!(d > 0.0) || !isfinite(d)) ? 2.0 : 0.0;
-      }
-      const double2 inv = crecip(c);
+      for (int sl = 0; sl < R; ++sl) {
+        if (ll + L * sl < q) {
+          const double2 p = sw ? a[sl] : c[sl], o = sw ? c[sl] : a[sl];
+          c[sl] = cfms(o, l, p);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) t[i] = cmul(b[i], inv);
-      bad = bad || seg_bc<L>(code, base) >= 2.0;
-    }
-    double2 yprev[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) yprev[i] = make_double2(0.0, 0.0);
-    for (int k = 0; k + 1 < M; ++k) {
-      double2 tin[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) tin[i] = seg_bc2<L>(t[i], base + k);
-      if (ll == k + 1) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const double2 v = cfms(my_z[i], my_l, tin[i]);
-          yprev[i] = my_sw ? v : tin[i];
-          t[i] = my_sw ? tin[i] : v;
+          for (int i = 0; i < 3; ++i) b[sl][i] = cfms(b[sl][i], p, z[i]);
         }
       }
     }
-    double2 y[3];
+    // z_0 at row 0 (lane 0, slot 0), then y = (column transforms) z by a
+    // chain over the rows
+    double2 t[R][3];
+    {
+      double code = 0.0;
+      if (ll == 0) {
+        const double d = c[0].x * c[0].x + c[0].y * c[0].y;
+        code = (!(d > 0.0) || !isfinite(d)) ? 2.0 : 0.0;
+      }
+      const double2 inv = crecip(c[0]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) t[0][i] = cmul(b[0][i], inv);
+#pragma unroll
+      for (int sl = 1; sl < R; ++sl)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t[sl][i] = make_double2(0.0, 0.0);
+      bad = bad || seg_bc<L>(code, base) >= 2.0;
+    }
+    double2 yprev[R][3];
+#pragma unroll
+    for (int sl = 0; sl < R; ++sl)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) yprev[sl][i] = make_double2(0.0, 0.0);
+    for (int k = 0; k + 1 < M; ++k) {
+      const int ks = k / L, kl = k % L;
+      const int q = k + 1, qs = q / L, ql = q % L;
+      double2 tin[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 tsel = (R == 2 && ks == 1) ? t[R - 1][i] : t[0][i];
+        tin[i] = seg_bc2<L>(tsel, base + kl);
+      }
+      if (ll == ql) {
+#pragma unroll
+        for (int sl = 0; sl < R; ++sl) {
+          if (sl == qs) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              const double2 v = cfms(my_z[sl][i], my_l[sl], tin[i]);
+              yprev[sl][i] = my_sw[sl] ? v : tin[i];
+              t[sl][i] = my_sw[sl] ? tin[i] : v;
+            }
+          }
+        }
+      }
+    }
+    // row r takes y_r from row r + 1's yprev; row M - 1 its own t
+    double2 y[R][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const int src = base + (ll + 1 < L ? ll + 1 : ll);
-      const double2 yn = make_double2(shfl_d(yprev[i].x, src), shfl_d(yprev[i].y, src));
-      y[i] = ll == M - 1 ? t[i] : yn;
-    }
-    if (ll < Kp) {
+      if constexpr (R == 1) {
+        const int src = base + (ll + 1 < L ? ll + 1 : ll);
+        const double2 yn = make_double2(shfl_d(yprev[0][i].x, src), shfl_d(yprev[0][i].y, src));
+        y[0][i] = ll == M - 1 ? t[0][i] : yn;
+      } else {
+        const int src = (ll + 1) & 63;
+        const double2 ya = make_double2(shfl_d(yprev[0][i].x, src), shfl_d(yprev[0][i].y, src));
+        const double2 yb = make_double2(shfl_d(yprev[R - 1][i].x, src),
+                                        shfl_d(yprev[R - 1][i].y, src));
+        y[0][i] = ll < 63 ? ya : yb;
+        y[R - 1][i] = yb;
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        sY[(i * Kp + ll) * kPenBatch + wloc] = (valid && act) ? y[i] : make_double2(0.0, 0.0);
+        for (int sl = 0; sl < R; ++sl)
+          if (ll + L * sl == M - 1) y[sl][i] = t[sl][i];
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < R; ++sl) {
+      const int row = ll + L * sl;
+      if (row < Kp) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          sY[(i * Kp + row) * kPenBatch + wloc] =
+              (valid && row < M) ? y[sl][i] : make_double2(0.0, 0.0);
+      }
     }
     if (ll == 0) sStat[wloc] = bad ? 1 : 0;
   }
@@ -700,7 +779,7 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
   // ---- 2a. a = Z y (MFMA), written back over y -----------------------------
   const int KB = Kp / 4, tpb = P.Mp / 16;
   {
-    constexpr int kMaxJobs = 3;  // (row tiles x 3 right-hand sides) / 4 waves, M <= 64
+    constexpr int kMaxJobs = R == 2 ? 5 : 3;  // (row tiles x 3 right-hand sides) / 4 waves
     double4_t zr[kMaxJobs], zi[kMaxJobs];
 #pragma unroll
     for (int q = 0; q < kMaxJobs; ++q) {
@@ -879,14 +958,17 @@ hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t
   const PencilArgs* no = nullptr;
   const int4* ni = nullptr;
   if (P.M <= 16)
-    hipLaunchKernelGGL((k_sweep_pencil<16>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
-                       status);
+    hipLaunchKernelGGL((k_sweep_pencil<16, 1>), grid, block, lds, st, P, no, ni, omega, n, out,
+                       a_out, status);
   else if (P.M <= 32)
-    hipLaunchKernelGGL((k_sweep_pencil<32>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
-                       status);
+    hipLaunchKernelGGL((k_sweep_pencil<32, 1>), grid, block, lds, st, P, no, ni, omega, n, out,
+                       a_out, status);
+  else if (P.M <= 64)
+    hipLaunchKernelGGL((k_sweep_pencil<64, 1>), grid, block, lds, st, P, no, ni, omega, n, out,
+                       a_out, status);
   else
-    hipLaunchKernelGGL((k_sweep_pencil<64>), grid, block, lds, st, P, no, ni, omega, n, out, a_out,
-                       status);
+    hipLaunchKernelGGL((k_sweep_pencil<64, 2>), grid, block, lds, st, P, no, ni, omega, n, out,
+                       a_out, status);
   return hipGetLastError();
 }
 
@@ -894,19 +976,22 @@ hipError_t pencil_sweep_items_launch(int L, const PencilArgs* objs, const int4* 
                                      int n_items, const double* omega, double* out,
                                      int32_t* status, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  // LDS for the largest object of the bucket: Kp <= L, NT <= L / 4 + 1
+  // LDS for the largest object of the bucket: Kp <= bucket, NT <= bucket / 4 + 1
   const size_t lds = sweep_lds(L, L / 4 + 1);
   const dim3 grid((unsigned)n_items), block(256);
   PencilArgs none{};
   double* no_a = nullptr;
   if (L == 16)
-    hipLaunchKernelGGL((k_sweep_pencil<16>), grid, block, lds, st, none, objs, items, omega,
+    hipLaunchKernelGGL((k_sweep_pencil<16, 1>), grid, block, lds, st, none, objs, items, omega,
                        (int64_t)0, out, no_a, status);
   else if (L == 32)
-    hipLaunchKernelGGL((k_sweep_pencil<32>), grid, block, lds, st, none, objs, items, omega,
+    hipLaunchKernelGGL((k_sweep_pencil<32, 1>), grid, block, lds, st, none, objs, items, omega,
                        (int64_t)0, out, no_a, status);
-  else
-    hipLaunchKernelGGL((k_sweep_pencil<64>), grid, block, lds, st, none, objs, items, omega,
+  else if (L == 64)
+    hipLaunchKernelGGL((k_sweep_pencil<64, 1>), grid, block, lds, st, none, objs, items, omega,
+                       (int64_t)0, out, no_a, status);
+  else  // 64 < M <= 96: two rows per lane
+    hipLaunchKernelGGL((k_sweep_pencil<64, 2>), grid, block, lds, st, none, objs, items, omega,
                        (int64_t)0, out, no_a, status);
   return hipGetLastError();
 }

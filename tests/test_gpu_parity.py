@@ -132,7 +132,7 @@ def test_sweep_deterministic(mpt):
 
 
 # ------------------------------------------------- pencil form of the sweep
-@pytest.mark.parametrize("M", [1, 2, 3, 16, 17, 31, 47, 48, 64])
+@pytest.mark.parametrize("M", [1, 2, 3, 16, 17, 31, 47, 48, 64, 65, 80, 96])
 def test_pencil_random_roms(mpt, M):
     rom_o, G, host, alpha = random_rom(M, seed=M)
     omega = np.logspace(1, 6, 131)
@@ -159,7 +159,7 @@ def test_pencil_magnetic_rom(mpt):
                  form="pencil")
 
 
-@pytest.mark.parametrize("M", [2, 17, 48, 64])
+@pytest.mark.parametrize("M", [2, 17, 48, 64, 96])
 def test_pencil_structure(mpt, M):
     """H upper Hessenberg and T upper triangular (exact zeros), Z unitary, and
     the generalised eigenvalues of (H, T) those of (A0, C_M)."""
@@ -196,10 +196,11 @@ def test_pencil_empty_bad_args_singular_deterministic(mpt):
     pen = mpt.mpt_pencil_reduce(mpt.Rom.from_host(host, alpha))
     out, st = mpt.mpt_sweep_pencil(pen, torch.empty(0, dtype=torch.float64, device="cuda"))
     assert out.shape == (0, 18)
-    assert mpt.lib().mpt_pencil_bytes(65) == 0
-    rom_o, G, host65, alpha = random_rom(65, seed=65)
+    assert mpt.lib().mpt_pencil_bytes(97) == 0 and mpt.lib().mpt_pencil_bytes(96) > 0
+    bad = mpt.Rom.from_host(host, alpha)
+    bad.M = 97
     with pytest.raises(mpt.MptError):
-        mpt.mpt_pencil_reduce(mpt.Rom.from_host(host65, alpha))
+        mpt.mpt_pencil_reduce(bad)
     # a zero pencil is flagged
     z = dict(host)
     z["A0"] = np.zeros((5, 5))
@@ -529,6 +530,10 @@ def test_batched_equals_per_object(mpt, use_graph):
 
 def test_pencil_batched_equals_per_object(mpt):
     roms, omegas = _dictionary(mpt)
+    # and one object above M = 64 (two rows per lane)
+    rom_o, G, host, alpha = random_rom(80, seed=180)
+    roms.append(mpt.Rom.from_host(host, alpha))
+    omegas.append(torch.tensor(np.logspace(1, 6, 77), dtype=torch.float64, device="cuda"))
     dic = mpt.Dictionary(roms, omegas)
     out, st, buf = mpt.mpt_sweep_pencil_batched(dic)
     out2, st2, _ = mpt.mpt_sweep_pencil_batched(dic, buf=buf)  # cached plan
