@@ -158,6 +158,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // rows), F (3 x M), v (M), beta.  The Givens chain runs in wave 0 (rotations
 // are sequential; each is applied by up to 64 lanes at once); the right
 // rotations are recorded for the accumulation of Z.
+template <int RR>  // rows (columns) per lane of wave 0: 1 for M <= 64, 2 for M <= 128
 __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
                                                        const PencilJob* __restrict__ jobs) {
   const PencilJob J = jobs ? jobs[blockIdx.x] : one;
@@ -195,8 +196,15 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
   for (int k = 0; k + 1 < M; ++k) {
     const int len = M - k;
     if (wave == 0) {
-      const double2 x = lane < len ? sB[(k + lane) * ld + k] : make_double2(0.0, 0.0);
-      const double nrm2 = wave_sum(x.x * x.x + x.y * x.y);
+      double2 x[RR];
+      double part = 0.0;
+#pragma unroll
+      for (int sl = 0; sl < RR; ++sl) {
+        const int u = lane + 64 * sl;
+        x[sl] = u < len ? sB[(k + u) * ld + k] : make_double2(0.0, 0.0);
+        part += x[sl].x * x[sl].x + x[sl].y * x[sl].y;
+      }
+      const double nrm2 = wave_sum(part);
       const double2 x0 = sB[k * ld + k];
       const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
       const double nrm = sqrt(nrm2);
@@ -205,7 +213,11 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
       const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
       const double2 v0 = make_double2(x0.x - alpha.x, x0.y - alpha.y);
       const double vn2 = nrm2 - ax0 * ax0 + (v0.x * v0.x + v0.y * v0.y);
-      if (lane < len) sV[lane] = lane == 0 ? v0 : x;
+#pragma unroll
+      for (int sl = 0; sl < RR; ++sl) {
+        const int u = lane + 64 * sl;
+        if (u < len) sV[u] = u == 0 ? v0 : x[sl];
+      }
       if (lane == 0) {
         const bool refl = nrm2 > 0.0 && vn2 > 0.0;
         sBeta = refl ? 2.0 / vn2 : 0.0;
@@ -271,21 +283,41 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
   double* sRot = reinterpret_cast<double*>(sV);  // recL (3 x M) then recR (3 x M)
   int nrec = 0;
   for (int j = 0; j + 2 < M; ++j) {
-    double myc = 1.0, myc2 = 1.0;
-    double2 mys = make_double2(0.0, 0.0), mys2 = make_double2(0.0, 0.0);
+    // rotation i is held by lane i % 64 in slot i / 64
+    double myc[RR], myc2[RR];
+    double2 mys[RR], mys2[RR];
+#pragma unroll
+    for (int sl = 0; sl < RR; ++sl) {
+      myc[sl] = myc2[sl] = 1.0;
+      mys[sl] = mys2[sl] = make_double2(0.0, 0.0);
+    }
     if (wave == 0) {
-      const bool act = lane < M;
-      const double2 colj = act ? sA[lane * ld + j] : make_double2(0.0, 0.0);
-      const double2 bd = act ? sB[lane * ld + lane] : make_double2(0.0, 0.0);  // diagonal of B
-      double2 carry = act ? sB[lane * ld + M - 1] : make_double2(0.0, 0.0);
-      double2 nx = act ? sB[lane * ld + M - 2] : make_double2(0.0, 0.0);
-      double2 y = bcast2(colj, M - 1);
+      double2 colj[RR], bd[RR], carry[RR], nx[RR];
+#pragma unroll
+      for (int sl = 0; sl < RR; ++sl) {
+        const int r = lane + 64 * sl;
+        const bool act = r < M;
+        colj[sl] = act ? sA[r * ld + j] : make_double2(0.0, 0.0);
+        bd[sl] = act ? sB[r * ld + r] : make_double2(0.0, 0.0);  // diagonal of B
+        carry[sl] = act ? sB[r * ld + M - 1] : make_double2(0.0, 0.0);
+        nx[sl] = act ? sB[r * ld + M - 2] : make_double2(0.0, 0.0);
+      }
+      // value of row r (uniform) from the lane and slot that hold it
+      auto rowv = [&](const double2 (&v)[RR], int r) -> double2 {
+        const int sl = r >> 6;
+        double2 x = v[0];
+#pragma unroll
+        for (int t = 1; t < RR; ++t)
+          if (sl == t) x = v[t];
+        return bcast2(x, r & 63);
+      };
+      double2 y = rowv(colj, M - 1);
       double c1 = 1.0, c21 = 1.0;
       double2 s1 = make_double2(0.0, 0.0), s21 = make_double2(0.0, 0.0);
       double2 e_prev = make_double2(0.0, 0.0), b_prev = make_double2(0.0, 0.0);
       for (int i = M - 1; i >= j + 2; --i) {
         // left rotation i (rows i-1, i) from column j
-        const double2 x = bcast2(colj, i - 1);
+        const double2 x = rowv(colj, i - 1);
         double c;
         double2 s;
         givens_left(x, y, c, s);
@@ -296,7 +328,7 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
           y = ny;
         }
         // B[i][i] before step i
-        const double2 bii = bcast2(bd, i);
+        const double2 bii = rowv(bd, i);
         double2 b_i;
         if (i == M - 1) {
           b_i = bii;
@@ -310,21 +342,26 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
           b_i.x = fma(c21 * c1, bii.x, b_i.x);
           b_i.y = fma(c21 * c1, bii.y, b_i.y);
         }
-        const double2 F = bcast2(carry, i - 1);  // B[i-1][i] before step i
+        const double2 F = rowv(carry, i - 1);  // B[i-1][i] before step i
         // after left i: fill w = B[i][i-1] = -conj(s) B[i-1][i-1], u = B[i][i]
         const double2 ms = make_double2(-s.x, s.y);  // -conj(s)
-        const double2 w = cmul(ms, bcast2(bd, i - 1));
+        const double2 w = cmul(ms, rowv(bd, i - 1));
         double2 u = cmul(ms, F);
         u.x = fma(c, b_i.x, u.x);
         u.y = fma(c, b_i.y, u.y);
         double c2;
         double2 s2;
         givens_right(w, u, c2, s2);
-        if (lane == i) {
-          myc = c;
-          mys = s;
-          myc2 = c2;
-          mys2 = s2;
+        if (lane == (i & 63)) {
+#pragma unroll
+          for (int sl = 0; sl < RR; ++sl) {
+            if (sl == (i >> 6)) {
+              myc[sl] = c;
+              mys[sl] = s;
+              myc2[sl] = c2;
+              mys2[sl] = s2;
+            }
+          }
         }
         c1 = c;
         s1 = s;
@@ -333,41 +370,42 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
         e_prev = F;
         b_prev = b_i;
         // the rows' carries: right rotation i on columns (i-1, i)
-        const double2 x1 = nx;
-        if (act && i - 2 >= 0) nx = sB[lane * ld + i - 2];
-        double2 nc = cmul(make_double2(-s2.x, s2.y), carry);
-        nc.x = fma(c2, x1.x, nc.x);
-        nc.y = fma(c2, x1.y, nc.y);
-        carry = nc;
+#pragma unroll
+        for (int sl = 0; sl < RR; ++sl) {
+          const int r = lane + 64 * sl;
+          const double2 x1 = nx[sl];
+          if (r < M && i - 2 >= 0) nx[sl] = sB[r * ld + i - 2];
+          double2 nc = cmul(make_double2(-s2.x, s2.y), carry[sl]);
+          nc.x = fma(c2, x1.x, nc.x);
+          nc.y = fma(c2, x1.y, nc.y);
+          carry[sl] = nc;
+        }
       }
-      // column j done: A[j+1][j] = y, zeros below
-      if (lane == j + 1) sA[(j + 1) * ld + j] = y;
-      if (lane >= j + 2 && lane < M) sA[lane * ld + j] = make_double2(0.0, 0.0);
-      // publish the rotations of this sweep (lane i holds rotation i)
-      if (lane >= j + 2 && lane < M) {
-        sRot[3 * lane] = myc;
-        sRot[3 * lane + 1] = mys.x;
-        sRot[3 * lane + 2] = mys.y;
-        sRot[3 * M + 3 * lane] = myc2;
-        sRot[3 * M + 3 * lane + 1] = mys2.x;
-        sRot[3 * M + 3 * lane + 2] = mys2.y;
-        const int k = nrec + (M - 1 - lane);  // recorded in the order applied
-        rec[3 * k] = myc2;
-        rec[3 * k + 1] = mys2.x;
-        rec[3 * k + 2] = mys2.y;
+#pragma unroll
+      for (int sl = 0; sl < RR; ++sl) {
+        const int r = lane + 64 * sl;
+        // column j done: A[j+1][j] = y, zeros below
+        if (r == j + 1) sA[(j + 1) * ld + j] = y;
+        if (r >= j + 2 && r < M) {
+          sA[r * ld + j] = make_double2(0.0, 0.0);
+          // publish the rotations of this sweep
+          sRot[3 * r] = myc[sl];
+          sRot[3 * r + 1] = mys[sl].x;
+          sRot[3 * r + 2] = mys[sl].y;
+          sRot[3 * M + 3 * r] = myc2[sl];
+          sRot[3 * M + 3 * r + 1] = mys2[sl].x;
+          sRot[3 * M + 3 * r + 2] = mys2[sl].y;
+          const int kk = nrec + (M - 1 - r);  // recorded in the order applied
+          rec[3 * kk] = myc2[sl];
+          rec[3 * kk + 1] = mys2[sl].x;
+          rec[3 * kk + 2] = mys2[sl].y;
+        }
       }
     }
     nrec += M - 2 - j;
     __syncthreads();
-    // ---- left rotations: columns j+1.. of A (wave 0), of B (wave 1), F (wave 2)
-    auto regL = [&](int i, double& c, double2& s) {
-      c = bcast(myc, i);
-      s = bcast2(mys, i);
-    };
-    auto regR = [&](int i, double& c, double2& s) {
-      c = bcast(myc2, i);
-      s = bcast2(mys2, i);
-    };
+    // ---- left rotations: columns j+1.. of A (wave 0, then wave 3 beyond 64
+    // columns), of B (wave 1, then wave 2), F (wave 2)
     auto ldsL = [&](int i, double& c, double2& s) {
       c = sRot[3 * i];
       s = make_double2(sRot[3 * i + 1], sRot[3 * i + 2]);
@@ -376,21 +414,48 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
       c = sRot[3 * M + 3 * i];
       s = make_double2(sRot[3 * M + 3 * i + 1], sRot[3 * M + 3 * i + 2]);
     };
+    // wave 0 reads rotations 0..63 from its registers (v_readlane ignores the
+    // execution mask, and slot 0 was written with the whole wave active);
+    // rotations 64.. come from their published copy
+    auto regL = [&](int i, double& c, double2& s) {
+      if (RR > 1 && i >= 64) {
+        ldsL(i, c, s);
+      } else {
+        c = bcast(myc[0], i);
+        s = bcast2(mys[0], i);
+      }
+    };
+    auto regR = [&](int i, double& c, double2& s) {
+      if (RR > 1 && i >= 64) {
+        ldsR(i, c, s);
+      } else {
+        c = bcast(myc2[0], i);
+        s = bcast2(mys2[0], i);
+      }
+    };
     if (wave == 0) {
       if (j + 1 + lane < M) rot_chain<true>(sA + (j + 1 + lane), ld, M, j, regL, -1);
     } else if (wave == 1) {
       if (j + 1 + lane < M) rot_chain<true>(sB + (j + 1 + lane), ld, M, j, ldsL, -1);
     } else if (wave == 2) {
       if (lane < 3) rot_chain<true>(sF + lane * M, 1, M, j, ldsL, -1);
+      if (RR > 1 && j + 65 + lane < M) rot_chain<true>(sB + (j + 65 + lane), ld, M, j, ldsL, -1);
+    } else if (RR > 1) {
+      if (j + 65 + lane < M) rot_chain<true>(sA + (j + 65 + lane), ld, M, j, ldsL, -1);
     }
     __syncthreads();
-    // ---- right rotations: rows of A (wave 0) and of B (wave 1), columns j+1..;
-    // B stays upper triangular: entries below the diagonal are written as
-    // exact zeros (the fills, cancelled to rounding by the bulk products)
+    // ---- right rotations: rows of A (waves 0, 2) and of B (waves 1, 3),
+    // columns j+1..; B stays upper triangular: entries below the diagonal
+    // are written as exact zeros (the fills, cancelled to rounding by the
+    // bulk products)
     if (wave == 0) {
       if (lane < M) rot_chain<false>(sA + lane * ld, 1, M, j, regR, -1);
     } else if (wave == 1) {
       if (lane < M) rot_chain<false>(sB + lane * ld, 1, M, j, ldsR, lane);
+    } else if (RR > 1 && wave == 2) {
+      if (lane + 64 < M) rot_chain<false>(sA + (lane + 64) * ld, 1, M, j, ldsR, -1);
+    } else if (RR > 1 && wave == 3) {
+      if (lane + 64 < M) rot_chain<false>(sB + (lane + 64) * ld, 1, M, j, ldsR, lane + 64);
     }
     __syncthreads();
   }
@@ -410,7 +475,7 @@ __global__ __launch_bounds__(256) void k_pencil_reduce(PencilJob one,
 // they share is carried in registers.
 __device__ __forceinline__ size_t wfrag_index(int row, int col, int Kp);
 
-__global__ __launch_bounds__(64) void k_pencil_z(PencilJob one, const PencilJob* __restrict__ jobs) {
+__global__ __launch_bounds__(128) void k_pencil_z(PencilJob one, const PencilJob* __restrict__ jobs) {
   const PencilJob J = jobs ? jobs[blockIdx.x] : one;
   const int M = J.M;
   const PencilLayout Lo = pencil_layout(M);
@@ -526,10 +591,14 @@ hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int
     lds1 = lds1 > reduce_lds(maxM) ? lds1 : reduce_lds(maxM);
     lds2 = lds2 > z_lds(maxM) ? lds2 : z_lds(maxM);
   }
-  hipLaunchKernelGGL(k_pencil_reduce, dim3(n_jobs), dim3(256), lds1, st, one, jobs);
+  if (maxM > 64)
+    hipLaunchKernelGGL((k_pencil_reduce<2>), dim3(n_jobs), dim3(256), lds1, st, one, jobs);
+  else
+    hipLaunchKernelGGL((k_pencil_reduce<1>), dim3(n_jobs), dim3(256), lds1, st, one, jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(64), lds2, st, one, jobs);
+  // one thread per row of Z
+  hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(maxM > 64 ? 128 : 64), lds2, st, one, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pencil_layout, dim3(5, n_jobs), dim3(256), 0, st, one, jobs);
