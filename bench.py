@@ -157,7 +157,7 @@ def main():
         f"D={p.D.shape} residual={p.snap_residual:.1e}")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     D = T(p.D, torch.complex128)
-    K = mpt.Csr.from_scipy(ops.K, dev)
+    K = mpt.Csr.from_scipy(ops.K, dev, row_blocks=3)
     c = T(ops.c, torch.float64)
     w = T(p.w, torch.float64)
     o = T(p.o, torch.float64) if np.any(p.o) else None
@@ -320,7 +320,7 @@ def build_dictionary(name, n_obj, dev, keep=2, tol_snap=1e-6):
         p = make_problem(name, o, grid=g, curl=C, tol=tol_snap, green=gr)
         ops = p.ops
         U, sig, M = mpt.mpt_pod_basis(T(p.D, torch.complex128), 0.0, p.M_cap)
-        rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K, dev), T(ops.c, torch.float64), ops.eps_h,
+        rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K, dev, row_blocks=3), T(ops.c, torch.float64), ops.eps_h,
                               T(p.w, torch.float64), T(p.o, torch.float64) if np.any(p.o) else None,
                               T(ops.vol, torch.float64), ops.alpha, U, T(ops.cond_idx, torch.int32),
                               T(p.S, torch.float64))
@@ -498,7 +498,7 @@ def bench_fmm(args):
     p = make_problem("ellipsoid48", verbose=True)
     ops = p.ops
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    K = mpt.Csr.from_scipy(ops.K, dev)
+    K = mpt.Csr.from_scipy(ops.K, dev, row_blocks=3)
     c = T(ops.c, torch.float64)
     w = T(p.w, torch.float64)
     o = T(p.o, torch.float64) if np.any(p.o) else None
@@ -633,7 +633,7 @@ def bench_adaptive(args):
     log(f"generated in {time.time() - t0:.0f} s: N={ops.N} nnz={ops.K.nnz} "
         f"n_c={ops.cond_idx.size} D={p.D.shape}")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    K = mpt.Csr.from_scipy(ops.K, dev)
+    K = mpt.Csr.from_scipy(ops.K, dev, row_blocks=3)
     c = T(ops.c, torch.float64)
     w = T(p.w, torch.float64)
     o = T(p.o, torch.float64) if np.any(p.o) else None

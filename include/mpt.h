@@ -55,13 +55,22 @@ const char* mpt_last_error(mpt_handle h);
 /* Largest reduced dimension M accepted by the sweep kernels. */
 int mpt_max_reduced_dim(void);
 
-/* Real sparse matrix in CSR form (sorted column indices, 0-based). */
+/* Real sparse matrix in CSR form (sorted column indices, 0-based).
+ * row_blocks is a layout hint for the sparse products: 0 or 1 when the rows
+ * have one spatial order; k > 1 when they form k equal consecutive blocks
+ * whose members follow one common spatial order (the three edge orientations
+ * of a Yee grid, each numbered with the same slowest coordinate).  The
+ * products then give each XCD the same slab of every block, so a row's
+ * stencil neighbours in the other blocks are read through that XCD's L2.
+ * k must divide n (MPT_E_ARG otherwise).  Results do not depend on it. */
 typedef struct {
   int64_t n;              /* rows = columns */
   int64_t nnz;
   const int32_t* rowptr;  /* n + 1 */
   const int32_t* colind;  /* nnz */
   const double* val;      /* nnz */
+  int32_t row_blocks;
+  int32_t pad_;
 } mpt_csr;
 
 /*
@@ -135,6 +144,24 @@ mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double e
                        const int32_t* cond, int64_t n_c, const double* S,
                        double* KM, double* A0, double* CM, double* g, double* G,
                        double* E, double* N0, double* Y, void* ws, size_t ws_bytes);
+
+/* Residual Gram of Lemma 4.1 from columns prepared by the caller:
+ *   G = (P + P^H) / 2,  P = Z^H Y over the N rows,
+ * where Z (N x (2M+3), ldZ) = [C_sigma w_1..3 | X U | C_sigma U] holds the
+ * affine residual's columns (the unknowns ordered as in mpt_project's G) and
+ * Y (N x (2M+3), ldY) = X^{-1} Z comes from the caller's full-order solver,
+ * as in the paper's offline stage.  mpt_project builds the same matrix from
+ * the conductor block S = P^T X^{-1} P instead, with no solve per basis
+ * vector.  Either way w^H G w cancels terms that grow like omega^2 / (eps h),
+ * so certificates of an accurate reduced model have a rounding floor that
+ * depends on how X^{-1} Z was computed.  Output G: (2M+3)^2 complex,
+ * row-major, exactly Hermitian; it may replace the G of a reduced model.
+ * 1 <= M <= 96.  Workspace: mpt_residual_gram_ws_size.  Asynchronous on the
+ * handle's stream. */
+size_t mpt_residual_gram_ws_size(int64_t N, int M);
+mpt_status mpt_residual_gram(mpt_handle h, const double* Z, int64_t ldZ, const double* XinvZ,
+                             int64_t ldY, int64_t N, int M, double* G, void* ws,
+                             size_t ws_bytes);
 
 /* Sparse x tall-skinny product Y = K U (K real CSR, U complex N x M,
  * ldU / ldY >= M).  The bandwidth-bound kernel of the projection. */

@@ -131,11 +131,17 @@ def tensors_mm(rom, a, omega, N0, alpha):
 
 
 # ------------------------------------------------------ certificates (a4)
+def residual_gram_from(Z, XinvZ):
+    """G = Z^H X^{-1} Z (Lemma 4.1) from the residual columns Z and X^{-1} Z;
+    Hermitian by definition, so the two computed triangles are averaged."""
+    G = np.asarray(Z).conj().T @ np.asarray(XinvZ)
+    return 0.5 * (G + G.conj().T)
+
+
 def residual_gram_direct(fo, U, w):
     """G = Z^H X^{-1} Z with Z = [C w_1, C w_2, C w_3, X U, C U] (SuperLU for X^{-1})."""
     Z = np.concatenate([fo.c[:, None] * w, fo.X @ U, fo.c[:, None] * U], 1).astype(np.complex128)
-    G = Z.conj().T @ fo.X_solve(Z)
-    return 0.5 * (G + G.conj().T)  # Hermitian by definition
+    return residual_gram_from(Z, fo.X_solve(Z))
 
 
 def residual_gram_schur(S, cond_idx, c, w, U, KM, UhU, eps_h):

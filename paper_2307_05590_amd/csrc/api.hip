@@ -411,11 +411,16 @@ extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c) {
   return off[14];
 }
 
+static bool row_blocks_ok(const mpt_csr& K) {
+  return K.row_blocks >= 0 && (K.row_blocks <= 1 || K.n % K.row_blocks == 0);
+}
+
 extern "C" mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU,
                                int M, double* Y, int64_t ldY) {
   if (!h) return MPT_E_ARG;
   ARG(K && K->rowptr && K->colind && K->val && U && Y, "NULL pointer");
   ARG(K->n > 0 && K->nnz >= 0 && K->nnz < (int64_t)1 << 31, "bad CSR sizes");
+  ARG(row_blocks_ok(*K), "row_blocks must be >= 0 and divide n");
   ARG(M >= 1 && ldU >= M && ldY >= M, "bad M or leading dimensions");
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(spmm_launch(*K, U, ldU, M, Y, ldY, h->stream));
@@ -432,6 +437,7 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
   ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && S, "NULL input");
   ARG(KM && A0 && CM && g && G && E && N0 && ws, "NULL output");
   ARG(K->n > 0 && M >= 1 && ldU >= M && n_c >= 1 && n_c <= K->n, "bad sizes");
+  ARG(row_blocks_ok(*K), "row_blocks must be >= 0 and divide n");
   ARG(eps_h >= 0.0 && alpha > 0.0, "bad eps_h or alpha");
   ARG(ws_bytes >= mpt_project_ws_size(K->n, M, n_c), "workspace too small");
   HIP_OK(hipSetDevice(h->device));
@@ -491,6 +497,43 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
                      reinterpret_cast<double2*>(KM), reinterpret_cast<double2*>(A0),
                      reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g),
                      reinterpret_cast<double2*>(G), E, N0);
+  HIP_OK(hipGetLastError());
+  return MPT_OK;
+}
+
+// ----------------------------------------- residual Gram from X^{-1} Z
+// G = (P + P^H) / 2 for the L x L contraction P = Z^H (X^{-1} Z)
+__global__ void k_herm_mean(const double2* __restrict__ P, int L, double2* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L * L) return;
+  const int i = e / L, j = e % L;
+  const double2 u = P[i * L + j], t = P[j * L + i];
+  G[e] = make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
+}
+
+extern "C" size_t mpt_residual_gram_ws_size(int64_t N, int M) {
+  if (N < 1 || M < 1 || M > mpt_max_reduced_dim()) return 0;
+  const int L = 2 * M + 3;
+  return align256((size_t)L * L * sizeof(double2)) + mpt::gram_ws_size(N, L, L);
+}
+
+extern "C" mpt_status mpt_residual_gram(mpt_handle h, const double* Z, int64_t ldZ,
+                                        const double* XinvZ, int64_t ldY, int64_t N, int M,
+                                        double* G, void* ws, size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(Z && XinvZ && G && ws, "NULL pointer");
+  ARG(N >= 1 && M >= 1 && M <= mpt_max_reduced_dim(), "bad N or M");
+  const int L = 2 * M + 3;
+  ARG(ldZ >= L && ldY >= L, "leading dimensions below 2M+3");
+  ARG(ws_bytes >= mpt_residual_gram_ws_size(N, M), "workspace too small");
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  char* wsb = reinterpret_cast<char*>(ws);
+  double* P = reinterpret_cast<double*>(wsb);
+  void* gws = wsb + align256((size_t)L * L * sizeof(double2));
+  HIP_OK(gram_launch(Z, ldZ, XinvZ, ldY, N, L, L, P, L, gws, st));
+  hipLaunchKernelGGL(k_herm_mean, dim3((L * L + 255) / 256), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(P), L, reinterpret_cast<double2*>(G));
   HIP_OK(hipGetLastError());
   return MPT_OK;
 }
@@ -709,6 +752,7 @@ extern "C" mpt_status mpt_tensors_im(mpt_handle h, const mpt_csr* curl, const do
                                      size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   ARG(curl && curl->rowptr && curl->colind && curl->val && curl->n >= 1, "bad curl");
+  ARG(row_blocks_ok(*curl), "row_blocks must be >= 0 and divide the row count");
   ARG(face_w && c && w && U && N0 && out && a && omega, "NULL pointer");
   ARG(N >= 1 && M >= 1 && ldU >= M, "bad N / M / ldU");
   ARG(n_c >= 0 && (n_c == 0 || cond), "bad conductor list");
@@ -729,6 +773,7 @@ extern "C" mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const doub
                                       double alpha, double* out, void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   ARG(K && K->rowptr && K->colind && K->val && K->n >= 1, "bad K");
+  ARG(row_blocks_ok(*K), "row_blocks must be >= 0 and divide n");
   ARG(c && w && U && N0 && out && a && omega, "NULL pointer");
   ARG(M >= 1 && ldU >= M, "bad M / ldU");
   ARG(n_c >= 0 && (n_c == 0 || cond), "bad conductor list");

@@ -21,7 +21,8 @@ class MptError(RuntimeError):
 
 class _Csr(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
-                ("colind", C.c_void_p), ("val", C.c_void_p)]
+                ("colind", C.c_void_p), ("val", C.c_void_p), ("row_blocks", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class _Rom(C.Structure):
@@ -63,6 +64,8 @@ def lib():
             "mpt_project_ws_size": ([I64, I32, I64], S),
             "mpt_project": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P,
                              P, P, P, P, P, P, P, P, P, S], I32),
+            "mpt_residual_gram_ws_size": ([I64, I32], S),
+            "mpt_residual_gram": ([P, P, I64, P, I64, I64, I32, P, P, S], I32),
             "mpt_spmm": ([P, P, P, I64, I32, P, I64], I32),
             "mpt_sweep": ([P, P, P, I64, P, P, P], I32),
             "mpt_select_snapshots": ([P, P, I64, P, P, I32, I32, P, P, P], I32),
@@ -154,17 +157,19 @@ class Csr:
     rowptr: torch.Tensor
     colind: torch.Tensor
     val: torch.Tensor
+    row_blocks: int = 1  # layout hint: equal row blocks sharing one spatial order
 
     @classmethod
-    def from_scipy(cls, K, device="cuda"):
+    def from_scipy(cls, K, device="cuda", row_blocks=1):
         K = K.tocsr()
         K.sort_indices()
         return cls(K.shape[0], torch.as_tensor(K.indptr.astype("int32"), device=device),
                    torch.as_tensor(K.indices.astype("int32"), device=device),
-                   torch.as_tensor(K.data.astype("float64"), device=device))
+                   torch.as_tensor(K.data.astype("float64"), device=device), int(row_blocks))
 
     def struct(self):
-        return _Csr(self.n, self.val.numel(), _ptr(self.rowptr), _ptr(self.colind), _ptr(self.val))
+        return _Csr(self.n, self.val.numel(), _ptr(self.rowptr), _ptr(self.colind), _ptr(self.val),
+                    self.row_blocks, 0)
 
 
 @dataclass
@@ -206,6 +211,25 @@ def mpt_spmm(K: Csr, U: torch.Tensor) -> torch.Tensor:
     k = K.struct()
     h._check(lib().mpt_spmm(h.h, C.byref(k), _ptr(U), M, M, _ptr(Y), M))
     return Y
+
+
+def mpt_residual_gram(Z: torch.Tensor, XinvZ: torch.Tensor) -> torch.Tensor:
+    """Residual Gram G = (Z^H Y + Y^H Z) / 2 with Y = X^{-1} Z (Lemma 4.1):
+    Z and Y are N x (2M+3) complex128 on the device; returns G (2M+3)^2."""
+    h = handle(Z.device)
+    _dev_check(Z)
+    _dev_check(XinvZ)
+    N, L = Z.shape
+    if XinvZ.shape != Z.shape or (L - 3) % 2:
+        raise MptError("Z and X^-1 Z must both be N x (2M+3)")
+    M = (L - 3) // 2
+    G = torch.empty((L, L), dtype=torch.complex128, device=Z.device)
+    n = lib().mpt_residual_gram_ws_size(N, M)
+    if n == 0:
+        raise MptError(f"unsupported sizes N={N} M={M}")
+    ws = torch.empty(n, dtype=torch.uint8, device=Z.device)
+    h._check(lib().mpt_residual_gram(h.h, _ptr(Z), L, _ptr(XinvZ), L, N, M, _ptr(G), _ptr(ws), n))
+    return G
 
 
 def mpt_pod_basis(D: torch.Tensor, tol_sigma: float, M_cap: int):

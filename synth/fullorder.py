@@ -211,6 +211,16 @@ class FullOrderSolver:
             self._S = 0.5 * (S + S.T)
         return self._S
 
+    def residual_columns(self, U, w):
+        """Z = [C_sigma w_1..3 | X U | C_sigma U] (N x (2M+3), complex) and
+        X^{-1} Z by this solver, column by column: the inputs of the residual
+        Gram in its full form."""
+        ops = self.ops
+        Z = np.concatenate([ops.c[:, None] * w, self.apply_X(U), ops.c[:, None] * U],
+                           1).astype(np.complex128)
+        Y = self.xinv(np.ascontiguousarray(Z.real)) + 1j * self.xinv(np.ascontiguousarray(Z.imag))
+        return np.ascontiguousarray(Z), np.ascontiguousarray(Y)
+
     def _eig(self):
         if not hasattr(self, "_lam"):
             S = self.schur()

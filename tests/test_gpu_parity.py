@@ -282,6 +282,36 @@ def test_im_matches_oracle_mesh_sums(mpt, case, M):
     assert eR.max() <= 1e-10 and eI.max() <= 1e-10
 
 
+# -------------------------------------------- residual Gram from X^{-1} Z
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 4), ("ellipsoid16", 40), ("magnetic10", 12)])
+def test_residual_gram_matches_oracle(mpt, case, M):
+    c = getattr(_cases, case)()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    Z, Y = c.fs.residual_columns(U, c.w)
+    G = mpt.mpt_residual_gram(_dev(Z, torch.complex128), _dev(Y, torch.complex128)).cpu().numpy()
+    ref = R.residual_gram_from(Z, Y)
+    # rounding of a length-N sum of products, entry by entry
+    scale = np.abs(Z).T @ np.abs(Y)
+    scale = 0.5 * (scale + scale.T)
+    err = np.abs(G - ref) / (64 * 2.2e-16 * scale + 1e-300)
+    print(f"{case} M={M} L={2 * M + 3}: residual Gram err / (64 eps |Z|^T|Y|) max {err.max():.2e}",
+          flush=True)
+    assert np.all(np.abs(G - ref) <= 64 * 2.2e-16 * scale)
+    assert np.array_equal(G, G.conj().T)
+
+
+def test_residual_gram_bad_args(mpt):
+    Z = torch.zeros((50, 9), dtype=torch.complex128, device="cuda")
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_residual_gram(Z, torch.zeros((50, 8), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(mpt.MptError):
+        Z8 = torch.zeros((50, 8), dtype=torch.complex128, device="cuda")
+        mpt.mpt_residual_gram(Z8, Z8)  # 8 is not 2M+3
+    big = torch.zeros((10, 2 * 97 + 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(mpt.MptError):
+        mpt.mpt_residual_gram(big, big)  # M = 97 > 96
+
+
 # ------------------------------------------------------------ selection (a5)
 def test_select_matches_oracle(mpt):
     c = _cases.ellipsoid16()
@@ -289,13 +319,14 @@ def test_select_matches_oracle(mpt):
     U = np.linalg.svd(c.D, full_matrices=False)[0][:, :8]
     rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
     omega = np.logspace(1, 5, 400)
-    rom = mpt.Rom.from_host(host, fo.alpha)
-    w = _dev(omega, torch.float64)
-    out, _ = mpt.mpt_sweep(rom, w)
+    # the certificates of a real reduced model, computed by the oracle; both
+    # selections take the same array
+    out, _ = R.sweep(rom_o, omega, G, fo.alpha)
     snaps = c.snap
-    new, lam, Lmax = mpt.mpt_select_snapshots(w, out, _dev(snaps, torch.float64), 2)
+    new, lam, Lmax = mpt.mpt_select_snapshots(_dev(omega, torch.float64), _dev(out, torch.float64),
+                                              _dev(snaps, torch.float64), 2)
     torch.cuda.synchronize()
-    ref_new, ref_L, ref_lam = R.select_snapshots(omega, out.cpu().numpy()[:, 12:], snaps, 2)
+    ref_new, ref_L, ref_lam = R.select_snapshots(omega, out[:, 12:], snaps, 2)
     assert np.array_equal(new.cpu().numpy(), ref_new)
     assert Lmax.item() == ref_L
     assert np.array_equal(lam.cpu().numpy(), ref_lam)
@@ -343,12 +374,40 @@ def test_select_ties_and_empty_intervals(mpt):
 def test_spmm_matches_scipy(mpt):
     c = _cases.ellipsoid16()
     K = mpt.Csr.from_scipy(c.ops.K)
+    # the Yee ordering: three equal blocks (edge orientations) in one spatial order
+    K3 = mpt.Csr.from_scipy(c.ops.K, row_blocks=3)
     rng = np.random.default_rng(0)
     for M in (1, 7, 16, 33, 48, 96):
         U = rng.standard_normal((c.ops.N, M)) + 1j * rng.standard_normal((c.ops.N, M))
-        Y = mpt.mpt_spmm(K, _dev(U, torch.complex128)).cpu().numpy()
+        Ud = _dev(U, torch.complex128)
+        Y = mpt.mpt_spmm(K, Ud).cpu().numpy()
         ref = c.ops.K @ U
         assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max(), M
+        # the layout hint changes the schedule only: every row is summed in the same order
+        assert np.array_equal(mpt.mpt_spmm(K3, Ud).cpu().numpy(), Y), M
+
+
+def test_spmm_row_blocks_ragged_and_rejected(mpt):
+    # a random sparse matrix whose row count is a multiple of 5 but not of 7,
+    # with empty rows and rows longer than one gather batch
+    import scipy.sparse as sp
+    rng = np.random.default_rng(3)
+    n = 5 * 613
+    A = sp.random(n, n, density=6.0 / n, random_state=4, format="csr")
+    A = (A + sp.diags(rng.standard_normal(n)) + sp.csr_matrix(
+        (rng.standard_normal(40), (np.full(40, 17), np.arange(40)), ), shape=(n, n))).tocsr()
+    A[100:140] = 0.0
+    A.eliminate_zeros()
+    U = rng.standard_normal((n, 5)) + 1j * rng.standard_normal((n, 5))
+    Ud = _dev(U, torch.complex128)
+    Y1 = mpt.mpt_spmm(mpt.Csr.from_scipy(A), Ud).cpu().numpy()
+    Y5 = mpt.mpt_spmm(mpt.Csr.from_scipy(A, row_blocks=5), Ud).cpu().numpy()
+    ref = A @ U
+    assert np.abs(Y1 - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert np.array_equal(Y5, Y1)
+    for bad in (7, -1):
+        with pytest.raises(mpt.MptError):
+            mpt.mpt_spmm(mpt.Csr.from_scipy(A, row_blocks=bad), Ud)
 
 
 @pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("ellipsoid16", 48), ("magnetic10", 12)])
@@ -585,8 +644,8 @@ def test_full_size_ellipsoid48_sampled(mpt):
     tol, cap = p.wl.tol_sigma, p.wl.m_cap
     print(f"ellipsoid48: N={ops.N} D={p.D.shape} residual={p.snap_residual:.1e}", flush=True)
     U, sig, M = mpt.mpt_pod_basis(_dev(p.D, torch.complex128), tol, cap)
-    rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
-                          _dev(p.w, torch.float64), _dev(p.o, torch.float64),
+    rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K, row_blocks=3), _dev(ops.c, torch.float64),
+                          ops.eps_h, _dev(p.w, torch.float64), _dev(p.o, torch.float64),
                           _dev(ops.vol, torch.float64), ops.alpha, U,
                           _dev(ops.cond_idx, torch.int32), _dev(p.S, torch.float64))
     omega_d = _dev(p.omega, torch.float64)

@@ -277,6 +277,13 @@ def test_certificate_gform_equals_direct_residual():
     Dd = R.certificate_direct(fo, U, a, om, c.w)
     assert np.all(np.abs(Dg - Dd) <= 1e-4 * np.abs(Dd) + 1e-12 * np.abs(Dd).max())
     assert np.all(Dd >= 0)
+    # the same G from the residual columns and X^{-1} applied to each of them,
+    # by the input generator's spectral solver and by SuperLU
+    Z, Y = c.fs.residual_columns(U, c.w)
+    for G in (R.residual_gram_from(Z, Y), R.residual_gram_direct(fo, U, c.w)):
+        assert np.array_equal(G, G.conj().T)
+        Dg2 = R.certificate_gform(G, a, om, fo.alpha)
+        assert np.all(np.abs(Dg2 - Dd) <= 1e-4 * np.abs(Dd) + 1e-12 * np.abs(Dd).max())
 
 
 # ------------------------------------------------------------ selection
