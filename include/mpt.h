@@ -248,6 +248,24 @@ mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* ome
                              const double* dout, double* dL_domega, double* sig_dsig,
                              int32_t* status);
 
+/* Per-material sigma sensitivities of an object with two conducting
+ * materials (C_sigma = C_1 + C_2, C_m proportional to sigma_m on material
+ * m's edges; basis frozen, K_M independent of sigma).  CM1 (M x M), g1
+ * (3 x M) and E1 (3 x 3, real) are the parts of C_M, g and E that material 1
+ * contributes (mpt_project of material 1's conductivities alone).  The
+ * adjoint of each frequency's solve gives
+ *   sigma_1 dL/dsigma_1 = sum_k [ -w_k Im sum_i lambda_i^H (g_1,i + C_M1 a_i)
+ *                                 + sum_p dL/dI_p (w_k a^3/4)(E_1 + Re(a_i^H C_M1 a_j
+ *                                   + a_i^H g_1,j + g_1,i^H a_j))_p ],
+ * and sigma_2 dL/dsigma_2 = sum_k w_k dL/dw_k - sigma_1 dL/dsigma_1 (the
+ * reduced model depends on sigma w only).  Outputs: dL_domega (n) as in
+ * mpt_sweep_adjoint, sig_dsig (2 device doubles: material 1, material 2),
+ * status.  M <= 64 (MPT_E_UNSUPPORTED otherwise).  Asynchronous. */
+mpt_status mpt_sweep_adjoint_materials(mpt_handle h, const mpt_rom* rom, const double* CM1,
+                                       const double* g1, const double* E1, const double* omega,
+                                       int64_t n, const double* dout, double* dL_domega,
+                                       double* sig_dsig, int32_t* status);
+
 /* Batched adjoint over a dictionary (same layout as mpt_sweep_batched);
  * sig_dsig has one value per object. */
 mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,

@@ -290,3 +290,33 @@ def forward_sensitivity(rom, omega, alpha, wR, wI):
         dw[k] = sum(wR[k, p] * dR[i, j] + wI[k, p] * dI[i, j] for p, (i, j) in enumerate(PAIRS))
         ds += sum(wR[k, p] * dRs[i, j] + wI[k, p] * dIs[i, j] for p, (i, j) in enumerate(PAIRS))
     return dw, ds
+
+
+def forward_sensitivity_materials(rom, parts, omega, alpha, wR, wI):
+    """sigma_m dL/dsigma_m for an object of several conducting materials (L as
+    in forward_sensitivity).  C_sigma is the sum of one term per material,
+    each proportional to that material's sigma, so C_M, g and E split into
+    parts (C_M,m, g_m, E_m), each the projection of one material's edges
+    alone; K_M and the basis do not depend on sigma.  Forward
+    differentiation: A (sigma_m da/dsigma_m) = i w (g_m + C_M,m a), and I
+    depends on sigma_m explicitly through C_M,m, g_m and E_m.
+    parts: list of dicts with keys CM, g, E.  Returns one value per part."""
+    omega = np.atleast_1d(np.asarray(omega, float))
+    a3 = alpha ** 3
+    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    KM, CM, g = rom["KM"], rom["CM"], rom["g"]
+    out = np.zeros(len(parts))
+    for k, om in enumerate(omega):
+        A = A0 - 1j * om * CM
+        a = np.linalg.solve(A, 1j * om * g)
+        for m, pm in enumerate(parts):
+            Cm, gm, Em = pm["CM"], pm["g"], pm["E"]
+            dam = np.linalg.solve(A, 1j * om * (gm + Cm @ a))
+            dR = -0.25 * a3 * np.real(dam.conj().T @ KM @ a + a.conj().T @ KM @ dam)
+            dI = 0.25 * a3 * om * (Em + np.real(a.conj().T @ Cm @ a + gm.conj().T @ a
+                                                + a.conj().T @ gm)
+                                   + np.real(dam.conj().T @ CM @ a + a.conj().T @ CM @ dam
+                                             + g.conj().T @ dam + dam.conj().T @ g))
+            out[m] += sum(wR[k, p] * dR[i, j] + wI[k, p] * dI[i, j]
+                          for p, (i, j) in enumerate(PAIRS))
+    return out

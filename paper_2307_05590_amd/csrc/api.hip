@@ -576,6 +576,36 @@ extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const 
   return MPT_OK;
 }
 
+extern "C" mpt_status mpt_sweep_adjoint_materials(mpt_handle h, const mpt_rom* rom,
+                                                  const double* CM1, const double* g1,
+                                                  const double* E1, const double* omega,
+                                                  int64_t n, const double* dout,
+                                                  double* dL_domega, double* sig_dsig,
+                                                  int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the adjoint sweep takes M <= 64");
+  ARG(n >= 1, "n must be >= 1");
+  ARG(CM1 && g1 && E1, "NULL material part");
+  ARG(omega && dout && dL_domega && sig_dsig && status, "NULL pointer");
+  HIP_OK(hipSetDevice(h->device));
+  // scratch: the (discarded) forward outputs and the per-frequency sigma_1 terms
+  const size_t fwd_bytes = align256((size_t)n * 18 * 8);
+  s = ensure_scr(h, fwd_bytes + align256((size_t)n * 8));
+  if (s != MPT_OK) return s;
+  double* fwd = reinterpret_cast<double*>(h->scr);
+  double* dsig = reinterpret_cast<double*>(reinterpret_cast<char*>(h->scr) + fwd_bytes);
+  mpt::MatSens ms;
+  ms.CM1 = CM1;
+  ms.g1 = g1;
+  ms.E1 = E1;
+  ms.dsig = dsig;
+  HIP_OK(sweep_launch(*rom, omega, n, fwd, nullptr, status, dout, dL_domega, h->stream, ms));
+  HIP_OK(mpt::material_reduce(omega, dL_domega, dsig, n, sig_dsig, h->stream));
+  return MPT_OK;
+}
+
 // ------------------------------------------------------ pencil form sweep
 extern "C" size_t mpt_pencil_bytes(int M) {
   if (M < 1 || M > 96) return 0;

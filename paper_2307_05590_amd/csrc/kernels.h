@@ -9,10 +9,24 @@ namespace mpt {
 
 int bucket_of(int M);
 
+// Material-1 part of a reduced model (C_M1 = U^H C_sigma,1 U, g_1, E_1:
+// the projections of material 1's conducting edges alone) for
+// sigma_1 dL/dsigma_1 in the adjoint sweep; dsig receives one value per
+// frequency.  All NULL: not computed.
+struct MatSens {
+  const double* CM1 = nullptr;
+  const double* g1 = nullptr;
+  const double* E1 = nullptr;
+  double* dsig = nullptr;
+};
+
 // sweep.hip
 hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom,
-                        hipStream_t st);
+                        hipStream_t st, const MatSens& ms = MatSens{});
+// out[0] = sum_k dsig[k], out[1] = sum_k omega_k dom[k] - out[0]
+hipError_t material_reduce(const double* omega, const double* dom, const double* dsig, int64_t n,
+                           double* out, hipStream_t st);
 hipError_t persistent_launch(int bucket, bool adj, const mpt_rom* roms, const int4* items,
                              int n_items, unsigned int* counter, const double* omega, double* out,
                              int32_t* status, const double* dout, double* dom, int wpg, int groups,

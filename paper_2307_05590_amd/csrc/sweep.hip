@@ -9,7 +9,7 @@ namespace mpt {
 template <int MAXM, bool ADJ>
 hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom, int wpg,
-                        hipStream_t st);
+                        const MatSens& ms, hipStream_t st);
 template <int MAXM, bool ADJ>
 hipError_t launch_persistent(const mpt_rom* roms, const int4* items, int n_items,
                              unsigned int* counter, const double* omega, double* out,
@@ -46,22 +46,23 @@ hipError_t sweep_big_launch(const mpt_rom& R, const double* omega, int64_t n, do
 
 hipError_t sweep_launch(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom,
-                        hipStream_t st) {
+                        hipStream_t st, const MatSens& ms) {
   if (n <= 0) return hipSuccess;
   const bool adj = dout != nullptr;
   if (R.M > 64) {  // LDS-resident kernel; no adjoint form at this size
     if (adj) return hipErrorInvalidValue;
     return sweep_big_launch(R, omega, n, out, a_out, status, st);
   }
+  if (!adj && ms.CM1) return hipErrorInvalidValue;  // material terms need the adjoint
   switch (bucket_of(R.M)) {
-    case 16: return adj ? launch_plain<16, true>(R, omega, n, out, a_out, status, dout, dom, 4, st)
-                        : launch_plain<16, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);
-    case 32: return adj ? launch_plain<32, true>(R, omega, n, out, a_out, status, dout, dom, 4, st)
-                        : launch_plain<32, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);
-    case 48: return adj ? launch_plain<48, true>(R, omega, n, out, a_out, status, dout, dom, 2, st)
-                        : launch_plain<48, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);
-    default: return adj ? launch_plain<64, true>(R, omega, n, out, a_out, status, dout, dom, 2, st)
-                        : launch_plain<64, false>(R, omega, n, out, a_out, status, dout, dom, 4, st);
+    case 16: return adj ? launch_plain<16, true>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st)
+                        : launch_plain<16, false>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st);
+    case 32: return adj ? launch_plain<32, true>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st)
+                        : launch_plain<32, false>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st);
+    case 48: return adj ? launch_plain<48, true>(R, omega, n, out, a_out, status, dout, dom, 2, ms, st)
+                        : launch_plain<48, false>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st);
+    default: return adj ? launch_plain<64, true>(R, omega, n, out, a_out, status, dout, dom, 2, ms, st)
+                        : launch_plain<64, false>(R, omega, n, out, a_out, status, dout, dom, 4, ms, st);
   }
 }
 
@@ -86,6 +87,39 @@ hipError_t persistent_launch(int bucket, bool adj, const mpt_rom* roms, const in
 
 hipError_t reset_counters(unsigned int* c, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, c, n);
+  return hipGetLastError();
+}
+
+// sigma_1 dL/dsigma_1 = sum_k dsig[k]; the other material takes the rest of
+// sum_k omega_k dL/domega_k (fixed order, one workgroup)
+__global__ void k_material_reduce(const double* __restrict__ omega,
+                                  const double* __restrict__ dom, const double* __restrict__ dsig,
+                                  int64_t n, double* __restrict__ out) {
+  __shared__ double pa[256], pb[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    a += dsig[k];
+    b += omega[k] * dom[k];
+  }
+  pa[threadIdx.x] = a;
+  pb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      pa[threadIdx.x] += pa[threadIdx.x + s];
+      pb[threadIdx.x] += pb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = pa[0];
+    out[1] = pb[0] - pa[0];
+  }
+}
+
+hipError_t material_reduce(const double* omega, const double* dom, const double* dsig, int64_t n,
+                           double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_material_reduce, dim3(1), dim3(256), 0, st, omega, dom, dsig, n, out);
   return hipGetLastError();
 }
 

@@ -125,7 +125,8 @@ __device__ __forceinline__ double seg_rs16(double (&v)[16], int wl) {
 //   out:    18 doubles for this omega
 //   status: one int
 //   ADJ:    dout (18 doubles, first 12 used) -> dom (1 double);
-//           lds_lu: MAXM x (MAXM+1) double2 private to the segment.
+//           lds_lu: MAXM x (MAXM+1) double2 private to the segment;
+//           with ms.CM1 set, also dsig (1 double) = sigma_1 dL/dsigma_1.
 //   red_lds: 64 doubles private to the segment.
 //   valid:  false for a padding segment (computes, writes nothing).
 template <int MAXM, bool ADJ>
@@ -134,7 +135,8 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
                                             int32_t* __restrict__ status,
                                             const double* __restrict__ dout,
                                             double* __restrict__ dom, double2* lds_lu,
-                                            double* red_lds) {
+                                            double* red_lds, const MatSens& ms,
+                                            double* __restrict__ dsig) {
   constexpr int L = SegOf<MAXM>::L;
   const int wl = __lane_id();
   const int ll = wl & (L - 1);   // lane within the segment
@@ -405,12 +407,13 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     // lambda = P^T y: lane r (original row r) takes y[order(r)]
     const int src = base + (order >= 0 ? order : ll);
     double acc = 0.0;
+    double2 lam[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double2 lam = make_double2(shfl_d(vk[i].x, src), shfl_d(vk[i].y, src));
+      lam[i] = make_double2(shfl_d(vk[i].x, src), shfl_d(vk[i].y, src));
       if (act) {
         const double2 t = make_double2(gl[i].x + Ca[i].x, gl[i].y + Ca[i].y);
-        acc -= cmulc(lam, t).y;  // -Im lambda^H (g + C_M a)
+        acc -= cmulc(lam[i], t).y;  // -Im lambda^H (g + C_M a)
       }
     }
     // explicit omega-dependence of I (prefactor w): sum_p tau_p I_p / w
@@ -418,6 +421,53 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     const double tot = seg_sum<L>(acc);
     if (valid && ll == 0) *dom = tot;
     __builtin_amdgcn_wave_barrier();
+
+    // ---- sigma_1 dL/dsigma_1 for the material-1 part (C_M1, g_1, E_1) of
+    // C_M, g and E: the right-hand side of the sensitivity system is
+    // i w (g_1 + C_M1 a), and I depends on sigma_1 explicitly through the
+    // same three parts (basis frozen, K_M independent of sigma)
+    if (ms.CM1 != nullptr) {
+      const double2* C1 = reinterpret_cast<const double2*>(ms.CM1);
+      const double2* g1v = reinterpret_cast<const double2*>(ms.g1);
+      double2 C1a[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) C1a[i] = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int j = 0; j < M; ++j) {
+        double2 aj[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) aj[i] = seg_bcast2<L>(x[i], base + j);
+        if (act) {
+          const double2 cc = cconj(C1[j * M + ll]);  // Hermitian: row ll from column ll
+#pragma unroll
+          for (int i = 0; i < 3; ++i) C1a[i] = cfma(C1a[i], cc, aj[i]);
+        }
+      }
+      const double c4 = 0.25 * a3 * om;
+      double accs = 0.0;
+      if (act) {
+        double2 g1l[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          g1l[i] = g1v[i * M + ll];
+          const double2 t = make_double2(g1l[i].x + C1a[i].x, g1l[i].y + C1a[i].y);
+          accs -= om * cmulc(lam[i], t).y;  // -w Im lambda^H (g_1 + C_M1 a)
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+          const int i = kPi[p], j = kPj[p];
+          accs += dout[6 + p] * c4 *
+                  (cmulc(x[i], C1a[j]).x + cmulc(x[i], g1l[j]).x + cmulc(g1l[i], x[j]).x);
+        }
+      }
+      if (ll == 0) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) accs += dout[6 + p] * c4 * ms.E1[3 * kPi[p] + kPj[p]];
+      }
+      const double tots = seg_sum<L>(accs);
+      if (valid && ll == 0) *dsig = tots;
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
@@ -428,7 +478,7 @@ __global__ __launch_bounds__(256) void k_sweep(const mpt_rom R, const double* __
                                                double* __restrict__ a_out,
                                                int32_t* __restrict__ status,
                                                const double* __restrict__ dout,
-                                               double* __restrict__ dom) {
+                                               double* __restrict__ dom, const MatSens ms) {
   constexpr int L = SegOf<MAXM>::L, S = SegOf<MAXM>::S;
   extern __shared__ double2 lds[];
   __shared__ double red[4 * 64 * S];
@@ -445,7 +495,7 @@ __global__ __launch_bounds__(256) void k_sweep(const mpt_rom R, const double* __
     sweep_point<MAXM, ADJ>(R, omega[kc], valid, out + 18 * kc,
                            a_out ? a_out + (size_t)kc * 6 * R.M : nullptr, status + kc,
                            ADJ ? dout + 18 * kc : nullptr, ADJ ? dom + kc : nullptr, my_lds,
-                           my_red);
+                           my_red, ms, ms.dsig ? ms.dsig + kc : nullptr);
   }
 }
 
@@ -476,7 +526,7 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(
       const int64_t k = (int64_t)w.y + (valid ? r + seg : w.z - 1);
       sweep_point<MAXM, ADJ>(R, omega[k], valid, out + 18 * k, nullptr, status + k,
                              ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
-                             my_red);
+                             my_red, MatSens{}, nullptr);
     }
   }
 }
@@ -484,14 +534,14 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(
 template <int MAXM, bool ADJ>
 hipError_t launch_plain(const mpt_rom& R, const double* omega, int64_t n, double* out,
                         double* a_out, int32_t* status, const double* dout, double* dom, int wpg,
-                        hipStream_t st) {
+                        const MatSens& ms, hipStream_t st) {
   constexpr int S = SegOf<MAXM>::S;
   const int64_t waves = (n + S - 1) / S;
   int64_t groups = (waves + wpg - 1) / wpg;
   if (groups > 65535 * 8) groups = 65535 * 8;
   const size_t lds = ADJ ? (size_t)wpg * S * MAXM * (MAXM + 1) * sizeof(double2) : 0;
   hipLaunchKernelGGL((k_sweep<MAXM, ADJ>), dim3((unsigned)groups), dim3(64 * wpg), lds, st, R,
-                     omega, n, out, a_out, status, dout, dom);
+                     omega, n, out, a_out, status, dout, dom, ms);
   return hipGetLastError();
 }
 

@@ -3,11 +3,11 @@
 
 namespace mpt {
 template hipError_t launch_plain<64, false>(const mpt_rom&, const double*, int64_t, double*,
-    double*, int32_t*, const double*, double*, int, hipStream_t);
+    double*, int32_t*, const double*, double*, int, const MatSens&, hipStream_t);
 template hipError_t launch_persistent<64, false>(const mpt_rom*, const int4*, int,
     unsigned int*, const double*, double*, int32_t*, const double*, double*, int, int, hipStream_t);
 template hipError_t launch_plain<64, true>(const mpt_rom&, const double*, int64_t, double*,
-    double*, int32_t*, const double*, double*, int, hipStream_t);
+    double*, int32_t*, const double*, double*, int, const MatSens&, hipStream_t);
 template hipError_t launch_persistent<64, true>(const mpt_rom*, const int4*, int,
     unsigned int*, const double*, double*, int32_t*, const double*, double*, int, int, hipStream_t);
 }  // namespace mpt

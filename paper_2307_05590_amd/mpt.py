@@ -66,6 +66,7 @@ def lib():
                              P, P, P, P, P, P, P, P, P, S], I32),
             "mpt_residual_gram_ws_size": ([I64, I32], S),
             "mpt_residual_gram": ([P, P, I64, P, I64, I64, I32, P, P, S], I32),
+            "mpt_sweep_adjoint_materials": ([P, P, P, P, P, P, I64, P, P, P, P], I32),
             "mpt_spmm": ([P, P, P, I64, I32, P, I64], I32),
             "mpt_sweep": ([P, P, P, I64, P, P, P], I32),
             "mpt_select_snapshots": ([P, P, I64, P, P, I32, I32, P, P, P], I32),
@@ -463,6 +464,26 @@ def mpt_sweep_adjoint(rom: Rom, omega, dout):
     r = rom.struct()
     h._check(lib().mpt_sweep_adjoint(h.h, C.byref(r), _ptr(omega), n, _ptr(dout), _ptr(dom),
                                      _ptr(sds), _ptr(st)))
+    return dom, sds, st
+
+
+def mpt_sweep_adjoint_materials(rom: Rom, part1: Rom, omega, dout):
+    """Per-material sigma sensitivities of a two-material object: part1 is the
+    reduced model projected with material 1's conductivities alone (its CM, g
+    and E are used).  Returns (dL/domega (n), [sigma_1 dL/dsigma_1,
+    sigma_2 dL/dsigma_2] (2), status)."""
+    h = handle(omega.device)
+    _dev_check(omega, dout, part1.CM, part1.g, part1.E)
+    if part1.M != rom.M:
+        raise MptError("material part and model must share the basis")
+    n = omega.numel()
+    dom = torch.empty(n, dtype=torch.float64, device=omega.device)
+    sds = torch.empty(2, dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    r = rom.struct()
+    h._check(lib().mpt_sweep_adjoint_materials(h.h, C.byref(r), _ptr(part1.CM), _ptr(part1.g),
+                                               _ptr(part1.E), _ptr(omega), n, _ptr(dout),
+                                               _ptr(dom), _ptr(sds), _ptr(st)))
     return dom, sds, st
 
 

@@ -40,6 +40,13 @@ def ellipsoid16():
 
 
 @functools.lru_cache(maxsize=None)
+def shell16():
+    """Two conducting materials that both carry eddy currents: a magnetic
+    core (sigma 6e6, mu_r 50, r < 1.2) in a non-magnetic shell (sigma 3.5e7)."""
+    return Case(16, shell_sphere(1.2, 2.0, (6e6, 50.0), (3.5e7, 1.0)), np.logspace(1, 6, 8))
+
+
+@functools.lru_cache(maxsize=None)
 def magnetic10():
     return Case(10, shell_sphere(1.0, 2.0, (6e6, 50.0), (3.5e7, 1.0)), np.logspace(1, 6, 8))
 

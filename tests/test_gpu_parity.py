@@ -522,6 +522,77 @@ def test_adjoint_matches_forward_sensitivity(mpt):
     assert abs(sds.item() - ref_s) <= 1e-8 * abs(ref_s)
 
 
+def _objective_dout(o, N0):
+    """dJ/dout for J = sum (R~ - N0)^2 + I^2 over the stored pairs (off-diagonal
+    pairs count twice)."""
+    mult = np.array([1.0 if i == j else 2.0 for i, j in PAIRS])
+    N0p = np.array([N0[i, j] for i, j in PAIRS])
+    dout = np.zeros((o.shape[0], 18))
+    dout[:, :6] = 2 * (o[:, :6] - N0p) * mult
+    dout[:, 6:12] = 2 * o[:, 6:12] * mult
+    return dout
+
+
+def _part_rom(mpt, rom_o, part, alpha):
+    host = {"KM": rom_o["KM"], "A0": rom_o["KM"], "CM": part["CM"],
+            "g": np.ascontiguousarray(part["g"].T), "G": np.eye(2 * part["CM"].shape[0] + 3),
+            "E": part["E"], "N0": rom_o["N0"]}
+    return mpt.Rom.from_host(host, alpha)
+
+
+def test_material_adjoint_whole_model_is_sigma_identity(mpt):
+    # one material: its part is the whole model, and sigma_1 dL/dsigma_1 is
+    # sum_k omega_k dL/domega_k; nothing is left for a second material
+    c = _cases.ellipsoid16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :10]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    rom = mpt.Rom.from_host(host, fo.alpha)
+    omega = np.logspace(1, 6, 61)
+    w = _dev(omega, torch.float64)
+    out, _ = mpt.mpt_sweep(rom, w)
+    dout = _dev(_objective_dout(out.cpu().numpy(), rom_o["N0"]), torch.float64)
+    dom, sds, st = mpt.mpt_sweep_adjoint(rom, w, dout)
+    whole = _part_rom(mpt, rom_o, {"CM": rom_o["CM"], "g": rom_o["g"], "E": rom_o["E"]}, fo.alpha)
+    dom2, s12, st2 = mpt.mpt_sweep_adjoint_materials(rom, whole, w, dout)
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0 and int(st2.abs().max()) == 0
+    assert torch.equal(dom, dom2)
+    s1, s2 = s12.cpu().numpy()
+    print(f"whole-model part: {s1:.6e} vs sigma identity {sds.item():.6e}; rest {s2:.2e}", flush=True)
+    assert abs(s1 - sds.item()) <= 1e-10 * abs(sds.item())
+    assert abs(s2) <= 1e-10 * abs(sds.item())
+
+
+def test_material_adjoint_matches_oracle(mpt):
+    # two materials that both carry eddy currents (magnetic core in a shell)
+    c = _cases.shell16()
+    fo = c.oracle_fo()
+    U = np.linalg.svd(c.D, full_matrices=False)[0][:, :10]
+    rom_o, G, host = oracle_rom(fo, U, c.w, c.o, c.S, c.ops.cond_idx)
+    sig = c.ops.sigma_e
+    parts = []
+    for s_m in np.unique(sig[sig > 0]):
+        pr = R.project(fo.K, np.where(sig == s_m, fo.c, 0.0), fo.eps_h, c.w, U)
+        parts.append({"CM": pr["CM"], "g": pr["g"], "E": pr["E"]})
+    rom = mpt.Rom.from_host(host, fo.alpha)
+    omega = np.logspace(1, 6, 97)
+    w = _dev(omega, torch.float64)
+    out, _ = mpt.mpt_sweep(rom, w)
+    dout_h = _objective_dout(out.cpu().numpy(), rom_o["N0"])
+    dom, s12, st = mpt.mpt_sweep_adjoint_materials(rom, _part_rom(mpt, rom_o, parts[0], fo.alpha),
+                                                   w, _dev(dout_h, torch.float64))
+    torch.cuda.synchronize()
+    assert int(st.abs().max()) == 0
+    ref = R.forward_sensitivity_materials(rom_o, parts, omega, fo.alpha, dout_h[:, :6],
+                                          dout_h[:, 6:12])
+    ref_w, _ = R.forward_sensitivity(rom_o, omega, fo.alpha, dout_h[:, :6], dout_h[:, 6:12])
+    got = s12.cpu().numpy()
+    print(f"per-material sigma terms {got} vs oracle {ref}", flush=True)
+    assert np.abs(dom.cpu().numpy() - ref_w).max() <= 1e-8 * np.abs(ref_w).max()
+    assert np.all(np.abs(got - ref) <= 1e-8 * np.abs(ref).max())
+
+
 def test_autograd_fd_and_sigma_identity(mpt):
     c = _cases.ellipsoid16()
     fo = c.oracle_fo()

@@ -352,6 +352,47 @@ def test_forward_sensitivity_matches_central_differences():
     assert abs(ds - np.sum(om * dw)) <= 1e-10 * abs(ds)
 
 
+def test_material_sensitivities_pins():
+    """sigma_m dL/dsigma_m per material of a two-material shell (core
+    sigma 6e6, mu_r 50; shell sigma 3.5e7): one part holding the whole model
+    gives sigma dL/dsigma; the parts sum to sum_k omega_k dL/domega_k (the
+    model depends on sigma omega only); central differences in sigma_1."""
+    c = _cases.shell16()
+    fo, U, rom = _rom(c, 10)
+    om = np.array([30.0, 2e3, 1e5])
+    rng = np.random.default_rng(7)
+    wR = rng.standard_normal((3, 6)) * 1e6
+    wI = rng.standard_normal((3, 6)) * 1e6
+    sig = c.ops.sigma_e
+    parts = []
+    for s_m in np.unique(sig[sig > 0]):
+        cm = np.where(sig == s_m, fo.c, 0.0)
+        pr = R.project(fo.K, cm, fo.eps_h, c.w, U)
+        parts.append({"CM": pr["CM"], "g": pr["g"], "E": pr["E"]})
+    assert len(parts) == 2
+    whole = R.forward_sensitivity_materials(rom, [{"CM": rom["CM"], "g": rom["g"], "E": rom["E"]}],
+                                            om, fo.alpha, wR, wI)
+    dw, ds = R.forward_sensitivity(rom, om, fo.alpha, wR, wI)
+    assert abs(whole[0] - ds) <= 1e-10 * abs(ds)
+    per = R.forward_sensitivity_materials(rom, parts, om, fo.alpha, wR, wI)
+    ident = np.sum(om * dw)
+    assert abs(per.sum() - ident) <= 1e-8 * np.abs(per).max()
+    assert np.all(np.abs(per) > 1e-3 * np.abs(per).max())  # both materials matter
+
+    def L(h):
+        r2 = dict(rom)
+        r2["CM"] = rom["CM"] + h * parts[0]["CM"]
+        r2["g"] = rom["g"] + h * parts[0]["g"]
+        r2["E"] = rom["E"] + h * parts[0]["E"]
+        a = R.reduced_solve(r2, om)
+        Rt, I = R.tensors_mm(r2, a, om, rom["N0"], fo.alpha)
+        return np.sum(wR * R.pack(Rt) + wI * R.pack(I))
+
+    # step 1e-4: truncation ~1e-8 relative, rounding below that
+    fd = (L(1e-4) - L(-1e-4)) / 2e-4
+    assert abs(fd - per[0]) <= 1e-6 * abs(per[0])
+
+
 def test_select_threshold_variant_limits():
     """theta = 1 keeps exactly the interval of the global maximum of Delta
     over all frequencies; theta -> 0 keeps every non-empty interval, in the
