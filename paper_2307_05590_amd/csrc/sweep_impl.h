@@ -197,19 +197,23 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
         pinv = inv;  // kept for the back substitution
       }
       const bool upd = !done;
-      const double2 l = cmul(A[k], inv);
-      if (upd) A[k] = l;
+      const double2 l0 = cmul(A[k], inv);
+      if (upd) A[k] = l0;
+      // rows already eliminated take a zero multiplier (x - 0 * y = x for
+      // finite y) instead of a predicated update: no select per entry, and
+      // the unrolled elimination stays small enough for short branches
+      const double2 l = upd ? l0 : make_double2(0.0, 0.0);
 #pragma unroll
       for (int j = k + 1; j < MAXM; ++j) {
         if (j < M) {
           const double2 pr = seg_bcast2<L>(A[j], p);
-          if (upd) A[j] = cfms(A[j], l, pr);
+          A[j] = cfms(A[j], l, pr);
         }
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const double2 pb = seg_bcast2<L>(b[i], p);
-        if (upd) b[i] = cfms(b[i], l, pb);
+        b[i] = cfms(b[i], l, pb);
       }
     }
   }
