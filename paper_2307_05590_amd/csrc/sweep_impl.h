@@ -51,6 +51,12 @@ template <int L>
 __device__ __forceinline__ double2 seg_bcast2(double2 v, int src) {
   return make_double2(seg_bcast<L>(v.x, src), seg_bcast<L>(v.y, src));
 }
+// src already wave-uniform (an SGPR): no v_readfirstlane per call for L = 64
+template <int L>
+__device__ __forceinline__ double2 seg_bcast2u(double2 v, int src) {
+  if constexpr (L == 64) return bcast2(v, src);
+  else return make_double2(shfl_d(v.x, src), shfl_d(v.y, src));
+}
 template <int L>
 __device__ __forceinline__ double seg_max(double v) {
   return group_max<L>(v);  // DPP inside rows, permlane swaps across rows
@@ -187,7 +193,9 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
         bad = 1;
         p = seg_first<L>(!done, base);
       }
-      const double2 piv = seg_bcast2<L>(A[k], p);
+      // for L = 64 the pivot lane is wave-uniform: read it into an SGPR once
+      const int pu = (L == 64) ? __builtin_amdgcn_readfirstlane(p) : p;
+      const double2 piv = seg_bcast2u<L>(A[k], pu);
       const double d = piv.x * piv.x + piv.y * piv.y;
       if (!(d > 0.0) || !isfinite(d)) bad = 1;
       const double2 inv = crecip(piv);
@@ -203,16 +211,19 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
       // finite y) instead of a predicated update: no select per entry, and
       // the unrolled elimination stays small enough for short branches
       const double2 l = upd ? l0 : make_double2(0.0, 0.0);
+      // columns j >= M hold exact zeros in every lane, so their update is a
+      // no-op: up to M = 48 no per-column branch (one basic block per step);
+      // the 64-wide bucket keeps the branch, or its registers spill
 #pragma unroll
       for (int j = k + 1; j < MAXM; ++j) {
-        if (j < M) {
-          const double2 pr = seg_bcast2<L>(A[j], p);
+        if (MAXM <= 48 || j < M) {
+          const double2 pr = seg_bcast2u<L>(A[j], pu);
           A[j] = cfms(A[j], l, pr);
         }
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 pb = seg_bcast2<L>(b[i], p);
+        const double2 pb = seg_bcast2u<L>(b[i], pu);
         b[i] = cfms(b[i], l, pb);
       }
     }
@@ -227,10 +238,11 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     if (k < M) {
       int q = seg_first<L>(order == k, base);
       if (q < 0) q = base;  // only after a flagged breakdown
-      const double2 inv = seg_bcast2<L>(pinv, q);
+      if (L == 64) q = __builtin_amdgcn_readfirstlane(q);
+      const double2 inv = seg_bcast2u<L>(pinv, q);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double2 xk = cmul(seg_bcast2<L>(b[i], q), inv);
+        const double2 xk = cmul(seg_bcast2u<L>(b[i], q), inv);
         if (ll == k) x[i] = xk;
         if (order >= 0 && order < k) b[i] = cfms(b[i], A[k], xk);
       }
@@ -260,7 +272,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   for (int j = 0; j < M; ++j) {
     double2 aj[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) aj[i] = seg_bcast2<L>(x[i], base + j);
+    for (int i = 0; i < 3; ++i) aj[i] = seg_bcast2u<L>(x[i], L == 64 ? j : base + j);
     if (act) {
       const double2 kk = cconj(KM[j * M + ll]);
       const double2 cc = cconj(CM[j * M + ll]);
