@@ -125,6 +125,27 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double2* __rest
     }
     __syncthreads();
     const double floor_abs = floor_rel * dmax;
+    // would this sweep rotate at all?  A sweep that rotates nothing leaves A
+    // unchanged, so testing every pair once on A as it stands is the same
+    // test; the converged case then costs one barrier instead of a sweep of
+    // rounds (and records no identity rotations)
+    for (int idx = tid; idx < n * n; idx += nt) {
+      const int p = idx / n, q = idx % n;
+      if (q > p) {
+        const double a = A[upos(p, p, n)].x, d = A[upos(q, q, n)].x;
+        const double2 b = A[upos(p, q, n)];
+        const double ab = sqrt(b.x * b.x + b.y * b.y);
+        if (ab > floor_abs && ab > 1e-300 && ab > tol * sqrt(fabs(a * d))) nrot = 1;
+      }
+    }
+    __syncthreads();
+    if (nrot == 0) {  // every thread reads the same value after the barrier
+      converged = true;
+      break;
+    }
+    __syncthreads();  // all have read nrot
+    if (tid == 0) nrot = 0;  // counts the rotations of this sweep again
+    __syncthreads();
     for (int r = 0; r < ne - 1; ++r) {
       if (tid < np) {
         const int t = tid;
@@ -207,8 +228,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(const double2* __rest
   }
   for (int i = tid; i < n; i += nt) lam[i] = A[upos(i, i, n)].x;
   if (tid == 0) {
-    info[0] = converged ? sweep + 1 : -1;
-    info[2] = converged ? sweep + 1 : max_sweeps;  // recorded sweeps
+    info[0] = converged ? sweep : -1;              // sweeps that rotated
+    info[2] = converged ? sweep : max_sweeps;      // recorded sweeps
   }
 }
 
