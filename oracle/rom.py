@@ -13,14 +13,25 @@ Readings of points the paper leaves open (each listed in the design notes):
     s_i = t_i, and o_i^T C o_j + c_ij + s_i^T o_j + s_j^T o_i = w_i^T C w_j;
   * truncation keeps M = #{s_m / s_1 >= TOL}, capped, and never splits a
     cluster of singular values that agree to 1e-8 relative;
-  * the Y^(hp) norm is the energy norm of X = K + eps h I, so the residual dual
-    norm is r^H X^{-1} r and alpha_LB = 1.
+  * Lemma 4.1's norm and stability constant: at frequency omega the residual
+    dual norm is taken in the energy norm of X + s C_sigma (X = K + eps h I),
+    s = s(omega) the largest of a list of reference shifts s_0 = 0 < s_1 < ...
+    that does not exceed omega (one residual Gram per shift, each independent
+    of omega).  For s <= omega the Galerkin error e obeys
+    ||e||^2_(X + omega C) <= 2 ||r||^2_(X + s C)^*, and the tensor errors are
+    bounded by the Lemma's quadratic form with alpha_LB = 2 / (3 + sqrt 10)
+    plus a term linear in the residual norms that vanishes when span(U) is
+    closed under complex conjugation (see certificate_gform).
 """
 from __future__ import annotations
 
 import numpy as np
 
 PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))  # stored order 11 12 13 22 23 33
+
+# Stability constant of Lemma 4.1 in the reference norms: 1 / (3/2 + sqrt(5/2))
+# (derivation in certificate_gform).
+ALPHA_LB = 2.0 / (3.0 + np.sqrt(10.0))
 
 
 # ---------------------------------------------------------------- POD (a1)
@@ -52,6 +63,7 @@ def project(K, c, eps_h, w, U):
     KU = K @ U
     cU = c[:, None] * U
     cw = c[:, None] * w
+    Ub = U.conj()
     return {
         "KM": U.conj().T @ KU,
         "CM": U.conj().T @ cU,
@@ -59,6 +71,10 @@ def project(K, c, eps_h, w, U):
         "g": U.conj().T @ cw,
         "E": w.T @ cw,
         "eps_h": float(eps_h),
+        # U^H X conj(U) and U^H C conj(U): how far span(U) is from being
+        # closed under conjugation (enters the certificate's linear term)
+        "TX": U.conj().T @ (K @ Ub) + float(eps_h) * (U.conj().T @ Ub),
+        "TC": U.conj().T @ (c[:, None] * Ub),
     }
 
 
@@ -138,37 +154,128 @@ def residual_gram_from(Z, XinvZ):
     return 0.5 * (G + G.conj().T)
 
 
-def residual_gram_direct(fo, U, w):
-    """G = Z^H X^{-1} Z with Z = [C w_1, C w_2, C w_3, X U, C U] (SuperLU for X^{-1})."""
-    Z = np.concatenate([fo.c[:, None] * w, fo.X @ U, fo.c[:, None] * U], 1).astype(np.complex128)
-    return residual_gram_from(Z, fo.X_solve(Z))
+def ref_index(s_ref, omega):
+    """Index of the reference shift used at each omega: the largest s_k <= omega
+    (s_ref ascending, s_ref[0] = 0)."""
+    s_ref = np.asarray(s_ref, float)
+    return np.searchsorted(s_ref, np.atleast_1d(np.asarray(omega, float)), side="right") - 1
 
 
-def residual_gram_schur(S, cond_idx, c, w, U, KM, UhU, eps_h):
-    """The same G using only the conductor block S = P^T X^{-1} P.
+def residual_columns(fo, U, w):
+    """Z = [C w_1, C w_2, C w_3, X U, C U]: the reduced solution's residual is
+    r_i - A(omega) U a_i = Z w^(i) with w^(i) = [i omega e_i; -a_i; i omega a_i]."""
+    return np.concatenate([fo.c[:, None] * w, fo.X @ U, fo.c[:, None] * U], 1).astype(np.complex128)
 
-    C w_i and C U vanish off the conductor edges, and X^{-1} (X U) = U, so
-    every block of Z^H X^{-1} Z is a product of S, U and the projected K.
-    """
+
+def residual_gram_direct(fo, U, w, s=0.0):
+    """G_s = Z^H (X + s C)^{-1} Z (Lemma 4.1's Gram in the reference norm of
+    shift s) with a SuperLU factorisation of X + s C."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    Z = residual_columns(fo, U, w)
+    if s == 0.0:
+        return residual_gram_from(Z, fo.X_solve(Z))
+    lu = spla.splu((fo.X + s * sp.diags(fo.c)).tocsc())
+    Y = lu.solve(np.ascontiguousarray(Z.real)) + 1j * lu.solve(np.ascontiguousarray(Z.imag))
+    return residual_gram_from(Z, Y)
+
+
+def residual_gram_spectral(lam, V, dc, cond_idx, w, U, A0, s):
+    """The same G_s from the conductor block alone.
+
+    C_sigma = P Dc P^T is supported on the n_c conductor edges (P selects
+    them, Dc = diag(c)).  With S = P^T X^{-1} P and the eigenpairs
+    Dc^(1/2) S Dc^(1/2) = V diag(lam) V^T, the Sherman-Morrison-Woodbury
+    identity gives Dc^(1/2) P^T (X + s C)^{-1} P Dc^(1/2) = V diag(phi) V^T,
+    phi = lam / (1 + s lam).  With B = V^T Dc^(1/2) [w_c, U_c] (rows of w and
+    U at the conductor edges) and chi = 1 / (1 + s lam), every block of G_s is
+    a weighted Gram of B:
+      [C w, C w]: B_w^H phi B_w     [C w, X U]: B_w^H chi B_U
+      [C w, C U]: B_w^H phi B_U     [X U, X U]: A0 - B_U^H (s chi) B_U
+      [X U, C U]: B_U^H chi B_U     [C U, C U]: B_U^H phi B_U
+    ((X + s C)^{-1} X = I - s (X + s C)^{-1} C on the X U columns).
+    lam, V: eigenpairs above; dc: sqrt(c) on the conductor edges."""
     M = U.shape[1]
-    cc = c[cond_idx]
-    Zc = np.concatenate([cc[:, None] * w[cond_idx], cc[:, None] * U[cond_idx]], 1).astype(np.complex128)
+    lam = np.asarray(lam, float)
+    B = V.T @ (dc[:, None] * np.concatenate([w[cond_idx], U[cond_idx]], 1).astype(np.complex128))
+    Bw, BU = B[:, :3], B[:, 3:]
+    phi = lam / (1.0 + s * lam)
+    chi = 1.0 / (1.0 + s * lam)
+    gram = lambda X, f, Y: X.conj().T @ (f[:, None] * Y)
     G = np.zeros((2 * M + 3, 2 * M + 3), np.complex128)
-    wc = np.r_[0:3, 3 + M:3 + 2 * M]  # positions of the conductor-supported columns
-    xs = np.arange(3, 3 + M)
-    Gc = Zc.conj().T @ (S @ Zc)
-    G[np.ix_(wc, wc)] = 0.5 * (Gc + Gc.conj().T)  # Hermitian by definition
-    ZU = Zc.conj().T @ U[cond_idx]
-    G[np.ix_(wc, xs)] = ZU
-    G[np.ix_(xs, wc)] = ZU.conj().T
-    G[np.ix_(xs, xs)] = KM + eps_h * UhU
-    return G
+    iw, ix, ic = slice(0, 3), slice(3, 3 + M), slice(3 + M, 3 + 2 * M)
+    G[iw, iw] = gram(Bw, phi, Bw)
+    G[iw, ix] = gram(Bw, chi, BU)
+    G[iw, ic] = gram(Bw, phi, BU)
+    G[ix, ix] = A0 - gram(BU, s * chi, BU)
+    G[ix, ic] = gram(BU, chi, BU)
+    G[ic, ic] = gram(BU, phi, BU)
+    G[ix, iw] = G[iw, ix].conj().T
+    G[ic, iw] = G[iw, ic].conj().T
+    G[ic, ix] = G[ix, ic].conj().T
+    return 0.5 * (G + G.conj().T)  # Hermitian by definition
 
 
-def certificate_gform(G, a, omega, alpha, alpha_lb=1.0):
-    """Delta_ij (Lemma 4.1) with ||r_i||^2 = w^(i)H G w^(i) and the cross term
-    -2 Re w^(i)H G w^(j);  w^(i) = [i w e_i ; -a_i ; i w a_i] so that the
-    residual of the reduced solution is Z w^(i).  Returns (n_omega, 3, 3)."""
+def conj_defect_matrix(rom, s):
+    """D'_s = D_s / 2 + 4 eps h U^H U with D_s the Hermitian form of the
+    conjugation defect: for q = U a,
+        a^H D_s a = min over v in span(U) of ||conj(q) - v||^2_(X + s C),
+    i.e. ||conj q||^2 - ||Pi conj q||^2 with Pi the (X + s C)-orthogonal
+    projector onto span(U):  D_s = A_s - conj(T_s^H A_s^{-1} T_s),
+    A_s = U^H (X + s C) U, T_s = U^H (X + s C) conj(U).  a^H D'_s a bounds
+    (d/2 + sqrt(2 eps h) |q|)^2 / 2 from above (see certificate_gform)."""
+    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    As = A0 + s * rom["CM"]
+    Ts = rom["TX"] + s * rom["TC"]
+    Q = Ts.conj().T @ np.linalg.solve(As, Ts)
+    D = As - Q.conj()
+    Dp = 0.5 * D + 4.0 * rom["eps_h"] * rom["UhU"]
+    return 0.5 * (Dp + Dp.conj().T)
+
+
+def _delta(n2, cross, e, alpha, alpha_lb):
+    """Delta_ij from n_i^2 = ||r_i||^2, cross_ij = Re <r_i, r_j> and e_i (the
+    conjugation-defect weights); arrays (..., 3) and (..., 3, 3)."""
+    a3 = alpha ** 3
+    n = np.sqrt(np.maximum(n2, 0.0))
+    diff = n2[..., :, None] + n2[..., None, :] - 2.0 * cross
+    quad = a3 / (8.0 * alpha_lb) * (n2[..., :, None] + n2[..., None, :] + diff)
+    lin = 0.25 * a3 * (n[..., :, None] * e[..., None, :] + n[..., None, :] * e[..., :, None])
+    return quad + lin
+
+
+def certificate_gform(Gs, Dps, s_ref, a, omega, alpha, alpha_lb=ALPHA_LB):
+    """Delta_ij (Lemma 4.1) from the residual Grams, one per reference shift.
+
+    At omega the shift s = s_k <= omega of ref_index is used:
+      n_i^2 = w^(i)H G_s w^(i),  ||r_i - r_j||^2 = n_i^2 + n_j^2 - 2 Re w^(i)H G_s w^(j),
+      w^(i) = [i omega e_i ; -a_i ; i omega a_i]  (residual Z w^(i)),
+      e_i = (a_i^H D'_s a_i)^(1/2)  (conj_defect_matrix),
+      Delta_ij = a^3/(8 alpha_LB) (n_i^2 + n_j^2 + ||r_i - r_j||^2)
+                 + a^3/4 (n_i e_j + n_j e_i).
+    Why this bounds |R~ - R~^PODP|_ij and |I - I^PODP|_ij.  Let e_i = q_i - U a_i
+    (full-order minus reduced), r_i its residual A e_i, l_j(v) = w_j^T C v.
+    The energy identities q_i^H A q_j = q_i^H r_j and q_j^H A q_i = q_j^H r_i
+    hold for the full-order solution and, by Galerkin orthogonality, for the
+    reduced one; they turn the Hermitian forms into
+      Re q_i^H X q_j = omega/2 Im(l_j(q_i) + l_i(q_j)),
+      I_ij = omega a^3/4 (E_ij + Re(l_j(q_i) + l_i(q_j)) / 2),
+    and R_ij = -a^3/4 (Re q_i^H X q_j - eps h Re q_i^H q_j).  Since A is
+    complex symmetric and A q_j = i omega C w_j,
+      i omega l_j(e_i) = q_j^T A e_i = (U a_j)^T A e_i + e_j^T A e_i.
+    The second term is bounded by ||e_i|| ||e_j|| in the norm of X + omega C,
+    and ||e||^2 <= 2 n^2 there for s <= omega (|e^H r| <= ||e||_s n and
+    e^H r = ||e||^2_X - i omega ||e||^2_C).  Maximising over what these
+    constraints allow gives |quadratic part| <= kappa a^3/4 n_i n_j with
+    kappa = 3/2 + sqrt(5/2) for R (the eps h term included) and 2 for I, so
+    alpha_LB = 1/kappa.  The first term is not quadratic: Galerkin
+    orthogonality removes only the part of conj(U a_j) inside span(U), leaving
+    |(U a_j)^T A e_i| <= d_j n_i with d_j the distance (in the s-norm) from
+    conj(U a_j) to span(U); with the eps h cross terms of R
+    (<= sqrt(2 eps h) |U a_j| n_i) the linear part is at most
+    a^3/4 (n_i e_j + n_j e_i), e_j >= d_j/2 + sqrt(2 eps h) |U a_j|.
+    Gs, Dps: lists (one per shift) of (2M+3)^2 and M x M matrices.
+    Returns (n_omega, 3, 3)."""
     omega = np.atleast_1d(np.asarray(omega, float))
     nw, M, _ = a.shape
     W = np.zeros((nw, 2 * M + 3, 3), np.complex128)
@@ -176,26 +283,46 @@ def certificate_gform(G, a, omega, alpha, alpha_lb=1.0):
         W[:, i, i] = 1j * omega
     W[:, 3:3 + M, :] = -a
     W[:, 3 + M:, :] = 1j * omega[:, None, None] * a
-    Cm = np.conj(np.swapaxes(W, 1, 2)) @ G @ W  # (nw, 3, 3): c_ij
-    n2 = np.real(np.diagonal(Cm, axis1=1, axis2=2))
-    diff = n2[:, :, None] + n2[:, None, :] - 2.0 * np.real(Cm)
-    return alpha ** 3 / (8.0 * alpha_lb) * (n2[:, :, None] + n2[:, None, :] + diff)
+    ks = ref_index(s_ref, omega)
+    out = np.empty((nw, 3, 3))
+    for k in range(nw):
+        Cm = W[k].conj().T @ Gs[ks[k]] @ W[k]  # c_ij
+        n2 = np.real(np.diag(Cm))
+        e = np.sqrt(np.maximum(np.real(np.einsum("mi,mn,ni->i", a[k].conj(), Dps[ks[k]], a[k])), 0.0))
+        out[k] = _delta(n2, np.real(Cm), e, alpha, alpha_lb)
+    return out
 
 
-def certificate_direct(fo, U, a, omega, w, alpha_lb=1.0):
-    """Delta_ij from full-order residuals res_i = r_i - A(omega) U a_i and X^{-1}."""
+def certificate_direct(fo, U, a, omega, w, s_ref, alpha_lb=ALPHA_LB):
+    """The same Delta_ij from full-order quantities: residuals
+    res_i = r_i - A(omega) U a_i, dual norms with (X + s C)^{-1} by SuperLU, and
+    the conjugation defect d_j = ||conj(q_j) - Pi conj(q_j)||_(X + s C)
+    computed as the norm of the full-order difference.  e_j =
+    (d_j^2 / 2 + 4 eps h |q_j|^2)^(1/2) as in conj_defect_matrix."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
     omega = np.atleast_1d(np.asarray(omega, float))
+    ks = ref_index(s_ref, omega)
     out = np.empty((omega.size, 3, 3))
-    a3 = fo.alpha ** 3
+    lus = {}
     for k in range(omega.size):
-        res = fo.rhs(omega[k], w) - fo.A(omega[k]) @ (U @ a[k])
-        Xr = fo.X_solve(res)
-        n2 = np.real(np.einsum("ni,ni->i", res.conj(), Xr))
-        for i in range(3):
-            for j in range(3):
-                d = res[:, i] - res[:, j]
-                dn = np.real(np.vdot(d, fo.X_solve(d)))
-                out[k, i, j] = a3 / (8.0 * alpha_lb) * (n2[i] + n2[j] + dn)
+        s = float(np.asarray(s_ref)[ks[k]])
+        Xs = (fo.X + s * sp.diags(fo.c)).tocsc()
+        if s not in lus:
+            lus[s] = spla.splu(Xs)
+        lu = lus[s]
+        solve = lambda B: lu.solve(np.ascontiguousarray(B.real)) + 1j * lu.solve(np.ascontiguousarray(B.imag))
+        q = U @ a[k]
+        res = fo.rhs(omega[k], w) - fo.A(omega[k]) @ q
+        Yr = solve(res)
+        G = res.conj().T @ Yr
+        n2 = np.real(np.diag(G))
+        cb = q.conj()
+        c = np.linalg.solve(U.conj().T @ (Xs @ U), U.conj().T @ (Xs @ cb))
+        dv = cb - U @ c
+        d2 = np.real(np.einsum("ni,ni->i", dv.conj(), Xs @ dv))
+        e = np.sqrt(0.5 * d2 + 4.0 * fo.eps_h * np.real(np.einsum("ni,ni->i", q.conj(), q)))
+        out[k] = _delta(n2, np.real(G), e, fo.alpha, alpha_lb)
     return out
 
 
@@ -204,11 +331,18 @@ def pack(T):
     return np.stack([T[:, i, j] for i, j in PAIRS], 1)
 
 
-def sweep(rom, omega, G, alpha, alpha_lb=1.0):
-    """Reduced solves plus matrix-method tensors and certificates: (n_omega, 18)."""
+def certificate_data(rom, s_ref, gram):
+    """Per-shift inputs of certificate_gform: gram(s) -> G_s for each s."""
+    return {"s_ref": np.asarray(s_ref, float), "G": [gram(s) for s in s_ref],
+            "Dp": [conj_defect_matrix(rom, s) for s in s_ref]}
+
+
+def sweep(rom, omega, cert, alpha, alpha_lb=ALPHA_LB):
+    """Reduced solves plus matrix-method tensors and certificates: (n_omega, 18).
+    cert: certificate_data(...)."""
     a = reduced_solve(rom, omega)
     Rt, I = tensors_mm(rom, a, omega, rom["N0"], alpha)
-    Dl = certificate_gform(G, a, omega, alpha, alpha_lb)
+    Dl = certificate_gform(cert["G"], cert["Dp"], cert["s_ref"], a, omega, alpha, alpha_lb)
     return np.concatenate([pack(Rt), pack(I), pack(Dl)], 1), a
 
 
