@@ -46,6 +46,24 @@ FP64_VALU_PEAK_TF = 78.6
 FP64_MFMA_PEAK_TF = 78.6
 
 
+
+def cert_inputs(p, T):
+    """Certificate inputs of mpt_project for a problem: the conductor block's
+    eigenvectors (rows) and eigenvalues, and the reference shifts."""
+    lam, Vt = p.cond_spectrum()
+    return T(Vt, torch.float64), T(lam, torch.float64), T(p.s_ref, torch.float64)
+
+
+def oracle_cert(p, fo, U, rom):
+    """The oracle's certificate data for a problem (the same conductor-block
+    eigenpairs as the GPU path)."""
+    from oracle import rom as R
+    lam, Vt = p.cond_spectrum()
+    A0 = rom["KM"] + fo.eps_h * rom["UhU"]
+    dc = np.sqrt(fo.c[p.ops.cond_idx])
+    return R.certificate_data(rom, p.s_ref, lambda s: R.residual_gram_spectral(
+        lam, Vt.T, dc, p.ops.cond_idx, p.w, U, A0, s))
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -163,7 +181,7 @@ def main():
     o = T(p.o, torch.float64) if np.any(p.o) else None
     vol = T(ops.vol, torch.float64)
     cond = T(ops.cond_idx, torch.int32)
-    S = T(p.S, torch.float64)
+    S = cert_inputs(p, T)
     omega = T(p.omega, torch.float64)
     snap = T(np.sort(p.snap_omega), torch.float64)
     tol, cap = p.wl.tol_sigma, p.wl.m_cap
@@ -179,7 +197,7 @@ def main():
         e[0].record()
         U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
         e[1].record()
-        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, S)
+        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, *S)
         e[2].record()
         if pencil:
             pen = mpt.mpt_pencil_reduce(rom)
@@ -323,7 +341,7 @@ def build_dictionary(name, n_obj, dev, keep=2, tol_snap=1e-6):
         rom = mpt.mpt_project(mpt.Csr.from_scipy(ops.K, dev, row_blocks=3), T(ops.c, torch.float64), ops.eps_h,
                               T(p.w, torch.float64), T(p.o, torch.float64) if np.any(p.o) else None,
                               T(ops.vol, torch.float64), ops.alpha, U, T(ops.cond_idx, torch.int32),
-                              T(p.S, torch.float64))
+                              *cert_inputs(p, T))
         roms.append(rom)
         omegas.append(T(p.omega, torch.float64))
         sigmas.append(p.draw.shape.materials[0][0])
@@ -507,7 +525,7 @@ def bench_fmm(args):
     omega = T(p.omega[:: p.omega.size // n_fmm][:n_fmm], torch.float64)
     U, sig, M = mpt.mpt_pod_basis(T(p.D, torch.complex128), p.wl.tol_sigma, p.wl.m_cap)
     rom = mpt.mpt_project(K, c, ops.eps_h, w, o, T(ops.vol, torch.float64), ops.alpha, U, cond,
-                          T(p.S, torch.float64))
+                          *cert_inputs(p, T))
     out_mm, st, a = mpt.mpt_sweep(rom, omega, want_a=True)
     torch.cuda.synchronize()
     assert int(st.abs().max()) == 0
@@ -594,7 +612,7 @@ def cpu_baseline_dictionary(kept, form, budget_s):
         U, s, M = R.pod_basis(p.D, 0.0, p.M_cap)
         rom = R.project(fo.K, fo.c, fo.eps_h, p.w, U)
         rom["N0"] = R.static_tensor_mesh(fo, p.o)
-        G = R.residual_gram_schur(p.S, ops.cond_idx, fo.c, p.w, U, rom["KM"], rom["UhU"], fo.eps_h)
+        G = oracle_cert(p, fo, U, rom)
         t += time.perf_counter() - t0
         om = p.omega[: max(1, int(len(p.omega) * min(1.0, budget_s / 20.0)))]
         t0 = time.perf_counter()
@@ -639,7 +657,7 @@ def bench_adaptive(args):
     o = T(p.o, torch.float64) if np.any(p.o) else None
     vol = T(ops.vol, torch.float64)
     cond = T(ops.cond_idx, torch.int32)
-    S = T(p.S, torch.float64)
+    S = cert_inputs(p, T)
     omega = T(p.omega, torch.float64)
     tol, cap, nstar = p.wl.tol_sigma, p.wl.m_cap, p.wl.n_star
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -649,7 +667,7 @@ def bench_adaptive(args):
         e[0].record()
         U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
         e[1].record()
-        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, S)
+        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, *S)
         e[2].record()
         if (form or args.sweep) == "pencil":
             out, st = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(rom), omega)
@@ -761,8 +779,7 @@ def cpu_baseline(p, budget_s):
         U, s, M = R.pod_basis(p.D, p.wl.tol_sigma, p.wl.m_cap)
         rom = R.project(fo.K, fo.c, fo.eps_h, p.w, U)
         rom["N0"] = R.static_tensor_mesh(fo, p.o)
-        G = R.residual_gram_schur(p.S, ops.cond_idx, fo.c, p.w, U, rom["KM"], rom["UhU"],
-                                  fo.eps_h)
+        G = oracle_cert(p, fo, U, rom)
         return rom, G
 
     def sweep_select(rom, G, om):

@@ -79,24 +79,31 @@ typedef struct {
  *   A0  M x M     K_M + eps h U^H U                  (A^M at w = 0)
  *   CM  M x M     C_M = U^H C_sigma U                (eq. (podpimagmpt))
  *   g   3 x M     row i = U^H C_sigma w_i, w_i = x_i + o_i (source, r = i w g)
- *   G   (2M+3)^2  residual Gram Z^H X^{-1} Z with
+ *   G   n_ref x (2M+3)^2   residual Grams G_s = Z^H (X + s C_sigma)^{-1} Z,
+ *                 one per reference shift s = s_ref[k], with
  *                 Z = [C_sigma w_1..3 | X U | C_sigma U]     (Lemma 4.1)
+ *   Dp  n_ref x M x M      conjugation-defect forms D'_s (mpt_project)
+ *   s_ref n_ref   reference shifts, ascending, s_ref[0] = 0
  *   E   3 x 3     w_i^T C_sigma w_j                   (the omega-independent
  *                 I terms of (I_tensor_coeffs) under Remark 3.1)
  *   N0  3 x 3     static tensor (eq. (NRI), first line)
- * alpha is the object size (m); alpha_lb the stability bound of Lemma 4.1.
- * KM, A0, CM and G are Hermitian by definition and must be stored Hermitian:
- * the sweep reads row r of these matrices as the conjugate of column r (one
- * coalesced load per column).  mpt_project stores them exactly Hermitian.
+ * alpha is the object size (m); alpha_lb the stability constant of Lemma 4.1
+ * (2 / (3 + sqrt 10) for these reference norms).  At frequency w the
+ * certificate uses the largest s_ref[k] <= w.  KM, A0, CM, G and Dp are
+ * Hermitian by definition and must be stored Hermitian: the sweep reads row r
+ * of these matrices as the conjugate of column r (one coalesced load per
+ * column).  mpt_project stores them exactly Hermitian.  1 <= n_ref <= 64.
  */
 typedef struct {
   int32_t M;
-  int32_t pad_;
+  int32_t n_ref;
   const double* KM;
   const double* A0;
   const double* CM;
   const double* g;
   const double* G;
+  const double* Dp;
+  const double* s_ref;
   const double* E;
   const double* N0;
   double alpha;
@@ -130,34 +137,46 @@ mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N, 
  * w: N x 3 real (x_i + o_i).  o: N x 3 real theta~^(0) DOFs or NULL (mu_r=1).
  * vol: 3 values h^3 sum_{faces normal to e_i} (1 - 1/mu_f).
  * U: N x M complex basis (ldU).
- * Conductor data for the certificate: cond (n_c sorted edge indices with
- * c > 0) and S (n_c x n_c real, row-major) = P^T X^{-1} P, the conductor
- * block of the inverse of X = K + eps h I.
- * Outputs (device, row-major): KM, A0, CM (M x M), g (3 x M), G
- * ((2M+3)^2), E (3x3), N0 (3x3; alpha^3 vol_i delta_ij + alpha^3/4 o^T K o).
- * Y (N x M complex) receives K U when non-NULL (else it lives in ws).
+ * Conductor data for the certificate (Lemma 4.1): cond (n_c sorted edge
+ * indices with c > 0) and the eigen-decomposition of the conductor block of
+ * X^{-1}, X = K + eps h I, scaled by the conductivities:
+ *   Dc^(1/2) P^T X^{-1} P Dc^(1/2) = Vt^T diag(lam) Vt,   Dc = diag(c[cond]),
+ * Vt (n_c x n_c, row-major, row k = eigenvector k), lam (n_c).  With it the
+ * residual Gram in the norm of X + s C_sigma needs no solve:
+ * Dc^(1/2) P^T (X + s C)^{-1} P Dc^(1/2) = Vt^T diag(lam / (1 + s lam)) Vt
+ * (Sherman-Morrison-Woodbury).  s_ref (n_ref, device, ascending, s_ref[0] =
+ * 0) lists the reference shifts.
+ * Outputs (device, row-major): KM, A0, CM (M x M), g (3 x M),
+ * G (n_ref x (2M+3)^2; G_s with Z = [C w | X U | C U]), Dp (n_ref x M x M;
+ *   D'_s = D_s / 2 + 4 eps h U^H U, where a^H D_s a is the squared distance
+ *   in the norm of X + s C from conj(U a) to span(U):
+ *   D_s = A_s - conj(T_s^H A_s^{-1} T_s), A_s = U^H (X + s C) U,
+ *   T_s = U^H (X + s C) conj(U)), E (3x3), N0 (3x3; alpha^3 vol_i delta_ij +
+ * alpha^3/4 o^T K o).  Y (N x M complex) receives K U when non-NULL (else it
+ * lives in ws).  1 <= M <= 96, 1 <= n_ref <= 64.
  */
-size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c);
+size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c, int n_ref);
 mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
                        const double* w, const double* o, const double* vol, double alpha,
                        const double* U, int64_t ldU, int M,
-                       const int32_t* cond, int64_t n_c, const double* S,
-                       double* KM, double* A0, double* CM, double* g, double* G,
+                       const int32_t* cond, int64_t n_c, const double* Vt, const double* lam,
+                       int n_ref, const double* s_ref,
+                       double* KM, double* A0, double* CM, double* g, double* G, double* Dp,
                        double* E, double* N0, double* Y, void* ws, size_t ws_bytes);
 
-/* Residual Gram of Lemma 4.1 from columns prepared by the caller:
- *   G = (P + P^H) / 2,  P = Z^H Y over the N rows,
+/* Residual Gram of Lemma 4.1 for one reference shift s from columns prepared
+ * by the caller:
+ *   G_s = (P + P^H) / 2,  P = Z^H Y over the N rows,
  * where Z (N x (2M+3), ldZ) = [C_sigma w_1..3 | X U | C_sigma U] holds the
- * affine residual's columns (the unknowns ordered as in mpt_project's G) and
- * Y (N x (2M+3), ldY) = X^{-1} Z comes from the caller's full-order solver,
- * as in the paper's offline stage.  mpt_project builds the same matrix from
- * the conductor block S = P^T X^{-1} P instead, with no solve per basis
- * vector.  Either way w^H G w cancels terms that grow like omega^2 / (eps h),
- * so certificates of an accurate reduced model have a rounding floor that
- * depends on how X^{-1} Z was computed.  Output G: (2M+3)^2 complex,
- * row-major, exactly Hermitian; it may replace the G of a reduced model.
- * 1 <= M <= 96.  Workspace: mpt_residual_gram_ws_size.  Asynchronous on the
- * handle's stream. */
+ * affine residual's columns (ordered as in mpt_project's G) and
+ * Y (N x (2M+3), ldY) = (X + s C_sigma)^{-1} Z comes from the caller's
+ * full-order solver, as in the paper's offline stage.  mpt_project builds the
+ * same matrices from the conductor block instead, with no solve per basis
+ * vector.  The certificate w^H G_s w is a difference of terms larger than
+ * itself, so its rounding floor depends on how Y was computed.  Output G:
+ * (2M+3)^2 complex, row-major, exactly Hermitian; it may replace slot k of a
+ * reduced model's G when s = s_ref[k].  1 <= M <= 96.  Workspace:
+ * mpt_residual_gram_ws_size.  Asynchronous on the handle's stream. */
 size_t mpt_residual_gram_ws_size(int64_t N, int M);
 mpt_status mpt_residual_gram(mpt_handle h, const double* Z, int64_t ldZ, const double* XinvZ,
                              int64_t ldY, int64_t N, int M, double* G, void* ws,
@@ -170,12 +189,20 @@ mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU
 
 /* ----------------------------------------------------------------------
  * a3+a4  Online sweep (eq. (ReducedA) per frequency; eqs. (podprealmpt),
- *     (podpimagmpt); Lemma 4.1 with ||r_i||^2 = w^(i)H G w^(i)).
+ *     (podpimagmpt); Lemma 4.1).
  * For each omega[k]: LU with partial pivoting of A0 - i w CM, the three
  * solves a_i for r_i = i w g_i, then out[k*18 + p]:
  *   p = 0..5   R~ (11,12,13,22,23,33)
  *   p = 6..11  I  (same order)
- *   p = 12..17 Delta (same order), w^(i) = [i w e_i ; -a_i ; i w a_i].
+ *   p = 12..17 Delta (same order):
+ *     Delta_ij = a^3/(8 alpha_lb) (n_i^2 + n_j^2 + ||r_i - r_j||^2)
+ *                + a^3/4 (n_i e_j + n_j e_i),
+ *     n_i^2 = w^(i)H G_s w^(i), ||r_i - r_j||^2 = n_i^2 + n_j^2
+ *     - 2 Re w^(i)H G_s w^(j), w^(i) = [i w e_i ; -a_i ; i w a_i],
+ *     e_i = (max(0, a_i^H D'_s a_i))^(1/2), s = the largest s_ref <= w.
+ *   Delta bounds |R~ - R~^PODP|_ij and |I - I^PODP|_ij (the second term
+ *   covers the part of the error that Galerkin orthogonality leaves linear in
+ *   the residual when span(U) is not closed under conjugation).
  * a_out (n_omega x 3 x M complex) receives a_i when non-NULL.
  * status[k] (device) = 0, or MPT_E_SINGULAR when a pivot was zero or
  * non-finite.  The call does not synchronise: it returns MPT_OK once the work
@@ -190,27 +217,33 @@ mpt_status mpt_sweep(mpt_handle h, const mpt_rom* rom, const double* omega, int6
 /* ----------------------------------------------------------------------
  * a5  Snapshot selection (Algorithm 1 selection step).
  * omega (n, ascending), out (n x 18 from mpt_sweep; the Delta columns are
- * used), snap (n_snap ascending).  Intervals [snap_j, snap_{j+1}), the last
- * one closed; Lambda_j = max Delta over the interval; the n_star intervals
+ * used), snap (n_snap ascending).  Intervals snap_j < w < snap_{j+1}
+ * (Algorithm 1's snap_j <= w < snap_{j+1} without its left end, a snapshot
+ * already: no frequency of the snapshot set is returned again);
+ * Lambda_j = max Delta over the interval; the n_star intervals
  * with the largest Lambda_j (ties: lower j) each give one new frequency at
  * their argmax (ties: smaller omega).  Device outputs: new_omega (n_star,
  * rank order; NaN when fewer intervals hold frequencies), lambda (n_snap-1;
- * -inf for empty intervals), Lambda_max (1).
+ * -inf for empty intervals), Lambda_max (1).  ws: device workspace of
+ * mpt_select_snapshots_ws_size(n_snap) bytes (per-interval argmax).
  */
+size_t mpt_select_snapshots_ws_size(int n_snap);
 mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n, const double* out,
                                 const double* snap, int n_snap, int n_star,
-                                double* new_omega, double* lambda, double* Lambda_max);
+                                double* new_omega, double* lambda, double* Lambda_max, void* ws,
+                                size_t ws_bytes);
 
 /* Threshold variant of the selection (the alternative to a fixed N_* that
- * §4.3 names, after Hesthaven et al.): every interval whose maximum reaches
+ * Section 4.4 names, after Hesthaven et al.): every interval whose maximum reaches
  * theta * Lambda (0 < theta <= 1) gives its argmax, at most one per interval,
  * in the rank order of mpt_select_snapshots.  new_omega (n_snap - 1, device;
  * NaN after the last chosen), n_new (1 int32, device) the number chosen;
- * lambda and Lambda_max as in mpt_select_snapshots. */
+ * lambda, Lambda_max and ws as in mpt_select_snapshots. */
 mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double* omega, int64_t n,
                                           const double* out, const double* snap, int n_snap,
                                           double theta, double* new_omega, int32_t* n_new,
-                                          double* lambda, double* Lambda_max);
+                                          double* lambda, double* Lambda_max, void* ws,
+                                          size_t ws_bytes);
 
 /* ----------------------------------------------------------------------
  * a6  Batched dictionary sweep: one persistent launch (captured in a HIP
@@ -219,7 +252,11 @@ mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double* omega, int
  * (n_obj + 1, host) indexes omega / out / status: object o owns rows
  * omega_off[o] .. omega_off[o+1]-1.  Results equal mpt_sweep object by
  * object.  tune: NULL for the tuned defaults.  Every object needs M <= 64
- * (MPT_E_UNSUPPORTED otherwise).
+ * (MPT_E_UNSUPPORTED otherwise).  ws: device workspace of
+ * mpt_sweep_batched_ws_size bytes that holds the work-item plan; the graph of
+ * the last call is reused while every argument (ws included) stays the same,
+ * and a call that rewrites the plan drops it.  Uploading a new plan
+ * synchronises the stream.
  */
 typedef struct {
   int32_t omegas_per_item;   /* frequencies per work item (>= 1) */
@@ -228,10 +265,12 @@ typedef struct {
   int32_t reserved;
 } mpt_tuning;
 
+size_t mpt_sweep_batched_ws_size(const mpt_rom* roms_host, int n_obj, const int64_t* omega_off,
+                                 const mpt_tuning* tune);
 mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host, const mpt_rom* roms_dev,
                              int n_obj, const int64_t* omega_off, const double* omega,
                              double* out, int32_t* status, const mpt_tuning* tune,
-                             int use_graph);
+                             int use_graph, void* ws, size_t ws_bytes);
 
 /* ----------------------------------------------------------------------
  * a7  Adjoint of the sweep (differentiated signature).
@@ -242,11 +281,26 @@ mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host, const mpt_r
  * sig_dsig = sigma_* dL/dsigma_* (one value) for a single conductivity
  * that scales C_sigma, g and E with the basis frozen.
  * Same sizes and rom rules as mpt_sweep, with M <= 64 (MPT_E_UNSUPPORTED
- * otherwise).
+ * otherwise).  No workspace; asynchronous (sig_dsig is a device pointer).
  */
 mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n,
                              const double* dout, double* dL_domega, double* sig_dsig,
                              int32_t* status);
+
+/* The differentiable signature of one object at conductivity sigma (device
+ * pointer, 1 value) when its reduced model was projected at sigma0: the
+ * model depends on w sigma only (C_sigma, g, E proportional to sigma, basis
+ * frozen), so
+ *   mpt_signature: the outputs of mpt_sweep at w sigma / sigma0;
+ *   mpt_signature_adjoint: dL/dw_k at the given w_k (chain rule included)
+ *     and dL/dsigma = sum_k w_k dL/dw_k / sigma (one device value), from
+ *     upstream gradients dout (n x 18, the Delta columns ignored).
+ * M <= 64.  No workspace; asynchronous. */
+mpt_status mpt_signature(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n,
+                         const double* sigma, double sigma0, double* out, int32_t* status);
+mpt_status mpt_signature_adjoint(mpt_handle h, const mpt_rom* rom, const double* omega, int64_t n,
+                                 const double* sigma, double sigma0, const double* dout,
+                                 double* dL_domega, double* dL_dsigma, int32_t* status);
 
 /* Per-material sigma sensitivities of an object with two conducting
  * materials (C_sigma = C_1 + C_2, C_m proportional to sigma_m on material
@@ -260,19 +314,22 @@ mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const double* ome
  * and sigma_2 dL/dsigma_2 = sum_k w_k dL/dw_k - sigma_1 dL/dsigma_1 (the
  * reduced model depends on sigma w only).  Outputs: dL_domega (n) as in
  * mpt_sweep_adjoint, sig_dsig (2 device doubles: material 1, material 2),
- * status.  M <= 64 (MPT_E_UNSUPPORTED otherwise).  Asynchronous. */
+ * status.  M <= 64 (MPT_E_UNSUPPORTED otherwise).  ws: device workspace of
+ * mpt_sweep_adjoint_materials_ws_size(n) bytes.  Asynchronous. */
+size_t mpt_sweep_adjoint_materials_ws_size(int64_t n);
 mpt_status mpt_sweep_adjoint_materials(mpt_handle h, const mpt_rom* rom, const double* CM1,
                                        const double* g1, const double* E1, const double* omega,
                                        int64_t n, const double* dout, double* dL_domega,
-                                       double* sig_dsig, int32_t* status);
+                                       double* sig_dsig, int32_t* status, void* ws,
+                                       size_t ws_bytes);
 
-/* Batched adjoint over a dictionary (same layout as mpt_sweep_batched);
- * sig_dsig has one value per object. */
+/* Batched adjoint over a dictionary (same layout and workspace as
+ * mpt_sweep_batched, with tune = NULL); sig_dsig has one value per object. */
 mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
                                      const mpt_rom* roms_dev, int n_obj,
                                      const int64_t* omega_off, const double* omega,
                                      const double* dout, double* dL_domega, double* sig_dsig,
-                                     int32_t* status);
+                                     int32_t* status, void* ws, size_t ws_bytes);
 
 /* ----------------------------------------------------------------------
  * Pencil form of the sweep: the shifted-system method of Laub (IEEE TAC
@@ -281,9 +338,10 @@ mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
  *   Q^H A0 Z = H (upper Hessenberg),  Q^H C_M Z = T (upper triangular)
  * (Householder QR of C_M, then Givens rotations from both sides), f_i =
  * Q^H g_i, and the quadratic-form matrices of eqs. (podprealmpt),
- * (podpimagmpt) and Lemma 4.1 transformed by Z.  buf (device, >=
- * mpt_pencil_bytes(M) bytes, owned by the caller and kept alive while the
- * pencil is used) receives all of it; *out (host struct) receives device
+ * (podpimagmpt) and Lemma 4.1 (one set per reference shift) in MFMA
+ * fragment order.  buf (device, >= mpt_pencil_bytes(M, rom->n_ref) bytes,
+ * owned by the caller and kept alive while the pencil is used) receives all
+ * of it; *out (host struct) receives device
  * pointers into buf.  The rom matrices are only read and may be freed after
  * the stream has passed the call.  1 <= M <= 96 (above 64 the reduction
  * keeps its working copy of A in buf and the sweep holds two rows per lane).
@@ -296,18 +354,18 @@ mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
  */
 typedef struct {
   int32_t M;
-  int32_t pad_;
+  int32_t n_ref;     /* reference shifts of the certificate */
   const double* H;   /* M x M complex, column-major */
   const double* T;   /* M x M complex, column-major */
   const double* f;   /* 3 x M complex */
   const double* Z;   /* M x M complex, row-major */
-  const double* W;   /* stacked transformed matrices, MFMA fragment order */
-  const double* S;   /* 27 doubles: Re G_ee (3 x 3), E, N0 */
+  const double* W;   /* stacked matrices, MFMA fragment order */
+  const double* S;   /* E (3 x 3), N0, then per shift: s, Re G_s[w, w] (3 x 3) */
   double alpha;
   double alpha_lb;
 } mpt_pencil;
 
-size_t mpt_pencil_bytes(int M);
+size_t mpt_pencil_bytes(int M, int n_ref);
 mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf, size_t bytes,
                              mpt_pencil* out);
 mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* omega,
@@ -319,11 +377,11 @@ mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* o
  * roms_host: n_obj host structs (device pointers), 1 <= M <= 96 each;
  * omega_off (n_obj + 1, host, omega_off[0] = 0) indexes omega / out / status
  * as in mpt_sweep_batched; buf (device, >= mpt_pencil_batched_bytes) holds
- * the objects' pencils, packed in order.  The work-item plan is uploaded once
- * and reused while the arguments stay the same (the call synchronises the
- * stream when it uploads a new plan).  Results equal mpt_sweep_pencil object
- * by object. */
-size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj);
+ * the objects' pencils, packed in order, and the work-item plan.  The plan is
+ * uploaded once and reused while the arguments stay the same (the call
+ * synchronises the stream when it uploads a new plan).  Results equal
+ * mpt_sweep_pencil object by object. */
+size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj, const int64_t* omega_off);
 mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms_host, int n_obj,
                                     const int64_t* omega_off, const double* omega, void* buf,
                                     size_t bytes, double* out, int32_t* status);

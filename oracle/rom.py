@@ -93,10 +93,15 @@ def static_tensor_mesh(fo, o):
 
 
 # --------------------------------------------------------------- sweep (a3)
+def a0_of(rom):
+    """A^M at w = 0: K_M + eps h U^H U (or the matrix supplied as rom["A0"])."""
+    return rom["A0"] if "A0" in rom else rom["KM"] + rom["eps_h"] * rom["UhU"]
+
+
 def reduced_solve(rom, omega):
     """a_i(omega) from (K_M + eps h U^H U - i omega C_M) a_i = i omega g_i."""
     omega = np.atleast_1d(np.asarray(omega, float))
-    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    A0 = a0_of(rom)
     A = A0[None] - 1j * omega[:, None, None] * rom["CM"][None]
     r = 1j * omega[:, None, None] * rom["g"][None]
     return np.linalg.solve(A, r)  # (n_omega, M, 3)
@@ -224,7 +229,7 @@ def conj_defect_matrix(rom, s):
     projector onto span(U):  D_s = A_s - conj(T_s^H A_s^{-1} T_s),
     A_s = U^H (X + s C) U, T_s = U^H (X + s C) conj(U).  a^H D'_s a bounds
     (d/2 + sqrt(2 eps h) |q|)^2 / 2 from above (see certificate_gform)."""
-    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    A0 = a0_of(rom)
     As = A0 + s * rom["CM"]
     Ts = rom["TX"] + s * rom["TC"]
     Q = Ts.conj().T @ np.linalg.solve(As, Ts)
@@ -350,11 +355,13 @@ def sweep(rom, omega, cert, alpha, alpha_lb=ALPHA_LB):
 def select_snapshots(omega, delta, snap_omega, n_star):
     """Algorithm 1 selection step.
 
-    Intervals [w_n, w_{n+1}) between consecutive sorted snapshot frequencies
-    (the last one closed); Lambda_n = max over omega in the interval and over
-    (i, j) of Delta_ij; Lambda = max_n Lambda_n; the N_* intervals with the
-    largest Lambda_n (ties: lower n) each contribute one new snapshot at the
-    omega attaining Lambda_n (ties: smaller omega).
+    Intervals w_n <= w < w_{n+1} between consecutive sorted snapshot
+    frequencies, as in Algorithm 1, without their left end: w_n is a snapshot
+    already, and a new snapshot there would repeat a column of D.  So
+    Lambda_n = max over w_n < w < w_{n+1} and over (i, j) of Delta_ij;
+    Lambda = max_n Lambda_n; the N_* intervals with the largest Lambda_n
+    (ties: lower n) each contribute one new snapshot at the omega attaining
+    Lambda_n (ties: smaller omega).
     Returns (new omegas in rank order, Lambda, Lambda_n per interval).
     """
     omega = np.asarray(omega, float)
@@ -365,7 +372,7 @@ def select_snapshots(omega, delta, snap_omega, n_star):
     arg = np.full(nint, -1)
     for n in range(nint):
         lo, hi = sn[n], sn[n + 1]
-        inside = (omega >= lo) & ((omega < hi) if n < nint - 1 else (omega <= hi))
+        inside = (omega > lo) & (omega < hi)
         idx = np.flatnonzero(inside)
         if idx.size == 0:
             continue
@@ -381,7 +388,7 @@ def select_snapshots(omega, delta, snap_omega, n_star):
 
 
 def select_snapshots_threshold(omega, delta, snap_omega, theta):
-    """Threshold variant of the selection step (§4.3, after Hesthaven et al.):
+    """Threshold variant of the selection step (Section 4.4, after Hesthaven et al.):
     instead of a fixed N_*, every interval whose maximum certificate reaches
     theta * Lambda (0 < theta <= 1) contributes one new snapshot at the omega
     attaining its maximum, at most one per interval as in Algorithm 1.  The
@@ -403,7 +410,7 @@ def forward_sensitivity(rom, omega, alpha, wR, wI):
     Returns (dL/domega (n_omega,), sigma * dL/dsigma)."""
     omega = np.atleast_1d(np.asarray(omega, float))
     a3 = alpha ** 3
-    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    A0 = a0_of(rom)
     KM, CM, g, E = rom["KM"], rom["CM"], rom["g"], rom["E"]
     dw = np.empty(omega.size)
     ds = 0.0
@@ -437,7 +444,7 @@ def forward_sensitivity_materials(rom, parts, omega, alpha, wR, wI):
     parts: list of dicts with keys CM, g, E.  Returns one value per part."""
     omega = np.atleast_1d(np.asarray(omega, float))
     a3 = alpha ** 3
-    A0 = rom["KM"] + rom["eps_h"] * rom["UhU"]
+    A0 = a0_of(rom)
     KM, CM, g = rom["KM"], rom["CM"], rom["g"]
     out = np.zeros(len(parts))
     for k, om in enumerate(omega):

@@ -18,23 +18,17 @@ struct mpt_handle_s {
   hipStream_t stream = nullptr;
   std::string err;
   int n_cu = 256;
-  // library-owned buffers for the batched path (work items, counters, offsets)
-  void* buf = nullptr;      // batched work items / counters (referenced by the graph)
-  size_t buf_bytes = 0;
-  void* scr = nullptr;      // scratch of the single-object calls
-  size_t scr_bytes = 0;
   int* host_M = nullptr;  // pinned
   // cached graph of the last batched launch
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
   hipStream_t cap = nullptr;  // private stream used only to record graphs
-  // uploaded plan of the last batched pencil call (jobs, per-object arguments,
-  // work items) and the key it was built for
-  void* pbuf = nullptr;
-  size_t pbuf_bytes = 0;
+  // key of the plan (jobs, per-object arguments, work items) that the last
+  // batched pencil call uploaded into its caller's buffer
   std::vector<int64_t> pkey;
   int pn[4] = {0, 0, 0, 0};
   int pmaxM = 0;
+  int pmaxRef = 0;
 };
 
 namespace {
@@ -58,41 +52,12 @@ mpt_status fail(mpt_handle h, mpt_status s, const std::string& m) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-mpt_status ensure_buf(mpt_handle h, size_t bytes) {
-  if (h->buf_bytes >= bytes) return MPT_OK;
-  if (h->buf) {
-    HIP_OK(hipStreamSynchronize(h->stream));
-    HIP_OK(hipFree(h->buf));
-    h->buf = nullptr;
-    h->buf_bytes = 0;
-  }
-  if (h->gexec) {  // the cached graph points into the old buffer
-    HIP_OK(hipGraphExecDestroy(h->gexec));
-    h->gexec = nullptr;
-    h->gkey.clear();
-  }
-  HIP_OK(hipMalloc(&h->buf, bytes));
-  h->buf_bytes = bytes;
-  return MPT_OK;
-}
-
-mpt_status ensure_scr(mpt_handle h, size_t bytes) {
-  if (h->scr_bytes >= bytes) return MPT_OK;
-  if (h->scr) {
-    HIP_OK(hipStreamSynchronize(h->stream));
-    HIP_OK(hipFree(h->scr));
-    h->scr = nullptr;
-    h->scr_bytes = 0;
-  }
-  HIP_OK(hipMalloc(&h->scr, bytes));
-  h->scr_bytes = bytes;
-  return MPT_OK;
-}
-
 mpt_status check_rom(mpt_handle h, const mpt_rom* R) {
   ARG(R != nullptr, "rom is NULL");
   ARG(R->M >= 1 && R->M <= 96, "rom M must be in [1, 96]");
-  ARG(R->KM && R->A0 && R->CM && R->g && R->G && R->E && R->N0, "rom has a NULL matrix");
+  ARG(R->KM && R->A0 && R->CM && R->g && R->G && R->Dp && R->s_ref && R->E && R->N0,
+      "rom has a NULL matrix");
+  ARG(R->n_ref >= 1 && R->n_ref <= 64, "rom n_ref must be in [1, 64]");
   ARG(R->alpha > 0.0 && R->alpha_lb > 0.0, "rom alpha and alpha_lb must be positive");
   return MPT_OK;
 }
@@ -147,27 +112,23 @@ __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __
   }
 }
 
-// Zc = [c w (3) | c U (M)] and Uc = U[cond] (n_c rows); also wc (real w, 3)
+// Zc = sqrt(c) [w (3) | U (M)] on the n_c conductor rows
 __global__ void k_gather_cond(const int32_t* __restrict__ cond, int64_t nc,
                               const double* __restrict__ c, const double* __restrict__ w,
                               const double2* __restrict__ U, int64_t ldU, int M,
-                              double2* __restrict__ Zc, double2* __restrict__ Uc,
-                              double2* __restrict__ Wc) {
+                              double2* __restrict__ Zc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = nc * (M + 3);
   if (e >= tot) return;
   const int64_t r = e / (M + 3);
   const int j = (int)(e % (M + 3));
   const int64_t row = cond[r];
-  const double cc = c[row];
+  const double sc = sqrt(c[row]);
   if (j < 3) {
-    const double wv = w[row * 3 + j];
-    Zc[r * (M + 3) + j] = make_double2(cc * wv, 0.0);
-    Wc[r * 3 + j] = make_double2(wv, 0.0);
+    Zc[e] = make_double2(sc * w[row * 3 + j], 0.0);
   } else {
     const double2 u = U[row * ldU + (j - 3)];
-    Zc[r * (M + 3) + j] = make_double2(cc * u.x, cc * u.y);
-    Uc[r * M + (j - 3)] = u;
+    Zc[e] = make_double2(sc * u.x, sc * u.y);
   }
 }
 
@@ -178,70 +139,38 @@ __global__ void k_real_to_complex(const double* __restrict__ x, int64_t cnt,
   if (i < cnt) y[i] = make_double2(x[i], 0.0);
 }
 
-// assemble A0, CM, g, G, E, N0 from the small contractions
-//   KM (M x M), UhU (M x M), Gc ((M+3)^2 = Zc^H S Zc), P (M x (M+3) = Uc^H Zc),
-//   Ew (3 x 3 complex = Wc^H (c w)), No (3 x 3 complex = o^H K o or NULL)
-__global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KM,
-                           const double2* __restrict__ UhU, const double2* __restrict__ Gc,
-                           const double2* __restrict__ P, const double2* __restrict__ Ew,
+// assemble K_M, A0, C_M, g, E, N0 from the small contractions
+//   KMt (M x M = U^H K U), UhU (M x M), P ((M+3)^2 = Zc^H Zc: C_M, g and E),
+//   No (3 x 3 complex = o^H K o, or NULL)
+__global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KMt,
+                           const double2* __restrict__ UhU, const double2* __restrict__ P,
                            const double2* __restrict__ No, const double* __restrict__ vol,
                            double alpha, double2* __restrict__ KMo, double2* __restrict__ A0,
                            double2* __restrict__ CM, double2* __restrict__ g,
-                           double2* __restrict__ G, double* __restrict__ E,
-                           double* __restrict__ N0) {
-  const int L = 2 * M + 3;
+                           double* __restrict__ E, double* __restrict__ N0) {
+  const int L = M + 3;
   // K_M, U^H U and C_M are Hermitian by definition; the two computed
   // triangles are averaged (the sweep reads them column-wise)
   auto herm = [&](const double2* X, int ld, int off, int i, int j) {
-    const double2 u = X[i * ld + off + j], t = X[j * ld + off + i];
+    const double2 u = X[(off + i) * ld + off + j], t = X[(off + j) * ld + off + i];
     return make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
   };
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nthreads = gridDim.x * blockDim.x;
-  // position maps: G index -> (block, local)
-  for (int e = tid; e < L * L; e += nthreads) {
-    const int a = e / L, b = e % L;
-    // classify: w (0..2), x (3..3+M), c (3+M..)
-    auto cls = [&](int i, int& loc) {
-      if (i < 3) { loc = i; return 0; }
-      if (i < 3 + M) { loc = i - 3; return 1; }
-      loc = i - 3 - M; return 2;
-    };
-    int la, lb;
-    const int ca = cls(a, la), cb = cls(b, lb);
-    double2 v;
-    const int LG = M + 3;  // Gc / Zc column index: w -> 0..2, c -> 3..
-    if (ca != 1 && cb != 1) {
-      // Z^H X^{-1} Z is Hermitian: average the two computed triangles
-      const int ia = ca == 0 ? la : 3 + la, ib = cb == 0 ? lb : 3 + lb;
-      const double2 u = Gc[ia * LG + ib], t = Gc[ib * LG + ia];
-      v = make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
-    } else if (ca == 1 && cb == 1) {
-      const double2 k = herm(KM, M, 0, la, lb), u = herm(UhU, M, 0, la, lb);
-      v = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
-    } else if (ca == 1) {  // x row, w/c column: (X U)^H X^{-1} Z = U^H Z = P
-      const int ib = cb == 0 ? lb : 3 + lb;
-      v = P[la * LG + ib];
-    } else {  // w/c row, x column: conj(P)^T
-      const int ia = ca == 0 ? la : 3 + la;
-      v = cconj(P[lb * LG + ia]);
-    }
-    G[e] = v;
-  }
   for (int e = tid; e < M * M; e += nthreads) {
     const int i = e / M, j = e % M;
-    const double2 k = herm(KM, M, 0, i, j), u = herm(UhU, M, 0, i, j);
+    const double2 k = herm(KMt, M, 0, i, j), u = herm(UhU, M, 0, i, j);
     KMo[e] = k;
-    A0[e] = make_double2(k.x + eps_h * u.x, k.y + eps_h * u.y);
-    CM[e] = herm(P, M + 3, 3, i, j);
+    A0[e] = make_double2(fma(eps_h, u.x, k.x), fma(eps_h, u.y, k.y));
+    CM[e] = herm(P, L, 3, i, j);
   }
   for (int e = tid; e < 3 * M; e += nthreads) {
     const int i = e / M, m = e % M;
-    g[e] = P[m * (M + 3) + i];  // g_i[m] = (Uc^H c w_i)[m]
+    g[e] = P[(3 + m) * L + i];  // g_i[m] = (U_c^H c w_i)[m]
   }
   if (tid < 9) {
     const int i = tid / 3, j = tid % 3;
-    E[tid] = Ew[tid].x;
+    E[tid] = 0.5 * (P[i * L + j].x + P[j * L + i].x);
     const double a3 = alpha * alpha * alpha;
     double n0 = (i == j) ? a3 * vol[i] : 0.0;
     if (No) n0 += 0.25 * a3 * No[tid].x;
@@ -284,9 +213,6 @@ extern "C" mpt_status mpt_destroy(mpt_handle h) {
   else hipDeviceSynchronize();
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->cap) hipStreamDestroy(h->cap);
-  if (h->buf) hipFree(h->buf);
-  if (h->scr) hipFree(h->scr);
-  if (h->pbuf) hipFree(h->pbuf);
   if (h->host_M) hipHostFree(h->host_M);
   delete h;
   return MPT_OK;
@@ -381,34 +307,28 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
 }
 
 // ---------------------------------------------------------- a2 projection
-static void proj_layout(int64_t N, int M, int64_t nc, size_t* off) {
+static void proj_layout(int64_t N, int M, int64_t nc, int n_ref, size_t* off) {
   const int L = M + 3;
   const int64_t gN = std::max<int64_t>(N, nc);
   size_t o = 0;
   off[0] = o; o = align256(o + (size_t)N * M * 16);         // Y (when not given)
   off[1] = o; o = align256(o + (size_t)M * M * 16);         // UhU
   off[2] = o; o = align256(o + (size_t)nc * L * 16);        // Zc
-  off[3] = o; o = align256(o + (size_t)nc * M * 16);        // Uc
-  off[4] = o; o = align256(o + (size_t)nc * L * 16);        // T = S Zc
-  off[5] = o; o = align256(o + (size_t)L * L * 16);         // Gc
-  off[6] = o; o = align256(o + (size_t)M * L * 16);         // P
-  off[7] = o; o = align256(o + (size_t)nc * 3 * 16);        // Wc
-  off[8] = o; o = align256(o + 9 * 16);                     // Ew
-  off[9] = o; o = align256(o + (size_t)N * 3 * 16);         // Oc (o as complex)
-  off[10] = o; o = align256(o + (size_t)N * 3 * 16);        // KO
-  off[11] = o; o = align256(o + 9 * 16);                    // No
-  off[12] = o; o = align256(o + (size_t)M * M * 16);        // U^H K U before symmetrising
-  off[13] = o;
-  o = align256(o + std::max(std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)),
-                            rcgemm_ws_size(nc, L)));
-  off[14] = o;
+  off[3] = o; o = align256(o + (size_t)L * L * 16);         // P = Zc^H Zc
+  off[4] = o; o = align256(o + (size_t)N * 3 * 16);         // Oc (o as complex)
+  off[5] = o; o = align256(o + (size_t)N * 3 * 16);         // KO
+  off[6] = o; o = align256(o + 9 * 16);                     // No
+  off[7] = o; o = align256(o + (size_t)M * M * 16);         // U^H K U before symmetrising
+  off[8] = o; o = align256(o + std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)));
+  off[9] = o; o = align256(o + cert_ws_size(N, M, nc, n_ref));
+  off[10] = o;
 }
 
-extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c) {
-  if (N <= 0 || M <= 0) return 0;
-  size_t off[15];
-  proj_layout(N, M, n_c, off);
-  return off[14];
+extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c, int n_ref) {
+  if (N <= 0 || M <= 0 || n_ref <= 0) return 0;
+  size_t off[11];
+  proj_layout(N, M, n_c, n_ref, off);
+  return off[10];
 }
 
 static bool row_blocks_ok(const mpt_csr& K) {
@@ -430,55 +350,51 @@ extern "C" mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, 
 extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
                                   const double* w, const double* o, const double* vol,
                                   double alpha, const double* U, int64_t ldU, int M,
-                                  const int32_t* cond, int64_t n_c, const double* S, double* KM,
-                                  double* A0, double* CM, double* g, double* G, double* E,
-                                  double* N0, double* Y, void* ws, size_t ws_bytes) {
+                                  const int32_t* cond, int64_t n_c, const double* Vt,
+                                  const double* lam, int n_ref, const double* s_ref, double* KM,
+                                  double* A0, double* CM, double* g, double* G, double* Dp,
+                                  double* E, double* N0, double* Y, void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
-  ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && S, "NULL input");
-  ARG(KM && A0 && CM && g && G && E && N0 && ws, "NULL output");
-  ARG(K->n > 0 && M >= 1 && ldU >= M && n_c >= 1 && n_c <= K->n, "bad sizes");
+  ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && Vt && lam && s_ref,
+      "NULL input");
+  ARG(KM && A0 && CM && g && G && Dp && E && N0 && ws, "NULL output");
+  ARG(K->n > 0 && M >= 1 && M <= mpt_max_reduced_dim() && ldU >= M && n_c >= 1 && n_c <= K->n,
+      "bad sizes");
+  ARG(n_ref >= 1 && n_ref <= 64, "n_ref must be in [1, 64]");
   ARG(row_blocks_ok(*K), "row_blocks must be >= 0 and divide n");
   ARG(eps_h >= 0.0 && alpha > 0.0, "bad eps_h or alpha");
-  ARG(ws_bytes >= mpt_project_ws_size(K->n, M, n_c), "workspace too small");
+  ARG(ws_bytes >= mpt_project_ws_size(K->n, M, n_c, n_ref), "workspace too small");
   HIP_OK(hipSetDevice(h->device));
   hipStream_t st = h->stream;
   const int64_t N = K->n;
   const int L = M + 3;
-  size_t off[15];
-  proj_layout(N, M, n_c, off);
+  size_t off[11];
+  proj_layout(N, M, n_c, n_ref, off);
   char* wsb = reinterpret_cast<char*>(ws);
   double* Yb = Y ? Y : reinterpret_cast<double*>(wsb + off[0]);
   const int64_t ldY = M;
   double* UhU = reinterpret_cast<double*>(wsb + off[1]);
   double* Zc = reinterpret_cast<double*>(wsb + off[2]);
-  double* Uc = reinterpret_cast<double*>(wsb + off[3]);
-  double* T = reinterpret_cast<double*>(wsb + off[4]);
-  double* Gc = reinterpret_cast<double*>(wsb + off[5]);
-  double* P = reinterpret_cast<double*>(wsb + off[6]);
-  double* Wc = reinterpret_cast<double*>(wsb + off[7]);
-  double* Ew = reinterpret_cast<double*>(wsb + off[8]);
-  double* Oc = reinterpret_cast<double*>(wsb + off[9]);
-  double* KO = reinterpret_cast<double*>(wsb + off[10]);
-  double* No = reinterpret_cast<double*>(wsb + off[11]);
-  double* KMt = reinterpret_cast<double*>(wsb + off[12]);
-  void* gws = wsb + off[13];
+  double* P = reinterpret_cast<double*>(wsb + off[3]);
+  double* Oc = reinterpret_cast<double*>(wsb + off[4]);
+  double* KO = reinterpret_cast<double*>(wsb + off[5]);
+  double* No = reinterpret_cast<double*>(wsb + off[6]);
+  double* KMt = reinterpret_cast<double*>(wsb + off[7]);
+  void* gws = wsb + off[8];
+  void* cws = wsb + off[9];
 
   // Y = K U; K_M = U^H Y; U^H U
   HIP_OK(spmm_launch(*K, U, ldU, M, Yb, ldY, st));
   HIP_OK(gram2_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, gws, st));
-  // conductor block: Zc = [c w | c U], T = S Zc, Gc = Zc^H T, P = Uc^H Zc
+  // conductor rows: Zc = sqrt(c) [w | U], P = Zc^H Zc (C_M, g, E)
   {
     const int64_t tot = n_c * L;
     hipLaunchKernelGGL(k_gather_cond, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, cond,
                        n_c, c, w, reinterpret_cast<const double2*>(U), ldU, M,
-                       reinterpret_cast<double2*>(Zc), reinterpret_cast<double2*>(Uc),
-                       reinterpret_cast<double2*>(Wc));
+                       reinterpret_cast<double2*>(Zc));
     HIP_OK(hipGetLastError());
   }
-  HIP_OK(real_complex_gemm(S, n_c, Zc, L, T, gws, st));
-  HIP_OK(gram_launch(Zc, L, T, L, n_c, L, L, Gc, L, gws, st));
-  HIP_OK(gram_launch(Uc, M, Zc, L, n_c, M, L, P, L, gws, st));
-  HIP_OK(gram_launch(Wc, 3, Zc, L, n_c, 3, 3, Ew, 3, gws, st));
+  HIP_OK(gram_launch(Zc, L, Zc, L, n_c, L, L, P, L, gws, st));
   // static tensor: o^H K o
   const double2* Nop = nullptr;
   if (o) {
@@ -492,12 +408,13 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
   }
   hipLaunchKernelGGL(k_assemble, dim3(64), dim3(256), 0, st, M, eps_h,
                      reinterpret_cast<const double2*>(KMt), reinterpret_cast<const double2*>(UhU),
-                     reinterpret_cast<const double2*>(Gc), reinterpret_cast<const double2*>(P),
-                     reinterpret_cast<const double2*>(Ew), Nop, vol, alpha,
+                     reinterpret_cast<const double2*>(P), Nop, vol, alpha,
                      reinterpret_cast<double2*>(KM), reinterpret_cast<double2*>(A0),
-                     reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g),
-                     reinterpret_cast<double2*>(G), E, N0);
+                     reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g), E, N0);
   HIP_OK(hipGetLastError());
+  // certificate data per reference shift: G_s and D'_s (Lemma 4.1)
+  HIP_OK(cert_launch(Yb, ldY, U, ldU, N, M, Zc, n_c, Vt, lam, n_ref, s_ref, A0, CM, UhU, eps_h,
+                     G, Dp, cws, st));
   return MPT_OK;
 }
 
@@ -561,19 +478,54 @@ extern "C" mpt_status mpt_sweep_adjoint(mpt_handle h, const mpt_rom* rom, const 
   ARG(n >= 1, "n must be >= 1");
   ARG(omega && dout && dL_domega && sig_dsig && status, "NULL pointer");
   HIP_OK(hipSetDevice(h->device));
-  // scratch for the (discarded) forward outputs and the object offsets
-  const size_t need = align256((size_t)n * 18 * 8) + 256;
-  s = ensure_scr(h, need);
-  if (s != MPT_OK) return s;
-  double* fwd = reinterpret_cast<double*>(h->scr);
-  int64_t* offd = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(h->scr) +
-                                             align256((size_t)n * 18 * 8));
-  const int64_t offh[2] = {0, n};
-  HIP_OK(hipMemcpyAsync(offd, offh, sizeof(offh), hipMemcpyHostToDevice, h->stream));
-  HIP_OK(sweep_launch(*rom, omega, n, fwd, nullptr, status, dout, dL_domega, h->stream));
-  HIP_OK(sigma_reduce(omega, dL_domega, offd, 1, sig_dsig, h->stream));
-  HIP_OK(hipStreamSynchronize(h->stream));  // offh is a host stack array
+  // the forward outputs are not kept (out = NULL)
+  HIP_OK(sweep_launch(*rom, omega, n, nullptr, nullptr, status, dout, dL_domega, h->stream));
+  HIP_OK(sigma_reduce_one(omega, dL_domega, n, nullptr, sig_dsig, h->stream));
   return MPT_OK;
+}
+
+extern "C" mpt_status mpt_signature(mpt_handle h, const mpt_rom* rom, const double* omega,
+                                    int64_t n, const double* sigma, double sigma0, double* out,
+                                    int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the signature form takes M <= 64");
+  ARG(n >= 0, "n < 0");
+  ARG(sigma && sigma0 > 0.0, "need a conductivity pointer and sigma0 > 0");
+  ARG(n == 0 || (omega && out && status), "NULL omega/out/status");
+  HIP_OK(hipSetDevice(h->device));
+  mpt::MatSens ms;
+  ms.sigma = sigma;
+  ms.inv_sigma0 = 1.0 / sigma0;
+  HIP_OK(sweep_launch(*rom, omega, n, out, nullptr, status, nullptr, nullptr, h->stream, ms));
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_signature_adjoint(mpt_handle h, const mpt_rom* rom,
+                                            const double* omega, int64_t n, const double* sigma,
+                                            double sigma0, const double* dout,
+                                            double* dL_domega, double* dL_dsigma,
+                                            int32_t* status) {
+  if (!h) return MPT_E_ARG;
+  mpt_status s = check_rom(h, rom);
+  if (s != MPT_OK) return s;
+  if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the signature form takes M <= 64");
+  ARG(n >= 1, "n must be >= 1");
+  ARG(sigma && sigma0 > 0.0, "need a conductivity pointer and sigma0 > 0");
+  ARG(omega && dout && dL_domega && dL_dsigma && status, "NULL pointer");
+  HIP_OK(hipSetDevice(h->device));
+  mpt::MatSens ms;
+  ms.sigma = sigma;
+  ms.inv_sigma0 = 1.0 / sigma0;
+  HIP_OK(sweep_launch(*rom, omega, n, nullptr, nullptr, status, dout, dL_domega, h->stream, ms));
+  // the model depends on w sigma only: dL/dsigma = sum_k w_k dL/dw_k / sigma
+  HIP_OK(sigma_reduce_one(omega, dL_domega, n, sigma, dL_dsigma, h->stream));
+  return MPT_OK;
+}
+
+extern "C" size_t mpt_sweep_adjoint_materials_ws_size(int64_t n) {
+  return n < 1 ? 0 : align256((size_t)n * 8);
 }
 
 extern "C" mpt_status mpt_sweep_adjoint_materials(mpt_handle h, const mpt_rom* rom,
@@ -581,35 +533,32 @@ extern "C" mpt_status mpt_sweep_adjoint_materials(mpt_handle h, const mpt_rom* r
                                                   const double* E1, const double* omega,
                                                   int64_t n, const double* dout,
                                                   double* dL_domega, double* sig_dsig,
-                                                  int32_t* status) {
+                                                  int32_t* status, void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   mpt_status s = check_rom(h, rom);
   if (s != MPT_OK) return s;
   if (rom->M > 64) return fail(h, MPT_E_UNSUPPORTED, "the adjoint sweep takes M <= 64");
   ARG(n >= 1, "n must be >= 1");
   ARG(CM1 && g1 && E1, "NULL material part");
-  ARG(omega && dout && dL_domega && sig_dsig && status, "NULL pointer");
+  ARG(omega && dout && dL_domega && sig_dsig && status && ws, "NULL pointer");
+  ARG(ws_bytes >= mpt_sweep_adjoint_materials_ws_size(n), "workspace too small");
   HIP_OK(hipSetDevice(h->device));
-  // scratch: the (discarded) forward outputs and the per-frequency sigma_1 terms
-  const size_t fwd_bytes = align256((size_t)n * 18 * 8);
-  s = ensure_scr(h, fwd_bytes + align256((size_t)n * 8));
-  if (s != MPT_OK) return s;
-  double* fwd = reinterpret_cast<double*>(h->scr);
-  double* dsig = reinterpret_cast<double*>(reinterpret_cast<char*>(h->scr) + fwd_bytes);
+  // ws: the per-frequency sigma_1 terms
+  double* dsig = reinterpret_cast<double*>(ws);
   mpt::MatSens ms;
   ms.CM1 = CM1;
   ms.g1 = g1;
   ms.E1 = E1;
   ms.dsig = dsig;
-  HIP_OK(sweep_launch(*rom, omega, n, fwd, nullptr, status, dout, dL_domega, h->stream, ms));
+  HIP_OK(sweep_launch(*rom, omega, n, nullptr, nullptr, status, dout, dL_domega, h->stream, ms));
   HIP_OK(mpt::material_reduce(omega, dL_domega, dsig, n, sig_dsig, h->stream));
   return MPT_OK;
 }
 
 // ------------------------------------------------------ pencil form sweep
-extern "C" size_t mpt_pencil_bytes(int M) {
-  if (M < 1 || M > 96) return 0;
-  return mpt::pencil_layout(M).total;
+extern "C" size_t mpt_pencil_bytes(int M, int n_ref) {
+  if (M < 1 || M > 96 || n_ref < 1 || n_ref > mpt::kPenMaxRef) return 0;
+  return mpt::pencil_total_bytes(M, n_ref);
 }
 
 extern "C" mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf,
@@ -619,14 +568,15 @@ extern "C" mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* 
   if (s != MPT_OK) return s;
   ARG(buf != nullptr && out != nullptr, "NULL buf/out");
   const mpt::PencilLayout L = mpt::pencil_layout(rom->M);
-  if (bytes < L.total) return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
+  if (bytes < mpt::pencil_total_bytes(rom->M, rom->n_ref))
+    return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
   HIP_OK(hipSetDevice(h->device));
-  mpt::PencilJob job{rom->M, 0, rom->A0, rom->CM, rom->KM, rom->G, rom->g, rom->E, rom->N0,
-                     static_cast<char*>(buf)};
-  HIP_OK(mpt::pencil_reduce_launch(job, nullptr, 1, rom->M, h->stream));
+  mpt::PencilJob job{rom->M,     rom->n_ref, rom->A0, rom->CM, rom->KM, rom->G,
+                     rom->Dp,    rom->s_ref, rom->g,  rom->E,  rom->N0, static_cast<char*>(buf)};
+  HIP_OK(mpt::pencil_reduce_launch(job, nullptr, 1, rom->M, rom->n_ref, h->stream));
   char* b = static_cast<char*>(buf);
   out->M = rom->M;
-  out->pad_ = 0;
+  out->n_ref = rom->n_ref;
   out->H = reinterpret_cast<const double*>(b + L.H);
   out->T = reinterpret_cast<const double*>(b + L.T);
   out->f = reinterpret_cast<const double*>(b + L.f);
@@ -644,6 +594,7 @@ extern "C" mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, cons
   if (!h) return MPT_E_ARG;
   ARG(pen != nullptr, "pencil is NULL");
   ARG(pen->M >= 1 && pen->M <= 96, "pencil M must be in [1, 96]");
+  ARG(pen->n_ref >= 1 && pen->n_ref <= mpt::kPenMaxRef, "pencil n_ref must be in [1, 64]");
   ARG(pen->H && pen->T && pen->f && pen->Z && pen->W && pen->S, "pencil has a NULL part");
   ARG(pen->alpha > 0.0 && pen->alpha_lb > 0.0, "pencil alpha and alpha_lb must be positive");
   ARG(n_omega >= 0, "n_omega < 0");
@@ -655,15 +606,28 @@ extern "C" mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, cons
 }
 
 // ------------------------------------------ pencil form for a dictionary
-extern "C" size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj) {
-  if (!roms_host || n_obj < 1) return 0;
-  size_t tot = 0;
+// the objects' pencils, packed in order, then the plan: jobs, per-object
+// sweep arguments, work items of at most 16 frequencies (plan_items of them)
+static size_t pencil_plan_bytes(int n_obj, size_t plan_items) {
+  return align256(n_obj * sizeof(mpt::PencilJob)) + align256(n_obj * sizeof(mpt::PencilArgs)) +
+         align256(plan_items * sizeof(int4));
+}
+
+extern "C" size_t mpt_pencil_batched_bytes(const mpt_rom* roms_host, int n_obj,
+                                           const int64_t* omega_off) {
+  if (!roms_host || !omega_off || n_obj < 1) return 0;
+  size_t tot = 0, items = 0;
   for (int o = 0; o < n_obj; ++o) {
     const int M = roms_host[o].M;
     if (M < 1 || M > 96) return 0;
-    tot += mpt::pencil_layout(M).total;
+    const int nr = roms_host[o].n_ref;
+    if (nr < 1 || nr > mpt::kPenMaxRef) return 0;
+    tot += mpt::pencil_total_bytes(M, nr);
+    const int64_t cnt = omega_off[o + 1] - omega_off[o];
+    if (cnt < 0) return 0;
+    items += (size_t)((cnt + 15) / 16);
   }
-  return tot;
+  return align256(tot) + pencil_plan_bytes(n_obj, items);
 }
 
 extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms_host, int n_obj,
@@ -678,8 +642,12 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     ARG(omega_off[o + 1] >= omega_off[o], "omega_off must be non-decreasing");
   }
   ARG(omega_off[0] == 0, "omega_off[0] must be 0");
-  if (bytes < mpt_pencil_batched_bytes(roms_host, n_obj))
+  if (bytes < mpt_pencil_batched_bytes(roms_host, n_obj, omega_off))
     return fail(h, MPT_E_NOMEM, "buffer smaller than mpt_pencil_batched_bytes");
+  size_t pen_bytes = 0;
+  for (int o = 0; o < n_obj; ++o)
+    pen_bytes += mpt::pencil_total_bytes(roms_host[o].M, roms_host[o].n_ref);
+  char* pb = static_cast<char*>(buf) + align256(pen_bytes);  // the plan region
   HIP_OK(hipSetDevice(h->device));
   std::vector<int64_t> key = {(int64_t)buf, (int64_t)omega, (int64_t)out, (int64_t)status, n_obj};
   for (int o = 0; o <= n_obj; ++o) key.push_back(omega_off[o]);
@@ -688,8 +656,9 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     int64_t a, b;
     std::memcpy(&a, &r.alpha, 8);
     std::memcpy(&b, &r.alpha_lb, 8);
-    for (int64_t v : {(int64_t)r.M, (int64_t)r.KM, (int64_t)r.A0, (int64_t)r.CM, (int64_t)r.g,
-                      (int64_t)r.G, (int64_t)r.E, (int64_t)r.N0, a, b})
+    for (int64_t v : {(int64_t)r.M, (int64_t)r.n_ref, (int64_t)r.KM, (int64_t)r.A0,
+                      (int64_t)r.CM, (int64_t)r.g, (int64_t)r.G, (int64_t)r.Dp, (int64_t)r.s_ref,
+                      (int64_t)r.E, (int64_t)r.N0, a, b})
       key.push_back(v);
   }
   if (key != h->pkey) {
@@ -697,18 +666,21 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     std::vector<mpt::PencilArgs> args(n_obj);
     std::vector<int4> items[4];
     char* base = static_cast<char*>(buf);
-    int maxM = 1;
+    int maxM = 1, maxRef = 1;
     for (int o = 0; o < n_obj; ++o) {
       const mpt_rom& r = roms_host[o];
-      jobs[o] = mpt::PencilJob{r.M, 0, r.A0, r.CM, r.KM, r.G, r.g, r.E, r.N0, base};
+      jobs[o] = mpt::PencilJob{r.M, r.n_ref, r.A0,   r.CM, r.KM, r.G,
+                               r.Dp, r.s_ref, r.g, r.E, r.N0, base};
       mpt_pencil pen{};
       pen.M = r.M;
+      pen.n_ref = r.n_ref;
       pen.H = reinterpret_cast<const double*>(base);
       pen.alpha = r.alpha;
       pen.alpha_lb = r.alpha_lb;
       args[o] = mpt::pencil_args(pen);
-      base += mpt::pencil_layout(r.M).total;
+      base += mpt::pencil_total_bytes(r.M, r.n_ref);
       maxM = std::max(maxM, r.M);
+      maxRef = std::max(maxRef, r.n_ref);
       const int bi = r.M <= 16 ? 0 : (r.M <= 32 ? 1 : (r.M <= 64 ? 2 : 3));
       for (int64_t k = omega_off[o]; k < omega_off[o + 1]; k += 16) {
         const int cnt = (int)std::min<int64_t>(16, omega_off[o + 1] - k);
@@ -718,21 +690,9 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     const size_t jb = align256(n_obj * sizeof(mpt::PencilJob));
     const size_t ab = align256(n_obj * sizeof(mpt::PencilArgs));
     const size_t ni = items[0].size() + items[1].size() + items[2].size() + items[3].size();
-    const size_t need = jb + ab + align256(ni * sizeof(int4));
-    if (h->pbuf_bytes < need) {
-      if (h->pbuf) {
-        HIP_OK(hipStreamSynchronize(h->stream));
-        HIP_OK(hipFree(h->pbuf));
-        h->pbuf = nullptr;
-        h->pbuf_bytes = 0;
-      }
-      HIP_OK(hipMalloc(&h->pbuf, need));
-      h->pbuf_bytes = need;
-    }
     std::vector<int4> all;
     all.reserve(ni);
     for (auto& v : items) all.insert(all.end(), v.begin(), v.end());
-    char* pb = static_cast<char*>(h->pbuf);
     HIP_OK(hipMemcpyAsync(pb, jobs.data(), n_obj * sizeof(mpt::PencilJob), hipMemcpyHostToDevice,
                           h->stream));
     HIP_OK(hipMemcpyAsync(pb + jb, args.data(), n_obj * sizeof(mpt::PencilArgs),
@@ -743,16 +703,16 @@ extern "C" mpt_status mpt_sweep_pencil_batched(mpt_handle h, const mpt_rom* roms
     HIP_OK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
     for (int b = 0; b < 4; ++b) h->pn[b] = (int)items[b].size();
     h->pmaxM = maxM;
+    h->pmaxRef = maxRef;
     h->pkey = key;
   }
-  char* pb = static_cast<char*>(h->pbuf);
   const size_t jb = align256(n_obj * sizeof(mpt::PencilJob));
   const size_t ab = align256(n_obj * sizeof(mpt::PencilArgs));
   const auto* jobs = reinterpret_cast<const mpt::PencilJob*>(pb);
   const auto* args = reinterpret_cast<const mpt::PencilArgs*>(pb + jb);
   const int4* items = reinterpret_cast<const int4*>(pb + jb + ab);
   mpt::PencilJob none{};
-  HIP_OK(mpt::pencil_reduce_launch(none, jobs, n_obj, h->pmaxM, h->stream));
+  HIP_OK(mpt::pencil_reduce_launch(none, jobs, n_obj, h->pmaxM, h->pmaxRef, h->stream));
   const int Ls[4] = {16, 32, 64, 96};
   int at = 0;
   for (int b = 0; b < 4; ++b) {
@@ -818,18 +778,21 @@ extern "C" mpt_status mpt_tensors_fmm(mpt_handle h, const mpt_csr* K, const doub
 }
 
 // -------------------------------------------------------------- a5 select
+extern "C" size_t mpt_select_snapshots_ws_size(int n_snap) {
+  return n_snap < 2 ? 0 : align256((size_t)n_snap * 8);
+}
+
 extern "C" mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n,
                                            const double* out, const double* snap, int n_snap,
                                            int n_star, double* new_omega, double* lambda,
-                                           double* Lambda_max) {
+                                           double* Lambda_max, void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
-  ARG(omega && out && snap && new_omega && lambda && Lambda_max, "NULL pointer");
+  ARG(omega && out && snap && new_omega && lambda && Lambda_max && ws, "NULL pointer");
   ARG(n >= 1 && n_snap >= 2 && n_star >= 1 && n_star <= 64, "bad sizes");
+  ARG(ws_bytes >= mpt_select_snapshots_ws_size(n_snap), "workspace too small");
   HIP_OK(hipSetDevice(h->device));
-  mpt_status s = ensure_scr(h, align256((size_t)n_snap * 8));
-  if (s != MPT_OK) return s;
   HIP_OK(select_launch(omega, n, out, snap, n_snap, n_star, new_omega, lambda, Lambda_max,
-                       reinterpret_cast<int64_t*>(h->scr), h->stream));
+                       reinterpret_cast<int64_t*>(ws), h->stream));
   return MPT_OK;
 }
 
@@ -837,16 +800,16 @@ extern "C" mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double*
                                                      const double* out, const double* snap,
                                                      int n_snap, double theta, double* new_omega,
                                                      int32_t* n_new, double* lambda,
-                                                     double* Lambda_max) {
+                                                     double* Lambda_max, void* ws,
+                                                     size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
-  ARG(omega && out && snap && new_omega && n_new && lambda && Lambda_max, "NULL pointer");
+  ARG(omega && out && snap && new_omega && n_new && lambda && Lambda_max && ws, "NULL pointer");
   ARG(n >= 1 && n_snap >= 2, "bad sizes");
   ARG(theta > 0.0 && theta <= 1.0, "theta must be in (0, 1]");
+  ARG(ws_bytes >= mpt_select_snapshots_ws_size(n_snap), "workspace too small");
   HIP_OK(hipSetDevice(h->device));
-  mpt_status s = ensure_scr(h, align256((size_t)n_snap * 8));
-  if (s != MPT_OK) return s;
   HIP_OK(select_threshold_launch(omega, n, out, snap, n_snap, theta, new_omega, n_new, lambda,
-                                 Lambda_max, reinterpret_cast<int64_t*>(h->scr), h->stream));
+                                 Lambda_max, reinterpret_cast<int64_t*>(ws), h->stream));
   return MPT_OK;
 }
 
@@ -881,11 +844,17 @@ mpt_status build_plan(mpt_handle h, const mpt_rom* roms_host, int n_obj, const i
   return MPT_OK;
 }
 
+// bytes of the batched workspace: work items, counters, object offsets
+size_t batched_ws_bytes(size_t nitems, int n_obj) {
+  return align256(nitems * sizeof(int4)) + 256 + align256((size_t)(n_obj + 1) * 8);
+}
+
 mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom* roms_dev,
                           int n_obj, const int64_t* omega_off, const double* omega, double* out,
                           int32_t* status, const mpt_tuning* tune, int use_graph,
-                          const double* dout, double* dom, double* sig) {
-  ARG(roms_host && roms_dev && omega_off && omega && status && n_obj >= 1, "NULL or empty");
+                          const double* dout, double* dom, double* sig, void* ws,
+                          size_t ws_bytes) {
+  ARG(roms_host && roms_dev && omega_off && omega && status && ws && n_obj >= 1, "NULL or empty");
   ARG(out || dout, "NULL out");
   HIP_OK(hipSetDevice(h->device));
   mpt_tuning t = {8, 4, 2, 0};
@@ -899,37 +868,39 @@ mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom*
   if (s != MPT_OK) return s;
   size_t nitems = 0;
   for (auto& v : plan.items) nitems += v.size();
-  const int64_t n_tot = omega_off[n_obj];
   const size_t items_bytes = align256(nitems * sizeof(int4));
   const size_t cnt_off = items_bytes;
   const size_t off_off = cnt_off + 256;
-  const size_t fwd_off = off_off + align256((size_t)(n_obj + 1) * 8);
-  const size_t need = fwd_off + (adj ? align256((size_t)n_tot * 18 * 8) : 0);
-  // graph cache key
+  ARG(ws_bytes >= batched_ws_bytes(nitems, n_obj), "workspace smaller than mpt_sweep_batched_ws_size");
+  // graph cache key: every argument the recorded launches depend on
   std::vector<int64_t> key = {(int64_t)roms_dev, (int64_t)omega, (int64_t)out, (int64_t)status,
-                              (int64_t)dout, (int64_t)dom, (int64_t)sig, n_obj,
+                              (int64_t)dout, (int64_t)dom, (int64_t)sig, (int64_t)ws, n_obj,
                               t.omegas_per_item, t.waves_per_group, t.groups_per_cu, adj};
   for (auto& v : plan.items) key.push_back((int64_t)v.size());
   for (int o = 0; o <= n_obj; ++o) key.push_back(omega_off[o]);
   for (int o = 0; o < n_obj; ++o) key.push_back(roms_host[o].M);
-  const bool cached = use_graph && h->gexec && key == h->gkey && h->buf_bytes >= need;
+  const bool cached = use_graph && h->gexec && key == h->gkey;
   if (!cached) {
-    s = ensure_buf(h, need);
-    if (s != MPT_OK) return s;
+    // the plan is rewritten into ws: a recorded graph reading that region
+    // would now see another plan, so it is dropped
+    if (h->gexec) {
+      HIP_OK(hipGraphExecDestroy(h->gexec));
+      h->gexec = nullptr;
+      h->gkey.clear();
+    }
     std::vector<int4> all;
     all.reserve(nitems);
     for (auto& v : plan.items) all.insert(all.end(), v.begin(), v.end());
-    char* b = reinterpret_cast<char*>(h->buf);
+    char* b = reinterpret_cast<char*>(ws);
     HIP_OK(hipMemcpyAsync(b, all.data(), nitems * sizeof(int4), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(b + off_off, omega_off, (size_t)(n_obj + 1) * 8, hipMemcpyHostToDevice,
                           h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));  // host vectors go out of scope
   }
-  char* b = reinterpret_cast<char*>(h->buf);
+  char* b = reinterpret_cast<char*>(ws);
   const int4* items = reinterpret_cast<const int4*>(b);
   unsigned int* counters = reinterpret_cast<unsigned int*>(b + cnt_off);
   const int64_t* offd = reinterpret_cast<const int64_t*>(b + off_off);
-  double* outp = adj ? reinterpret_cast<double*>(b + fwd_off) : out;
   auto enqueue = [&](hipStream_t st) -> hipError_t {
     hipError_t e = reset_counters(counters, 4, st);
     if (e != hipSuccess) return e;
@@ -942,7 +913,7 @@ mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom*
         int groups = h->n_cu * t.groups_per_cu;
         groups = std::max(1, std::min(groups, (ni + wpg - 1) / wpg));
         e = persistent_launch(buckets[bi], adj, roms_dev, items + base, ni, counters + bi, omega,
-                              outp, status, dout, dom, wpg, groups, st);
+                              adj ? nullptr : out, status, dout, dom, wpg, groups, st);
         if (e != hipSuccess) return e;
       }
       base += ni;
@@ -955,10 +926,6 @@ mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom*
     return MPT_OK;
   }
   if (!cached) {
-    if (h->gexec) {
-      HIP_OK(hipGraphExecDestroy(h->gexec));
-      h->gexec = nullptr;
-    }
     // record on a private stream (the caller's may be the null stream, which
     // cannot be captured); the instantiated graph is launched on the caller's
     if (!h->cap) HIP_OK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -981,23 +948,39 @@ mpt_status batched_common(mpt_handle h, const mpt_rom* roms_host, const mpt_rom*
 
 }  // namespace
 
+extern "C" size_t mpt_sweep_batched_ws_size(const mpt_rom* roms_host, int n_obj,
+                                            const int64_t* omega_off, const mpt_tuning* tune) {
+  if (!roms_host || !omega_off || n_obj < 1) return 0;
+  const int per = tune ? tune->omegas_per_item : 8;
+  if (per < 1) return 0;
+  size_t nitems = 0;
+  for (int o = 0; o < n_obj; ++o) {
+    const int64_t cnt = omega_off[o + 1] - omega_off[o];
+    if (cnt < 0) return 0;
+    nitems += (size_t)((cnt + per - 1) / per);
+  }
+  return batched_ws_bytes(nitems, n_obj);
+}
+
 extern "C" mpt_status mpt_sweep_batched(mpt_handle h, const mpt_rom* roms_host,
                                         const mpt_rom* roms_dev, int n_obj,
                                         const int64_t* omega_off, const double* omega, double* out,
-                                        int32_t* status, const mpt_tuning* tune, int use_graph) {
+                                        int32_t* status, const mpt_tuning* tune, int use_graph,
+                                        void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   ARG(out != nullptr, "NULL out");
   return batched_common(h, roms_host, roms_dev, n_obj, omega_off, omega, out, status, tune,
-                        use_graph, nullptr, nullptr, nullptr);
+                        use_graph, nullptr, nullptr, nullptr, ws, ws_bytes);
 }
 
 extern "C" mpt_status mpt_sweep_adjoint_batched(mpt_handle h, const mpt_rom* roms_host,
                                                 const mpt_rom* roms_dev, int n_obj,
                                                 const int64_t* omega_off, const double* omega,
                                                 const double* dout, double* dL_domega,
-                                                double* sig_dsig, int32_t* status) {
+                                                double* sig_dsig, int32_t* status, void* ws,
+                                                size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   ARG(dout && dL_domega && sig_dsig, "NULL adjoint pointer");
   return batched_common(h, roms_host, roms_dev, n_obj, omega_off, omega, nullptr, status, nullptr,
-                        1, dout, dL_domega, sig_dsig);
+                        1, dout, dL_domega, sig_dsig, ws, ws_bytes);
 }

@@ -9,15 +9,22 @@ namespace mpt {
 
 int bucket_of(int M);
 
-// Material-1 part of a reduced model (C_M1 = U^H C_sigma,1 U, g_1, E_1:
-// the projections of material 1's conducting edges alone) for
-// sigma_1 dL/dsigma_1 in the adjoint sweep; dsig receives one value per
-// frequency.  All NULL: not computed.
+// Options of a single-object sweep:
+//   material-1 part of a reduced model (C_M1 = U^H C_sigma,1 U, g_1, E_1: the
+//   projections of material 1's conducting edges alone) for
+//   sigma_1 dL/dsigma_1 in the adjoint sweep; dsig receives one value per
+//   frequency.  All NULL: not computed.
+//   sigma (device, 1 value) and inv_sigma0: the model was projected at
+//   conductivity sigma0 and is evaluated at sigma, i.e. at w sigma / sigma0
+//   (it depends on w sigma only); the adjoint then returns dL/dw at the given
+//   w.  sigma NULL: no scaling.
 struct MatSens {
   const double* CM1 = nullptr;
   const double* g1 = nullptr;
   const double* E1 = nullptr;
   double* dsig = nullptr;
+  const double* sigma = nullptr;
+  double inv_sigma0 = 1.0;
 };
 
 // sweep.hip
@@ -34,6 +41,10 @@ hipError_t persistent_launch(int bucket, bool adj, const mpt_rom* roms, const in
 hipError_t reset_counters(unsigned int* c, int n, hipStream_t st);
 hipError_t sigma_reduce(const double* omega, const double* dom, const int64_t* off, int n_obj,
                         double* sig, hipStream_t st);
+// one object of n frequencies: sig[0] = sum_k omega_k dom_k, divided by
+// sigma[0] when sigma is not NULL (then dL/dsigma)
+hipError_t sigma_reduce_one(const double* omega, const double* dom, int64_t n,
+                            const double* sigma, double* sig, hipStream_t st);
 
 // select.hip
 hipError_t select_launch(const double* omega, int64_t n, const double* out, const double* snap,
@@ -67,6 +78,17 @@ size_t rcgemm_ws_size(int64_t r, int n);
 hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
                              void* ws, hipStream_t st);
 
+// cert.hip : certificate data per reference shift (Lemma 4.1):
+//   G (n_ref x (2M+3)^2) and D' (n_ref x M x M) from Y = K U, U, the scaled
+//   conductor rows Zc = sqrt(c) [w | U] (n_c x (M+3)), the conductor block's
+//   eigenpairs (Vt rows, lam), the shifts, and the assembled A0, C_M, U^H U.
+size_t cert_ws_size(int64_t N, int M, int64_t nc, int n_ref);
+hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ldU, int64_t N,
+                       int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
+                       int n_ref, const double* s_ref, const double* A0, const double* CM,
+                       const double* UhU, double eps_h, double* G, double* Dp, void* ws,
+                       hipStream_t st);
+
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
 //   by cyclic two-sided Jacobi in one workgroup; V (n x n)
 //   eigenvectors in columns, lam eigenvalues (unsorted); info[0] sweeps used
@@ -94,16 +116,21 @@ hipError_t fmm_launch(const mpt_csr& Op, const double* wf, const double* c, cons
                       const double* N0, double alpha, double* out, void* ws, hipStream_t st);
 
 // pencil.hip : Hessenberg-triangular form of (A0, C_M) and the sweep on it.
-//   Byte offsets of the parts of one object's pencil buffer.
+//   Byte offsets of the parts of one object's pencil buffer.  The stacked
+//   matrices W come last: NTs shared row tiles (K_M, C_M, then a tile with
+//   conj(g)) and, per reference shift, NTr tiles (Gxx, H, D', then a tile
+//   with the rows of G_s[Cw, XU] and G_s[Cw, CU]).
+constexpr int kPenMaxRef = 64;
 struct PencilLayout {
-  size_t H, T, f, Z, Zf, W, S, rec, Aw, total;
-  int Mp, Kp, NT;  // M rounded up to 16 / to 4; MFMA row tiles of W
+  size_t H, T, f, Z, Zf, S, rec, Aw, W;
+  int Mp, Kp, NTs, NTr;  // M rounded up to 16 / to 4; MFMA row tiles of W
 };
 __host__ __device__ inline PencilLayout pencil_layout(int M) {
   PencilLayout L;
   L.Mp = (M + 15) / 16 * 16;
   L.Kp = (M + 3) / 4 * 4;
-  L.NT = 4 * (L.Mp / 16) + 1;
+  L.NTs = 2 * (L.Mp / 16) + 1;
+  L.NTr = 3 * (L.Mp / 16) + 1;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -116,22 +143,31 @@ __host__ __device__ inline PencilLayout pencil_layout(int M) {
   L.f = take((size_t)3 * M * 16);
   L.Z = take(mm);
   L.Zf = take((size_t)(L.Mp / 16) * (L.Kp / 4) * 64 * 16);
-  L.W = take((size_t)L.NT * (L.Kp / 4) * 64 * 16);
-  L.S = take(27 * 8);
+  L.S = take((18 + 10 * (size_t)kPenMaxRef) * 8);  // E, N0, then (s, Re G_s[w,w]) per shift
   const size_t nrot = M >= 3 ? (size_t)(M - 1) * (M - 2) / 2 : 1;
   L.rec = take(nrot * 3 * 8);
   L.Aw = take(M > 64 ? (size_t)M * (M + 1) * 16 : 16);  // reduction work copy of A (M > 64)
-  L.total = o;
+  L.W = o;
   return L;
+}
+__host__ __device__ inline size_t pencil_tile_bytes(int M) {
+  const PencilLayout L = pencil_layout(M);
+  return (size_t)(L.Kp / 4) * 64 * 16;
+}
+__host__ __device__ inline size_t pencil_total_bytes(int M, int n_ref) {
+  const PencilLayout L = pencil_layout(M);
+  return L.W + (((size_t)(L.NTs + n_ref * L.NTr) * pencil_tile_bytes(M) + 255) & ~size_t(255));
 }
 // one object of a pencil reduction: the reduced model's matrices and the
 // pencil buffer (laid out by pencil_layout(M))
 struct PencilJob {
-  int M, pad_;
+  int M, n_ref;
   const double* A0;
   const double* CM;
   const double* KM;
   const double* G;
+  const double* Dp;
+  const double* s_ref;
   const double* g;
   const double* E;
   const double* N0;
@@ -139,7 +175,7 @@ struct PencilJob {
 };
 // per-object arguments of the pencil sweep
 struct PencilArgs {
-  int M, Mp, Kp, NT;
+  int M, Mp, Kp, NTs, NTr, n_ref;
   const double2* H;
   const double2* T;
   const double2* f;
@@ -152,7 +188,7 @@ PencilArgs pencil_args(const mpt_pencil& pen);
 // jobs == nullptr: the single job `one`; else n_jobs jobs from the device
 // array (maxM bounds their M)
 hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
-                                hipStream_t st);
+                                int maxRef, hipStream_t st);
 // items == nullptr: one object (P) over omega[0, n); else n_items work items
 // (object, first omega, count <= 16, -) of objects with segment width L
 hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,

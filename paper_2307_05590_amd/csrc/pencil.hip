@@ -21,9 +21,12 @@
 //      adjacent columns, the back substitution interleaved with it, then the
 //      column transforms applied to the solution (a chain over the lanes);
 //   2. a = Z y for the 48 solutions of the batch, then the products W A of the
-//      stacked matrices W = [K_M; C_M; A0; G_cc; conj(g); F] (4 Mp + 16 rows)
-//      with them, on FP64 MFMA; each output tile is contracted at once with
-//      the solutions (the quadratic forms);
+//      stacked matrices with them, on FP64 MFMA: the shared W = [K_M; C_M;
+//      conj(g)] and, for each reference shift used by a frequency of the
+//      batch, W_s = [Gxx; H; D'; B; F] (blocks of the residual Gram G_s of
+//      Lemma 4.1 and the defect form); each output tile is contracted at once
+//      with the solutions (the quadratic forms), the tiles of a shift only for
+//      the frequencies that use it;
 //   3. one thread per frequency combines the sums into R~, I and Delta.
 #include "device_util.h"
 #include "kernels.h"
@@ -516,10 +519,12 @@ __global__ __launch_bounds__(128) void k_pencil_z(PencilJob one, const PencilJob
 }
 
 // ------------------------------------------- stacked matrices for MFMA
-// blockIdx.x = 0..3: K_M, C_M, A0, G_cc into rows b Mp .. of W; blockIdx.x =
-// 4: the last tile of W (rows conj(g_i) and F_i = G[i][c block]) and the
-// 3 x 3 constants (Re G_ee, E, N0).  W is stored in MFMA A-fragment order:
+// W is stored in MFMA A-fragment order, one 16-row tile after the other:
 // W_frag[(tile * Kp/4 + kk) * 64 + l] = W[16 tile + l % 16][4 kk + l / 16].
+// blockIdx.x = 0, 1: K_M, C_M (shared tiles); 2: the shared last tile (rows
+// conj(g_i)) and the constants (E, N0, per shift s and Re G_s[w, w]);
+// 3 + 4 k + m: shift k, m = 0..2 the blocks Gxx = G_s[XU, XU], H = G_s[CU, CU]
+// and D'_s, m = 3 its last tile (rows G_s[Cw_i, XU], then G_s[Cw_i, CU]).
 __device__ __forceinline__ size_t wfrag_index(int row, int col, int Kp) {
   const int rt = row >> 4, kk = col >> 2;
   const int l = (row & 15) + 16 * (col & 3);
@@ -531,45 +536,67 @@ __global__ __launch_bounds__(256) void k_pencil_layout(PencilJob one,
   const PencilJob J = jobs ? jobs[blockIdx.y] : one;
   const int M = J.M;
   const PencilLayout Lo = pencil_layout(M);
-  const int Mp = Lo.Mp, Kp = Lo.Kp;
+  const int Mp = Lo.Mp, Kp = Lo.Kp, tpb = Mp / 16;
+  const int b = blockIdx.x;
+  if (b >= 3 + 4 * J.n_ref) return;
   const double2* KM = reinterpret_cast<const double2*>(J.KM);
   const double2* CM = reinterpret_cast<const double2*>(J.CM);
-  const double2* A0 = reinterpret_cast<const double2*>(J.A0);
-  const double2* G = reinterpret_cast<const double2*>(J.G);
   const double2* g = reinterpret_cast<const double2*>(J.g);
-  const double* E = J.E;
-  const double* N0 = J.N0;
   double2* W = reinterpret_cast<double2*>(J.base + Lo.W);
   double* S = reinterpret_cast<double*>(J.base + Lo.S);
-  const int tid = threadIdx.x, b = blockIdx.x;
+  const int tid = threadIdx.x;
   const int ldG = 2 * M + 3;
-  if (b < 4) {
+  if (b < 2) {
     for (int e = tid; e < Mp * Kp; e += blockDim.x) {
       const int r = e / Kp, c = e % Kp;
       double2 v = make_double2(0.0, 0.0);
-      if (r < M && c < M) {
-        if (b == 0) v = KM[r * M + c];
-        else if (b == 1) v = CM[r * M + c];
-        else if (b == 2) v = A0[r * M + c];
-        else v = G[(size_t)(3 + M + r) * ldG + 3 + M + c];
-      }
+      if (r < M && c < M) v = b == 0 ? KM[r * M + c] : CM[r * M + c];
       W[wfrag_index(b * Mp + r, c, Kp)] = v;
     }
-  } else {
+  } else if (b == 2) {
     for (int e = tid; e < 16 * Kp; e += blockDim.x) {
       const int q = e / Kp, c = e % Kp;
-      double2 v = make_double2(0.0, 0.0);
-      if (c < M) {
-        if (q < 3) v = cconj(g[q * M + c]);                            // g_q^H a = conj(g_q) . a
-        else if (q < 6) v = G[(size_t)(q - 3) * ldG + 3 + M + c];      // (F a)_i
-      }
-      W[wfrag_index(4 * Mp + q, c, Kp)] = v;
+      const double2 v = (c < M && q < 3) ? cconj(g[q * M + c]) : make_double2(0.0, 0.0);
+      W[wfrag_index(2 * Mp + q, c, Kp)] = v;  // g_q^H a = conj(g_q) . a
     }
     if (tid < 9) {
-      S[tid] = G[(size_t)(tid / 3) * ldG + tid % 3].x;
-      S[9 + tid] = E[tid];
-      S[18 + tid] = N0[tid];
+      S[tid] = J.E[tid];
+      S[9 + tid] = J.N0[tid];
     }
+    for (int k = tid; k < J.n_ref; k += blockDim.x) {
+      const double2* G = reinterpret_cast<const double2*>(J.G) + (size_t)k * ldG * ldG;
+      S[18 + 10 * k] = J.s_ref[k];
+      for (int t = 0; t < 9; ++t) S[18 + 10 * k + 1 + t] = G[(size_t)(t / 3) * ldG + t % 3].x;
+    }
+  } else {
+    const int k = (b - 3) / 4, m = (b - 3) % 4;
+    const double2* G = reinterpret_cast<const double2*>(J.G) + (size_t)k * ldG * ldG;
+    const double2* Dq = reinterpret_cast<const double2*>(J.Dp) + (size_t)k * M * M;
+    // first row of shift k's tiles (rows of 16 per tile)
+    const int row0 = (Lo.NTs + k * Lo.NTr) * 16;
+    if (m < 3) {
+      for (int e = tid; e < Mp * Kp; e += blockDim.x) {
+        const int r = e / Kp, c = e % Kp;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < M && c < M) {
+          if (m == 0) v = G[(size_t)(3 + r) * ldG + 3 + c];
+          else if (m == 1) v = G[(size_t)(3 + M + r) * ldG + 3 + M + c];
+          else v = Dq[r * M + c];
+        }
+        W[wfrag_index(row0 + m * Mp + r, c, Kp)] = v;
+      }
+    } else {
+      for (int e = tid; e < 16 * Kp; e += blockDim.x) {
+        const int q = e / Kp, c = e % Kp;
+        double2 v = make_double2(0.0, 0.0);
+        if (c < M) {
+          if (q < 3) v = G[(size_t)q * ldG + 3 + c];              // (B a)_q
+          else if (q < 6) v = G[(size_t)(q - 3) * ldG + 3 + M + c];  // (F a)_q
+        }
+        W[wfrag_index(row0 + 3 * Mp + q, c, Kp)] = v;
+      }
+    }
+    (void)tpb;
   }
 }
 
@@ -583,7 +610,7 @@ static size_t z_lds(int M) {
 }
 
 hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
-                                hipStream_t st) {
+                                int maxRef, hipStream_t st) {
   // LDS for the largest requirement among M <= maxM (not monotonic at kPenLdsM)
   const int Ml = maxM < kPenLdsM ? maxM : kPenLdsM;
   size_t lds1 = reduce_lds(Ml), lds2 = z_lds(Ml);
@@ -601,7 +628,7 @@ hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int
   hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(maxM > 64 ? 128 : 64), lds2, st, one, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pencil_layout, dim3(5, n_jobs), dim3(256), 0, st, one, jobs);
+  hipLaunchKernelGGL(k_pencil_layout, dim3(3 + 4 * maxRef, n_jobs), dim3(256), 0, st, one, jobs);
   return hipGetLastError();
 }
 
@@ -666,11 +693,15 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
     b0 = (int64_t)blockIdx.x * kPenBatch;
     cnt = (int)(n - b0 < kPenBatch ? n - b0 : kPenBatch);
   }
-  const int M = P.M, Kp = P.Kp, NT = P.NT;
+  const int M = P.M, Kp = P.Kp, NTs = P.NTs, NTr = P.NTr;
+  const int tpb0 = P.Mp / 16;
   double2* sY = lds;                                                  // [3][Kp][16]
-  double2* sEt = sY + 3 * Kp * kPenBatch;                             // [3][6][16]
-  double* sPart = reinterpret_cast<double*>(sEt + 18 * kPenBatch);    // [NT][6][16]
-  int* sStat = reinterpret_cast<int*>(sPart + (size_t)NT * 6 * kPenBatch);
+  double2* sEt = sY + 3 * Kp * kPenBatch;                             // [3][12][16]
+  double* sPart = reinterpret_cast<double*>(sEt + 36 * kPenBatch);    // [5 tpb][6][16]
+  int* sStat = reinterpret_cast<int*>(sPart + (size_t)5 * tpb0 * 6 * kPenBatch);
+  int* sRef = sStat + kPenBatch;   // reference shift of each frequency
+  int* sList = sRef + kPenBatch;   // the distinct shifts of the batch, ascending
+  int* sNList = sList + kPenBatch;
   const int tid = threadIdx.x, wl = __lane_id(), wave = tid >> 6;
   const int ll = wl & (L - 1), base = wl - ll;
   constexpr int kSegs = 64 / L;
@@ -841,7 +872,27 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
               (valid && row < M) ? y[sl][i] : make_double2(0.0, 0.0);
       }
     }
-    if (ll == 0) sStat[wloc] = bad ? 1 : 0;
+    if (ll == 0) {
+      sStat[wloc] = bad ? 1 : 0;
+      // reference shift: the largest s_k <= w (s_0 = 0)
+      int kr = 0;
+      for (int k = 1; k < P.n_ref; ++k)
+        if (P.S[18 + 10 * k] <= om) kr = k;
+      sRef[wloc] = valid ? kr : -1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int nl = 0, last = -1;
+    for (;;) {  // ascending distinct shifts of the valid frequencies
+      int nxt = 1 << 30;
+      for (int w = 0; w < cnt; ++w)
+        if (sRef[w] > last && sRef[w] < nxt) nxt = sRef[w];
+      if (nxt == (1 << 30)) break;
+      sList[nl++] = nxt;
+      last = nxt;
+    }
+    *sNList = nl;
   }
   __syncthreads();
 
@@ -885,8 +936,28 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
     __syncthreads();
   }
 
-  // ---- 2b. MFMA products with the stacked matrices, contracted at once ----
-  for (int rt = wave; rt < NT; rt += 4) {
+  // ---- 2b. MFMA products with the stacked matrices, contracted at once.
+  // Jobs: the NTs shared tiles, then NTr tiles for each shift of the batch;
+  // a shift's results are kept only for the frequencies that use it. --------
+  const int nlist = *sNList;
+  const int njobs = NTs + nlist * NTr;
+  for (int job = wave; job < njobs; job += 4) {
+    int rt, blk0, kr = -1;  // W tile, first quadratic-form block of its part
+    bool last;
+    if (job < NTs) {
+      rt = job;
+      last = job == NTs - 1;
+      blk0 = 0;
+    } else {
+      const int u = (job - NTs) / NTr, t = (job - NTs) % NTr;
+      kr = sList[u];
+      rt = NTs + kr * NTr + t;
+      last = t == NTr - 1;
+      blk0 = 2 * tpb;  // Gxx, H, D' after K_M, C_M
+    }
+    const int tloc = job < NTs ? job : (job - NTs) % NTr;  // tile within its part
+    const int col = wl & 15;
+    const bool keep = kr < 0 || (col < cnt && sRef[col] == kr);
     double4_t ar[3], ai[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -905,9 +976,9 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
         ai[j] = mfma(w.y, yv.x, ai[j]);
       }
     }
-    if (rt < NT - 1) {
+    if (!last) {
       // Re y_i^H (P y_j) for the six pairs i <= j, rows of this tile
-      const int row0 = (rt % tpb) * 16;
+      const int row0 = (tloc % tpb) * 16;
       double part[6];
 #pragma unroll
       for (int p = 0; p < 6; ++p) part[p] = 0.0;
@@ -926,20 +997,22 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
           }
         }
       }
+      const int sb = blk0 + tloc;  // slot block: blk * tpb + tile
 #pragma unroll
       for (int p = 0; p < 6; ++p) {
         double s = part[p] + other16(part[p], wl);
         s = s + other32(s, wl);
-        if (wl < 16) sPart[(rt * 6 + p) * kPenBatch + wl] = s;
+        if (wl < 16 && keep) sPart[(sb * 6 + p) * kPenBatch + wl] = s;
       }
-    } else {
+    } else if (keep) {
+      const int rb = kr < 0 ? 0 : 6;  // rows of sEt: shared tile, then the shift's
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         const int row = (wl >> 4) + 4 * v;
         if (row < 6) {
 #pragma unroll
           for (int j = 0; j < 3; ++j)
-            sEt[(j * 6 + row) * kPenBatch + (wl & 15)] = make_double2(ar[j][v], ai[j][v]);
+            sEt[(j * 12 + rb + row) * kPenBatch + (wl & 15)] = make_double2(ar[j][v], ai[j][v]);
         }
       }
     }
@@ -951,37 +1024,45 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
     const int w = tid;
     const int64_t gi = b0 + w;
     const double om = omega[gi];
-    double Q[4][6];
+    double Q[5][6];  // K_M, C_M, Gxx, H, D'
 #pragma unroll
-    for (int blk = 0; blk < 4; ++blk)
+    for (int blk = 0; blk < 5; ++blk)
 #pragma unroll
       for (int p = 0; p < 6; ++p) {
         double s = 0.0;
         for (int tb = 0; tb < tpb; ++tb) s += sPart[((blk * tpb + tb) * 6 + p) * kPenBatch + w];
         Q[blk][p] = s;
       }
-    auto GA = [&](int i, int j) { return sEt[(j * 6 + i) * kPenBatch + w]; };      // g_i^H a_j
-    auto FA = [&](int i, int j) { return sEt[(j * 6 + 3 + i) * kPenBatch + w]; };  // (F a_j)_i
-    const double* Wee = P.S;
-    const double* E = P.S + 9;
-    const double* N0 = P.S + 18;
+    auto GA = [&](int i, int j) { return sEt[(j * 12 + i) * kPenBatch + w]; };      // g_i^H a_j
+    auto BA = [&](int i, int j) { return sEt[(j * 12 + 6 + i) * kPenBatch + w]; };  // (B a_j)_i
+    auto FA = [&](int i, int j) { return sEt[(j * 12 + 9 + i) * kPenBatch + w]; };  // (F a_j)_i
+    const double* E = P.S;
+    const double* N0 = P.S + 9;
+    const double* Wee = P.S + 18 + 10 * sRef[w] + 1;
     const double a3 = P.alpha * P.alpha * P.alpha;
     double* o = out + gi * 18;
+    double nn[3], ee[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ee[i] = sqrt(fmax(Q[4][pair_of(i, i)], 0.0));
+    double crd[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int q = pair_of(i, i);
+      crd[i] = om * om * (Wee[4 * i] + 2.0 * FA(i, i).x + Q[3][q]) - 2.0 * om * BA(i, i).y +
+               Q[2][q];
+      nn[i] = sqrt(fmax(crd[i], 0.0));
+    }
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       const int i = kPairI[p], j = kPairJ[p];
       o[p] = N0[3 * i + j] - 0.25 * a3 * Q[0][p];
       o[6 + p] = 0.25 * a3 * om * (E[3 * i + j] + Q[1][p] + GA(i, j).x + GA(j, i).x);
-      double cr[3];
-#pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int a = u == 0 ? i : (u == 1 ? j : i);
-        const int bb = u == 0 ? i : j;
-        const int q = pair_of(a, bb);
-        cr[u] = om * om * (Wee[3 * a + bb] + FA(a, bb).x + FA(bb, a).x + Q[3][q]) -
-                om * (GA(a, bb).y + GA(bb, a).y) + Q[2][q];
-      }
-      o[12 + p] = a3 / (8.0 * P.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
+      // Re c_ij = w^2 [W_ij + Re(F a_j)_i + Re(F a_i)_j + Re a_i^H H a_j]
+      //           - w [Im (B a_j)_i + Im (B a_i)_j] + Re a_i^H Gxx a_j
+      const double cij = om * om * (Wee[3 * i + j] + FA(i, j).x + FA(j, i).x + Q[3][p]) -
+                         om * (BA(i, j).y + BA(j, i).y) + Q[2][p];
+      o[12 + p] = a3 / (8.0 * P.alpha_lb) * (2.0 * crd[i] + 2.0 * crd[j] - 2.0 * cij) +
+                  0.25 * a3 * (nn[i] * ee[j] + nn[j] * ee[i]);
     }
     status[gi] = sStat[w] ? MPT_E_SINGULAR : 0;
   }
@@ -1002,7 +1083,9 @@ PencilArgs pencil_args(const mpt_pencil& pen) {
   P.M = pen.M;
   P.Mp = Lo.Mp;
   P.Kp = Lo.Kp;
-  P.NT = Lo.NT;
+  P.NTs = Lo.NTs;
+  P.NTr = Lo.NTr;
+  P.n_ref = pen.n_ref;
   P.H = reinterpret_cast<const double2*>(base + Lo.H);
   P.T = reinterpret_cast<const double2*>(base + Lo.T);
   P.f = reinterpret_cast<const double2*>(base + Lo.f);
@@ -1014,15 +1097,16 @@ PencilArgs pencil_args(const mpt_pencil& pen) {
   return P;
 }
 
-static size_t sweep_lds(int Kp, int NT) {
-  return ((size_t)3 * Kp * kPenBatch + 18 * kPenBatch) * sizeof(double2) +
-         (size_t)NT * 6 * kPenBatch * sizeof(double) + kPenBatch * sizeof(int);
+// Kp: rows of the solutions; tpb: 16-row tiles per M x M block
+static size_t sweep_lds(int Kp, int tpb) {
+  return ((size_t)3 * Kp * kPenBatch + 36 * kPenBatch) * sizeof(double2) +
+         (size_t)5 * tpb * 6 * kPenBatch * sizeof(double) + (3 * kPenBatch + 1) * sizeof(int);
 }
 
 hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,
                                double* a_out, int32_t* status, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sweep_lds(P.Kp, P.NT);
+  const size_t lds = sweep_lds(P.Kp, P.Mp / 16);
   const dim3 grid((unsigned)((n + kPenBatch - 1) / kPenBatch)), block(256);
   const PencilArgs* no = nullptr;
   const int4* ni = nullptr;
@@ -1045,8 +1129,8 @@ hipError_t pencil_sweep_items_launch(int L, const PencilArgs* objs, const int4* 
                                      int n_items, const double* omega, double* out,
                                      int32_t* status, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  // LDS for the largest object of the bucket: Kp <= bucket, NT <= bucket / 4 + 1
-  const size_t lds = sweep_lds(L, L / 4 + 1);
+  // LDS for the largest object of the bucket: Kp <= bucket, tiles <= bucket / 16
+  const size_t lds = sweep_lds(L, L / 16);
   const dim3 grid((unsigned)n_items), block(256);
   PencilArgs none{};
   double* no_a = nullptr;

@@ -17,7 +17,8 @@ __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t b
 }
 }  // namespace
 
-// one block per interval j: [snap[j], snap[j+1]) (the last one closed)
+// one block per interval j: snap[j] < w < snap[j+1] (Algorithm 1's interval
+// without its left end, which is a snapshot already)
 __global__ __launch_bounds__(256) void k_interval_max(const double* __restrict__ omega, int64_t n,
                                                       const double* __restrict__ out,
                                                       const double* __restrict__ snap, int n_snap,
@@ -25,12 +26,11 @@ __global__ __launch_bounds__(256) void k_interval_max(const double* __restrict__
                                                       int64_t* __restrict__ arg) {
   const int j = blockIdx.x;
   const double lo = snap[j], hi = snap[j + 1];
-  const bool last = (j == n_snap - 2);
   double bv = -INFINITY;
   int64_t bi = -1;
   for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
     const double w = omega[k];
-    const bool in = (w >= lo) && (last ? (w <= hi) : (w < hi));
+    const bool in = (w > lo) && (w < hi);
     if (!in) continue;
     double d = out[18 * k + 12];
 #pragma unroll

@@ -129,4 +129,26 @@ hipError_t sigma_reduce(const double* omega, const double* dom, const int64_t* o
   return hipGetLastError();
 }
 
+// sum_k omega_k dom_k over one object (fixed order), over sigma[0] if given
+__global__ void k_sigma_reduce_one(const double* __restrict__ omega,
+                                   const double* __restrict__ dom, int64_t n,
+                                   const double* __restrict__ sigma, double* __restrict__ sig) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) acc += omega[k] * dom[k];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sig[0] = sigma ? part[0] / sigma[0] : part[0];
+}
+
+hipError_t sigma_reduce_one(const double* omega, const double* dom, int64_t n,
+                            const double* sigma, double* sig, hipStream_t st) {
+  hipLaunchKernelGGL(k_sigma_reduce_one, dim3(1), dim3(256), 0, st, omega, dom, n, sigma, sig);
+  return hipGetLastError();
+}
+
 }  // namespace mpt

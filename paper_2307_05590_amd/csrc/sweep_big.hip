@@ -7,9 +7,9 @@
 //     column of multipliers by wave 0, the trailing update by all waves;
 //   - forward and back substitution of the three right-hand sides by wave 0
 //     (wave-level LDS ordering, no workgroup barriers);
-//   - the four reduced mat-vecs with one thread per (row, vector), reading
+//   - the five reduced mat-vecs with one thread per (row, vector), reading
 //     the Hermitian matrices column-wise (coalesced) and conjugating;
-//   - the 60 quadratic-form sums in fixed order, one thread per slot.
+//   - the 54 quadratic-form sums in fixed order, one thread per slot.
 #include "device_util.h"
 #include "kernels.h"
 
@@ -47,11 +47,16 @@ __global__ __launch_bounds__(kBigThreads) void k_sweep_big(const mpt_rom R,
   const double2* CM = reinterpret_cast<const double2*>(R.CM);
   const double2* KM = reinterpret_cast<const double2*>(R.KM);
   const double2* gv = reinterpret_cast<const double2*>(R.g);
-  const double2* G = reinterpret_cast<const double2*>(R.G);
   const double a3 = R.alpha * R.alpha * R.alpha;
 
   for (int64_t k_om = blockIdx.x; k_om < n; k_om += gridDim.x) {
     const double om = omega[k_om];
+    // reference shift of this frequency: the largest s_ref[k] <= om
+    int kref = 0;
+    for (int j = 1; j < R.n_ref; ++j)
+      if (R.s_ref[j] <= om) kref = j;
+    const double2* G = reinterpret_cast<const double2*>(R.G) + (size_t)kref * ldG * ldG;
+    const double2* Dq = reinterpret_cast<const double2*>(R.Dp) + (size_t)kref * M * M;
     // ---- A = A0 - i w C_M (row r = conj of column r), rhs i w g_i -------
     for (int e = tid; e < M * M; e += kBigThreads) {
       const int j = e / M, r = e % M;  // consecutive threads: consecutive r
@@ -149,29 +154,34 @@ __global__ __launch_bounds__(kBigThreads) void k_sweep_big(const mpt_rom R,
       }
     }
     __syncthreads();
-    // ---- mat-vecs: (K_M a_i, C_M a_i, A0 a_i, H a_i) into the A region ----
+    // ---- mat-vecs: K_M a_i, C_M a_i, Gxx a_i, H a_i, D' a_i into the A region
+    // (Gxx = G_s[XU, XU], H = G_s[CU, CU]) ----------------------------------
     double2* sKa = sA;              // [3][M]
     double2* sCa = sA + 3 * kBigMaxM;
     double2* sAa = sA + 6 * kBigMaxM;
     double2* sHa = sA + 9 * kBigMaxM;
+    double2* sDa = sA + 12 * kBigMaxM;
     for (int e = tid; e < 3 * M; e += kBigThreads) {
       const int i = e / M, r = e % M;
-      double2 ka = make_double2(0.0, 0.0), ca = ka, aa = ka, ha = ka;
+      double2 ka = make_double2(0.0, 0.0), ca = ka, aa = ka, ha = ka, da = ka;
       for (int j = 0; j < M; ++j) {
         const double2 xj = sX[i][j];
         ka = cfma(ka, cconj(KM[j * M + r]), xj);
         ca = cfma(ca, cconj(CM[j * M + r]), xj);
-        aa = cfma(aa, cconj(A0[j * M + r]), xj);
+        aa = cfma(aa, cconj(G[(size_t)(3 + j) * ldG + 3 + r]), xj);
         ha = cfma(ha, cconj(G[(size_t)(3 + M + j) * ldG + 3 + M + r]), xj);
+        da = cfma(da, cconj(Dq[j * M + r]), xj);
       }
       sKa[i * kBigMaxM + r] = ka;
       sCa[i * kBigMaxM + r] = ca;
       sAa[i * kBigMaxM + r] = aa;
       sHa[i * kBigMaxM + r] = ha;
+      sDa[i * kBigMaxM + r] = da;
     }
     __syncthreads();
-    // ---- 60 quadratic-form slots, one thread each, fixed order ----------
-    if (tid < 60) {
+    // ---- 54 quadratic-form slots (the register kernel's order), one thread
+    // each, fixed order ---------------------------------------------------
+    if (tid < 54) {
       const int sl = tid;
       double acc = 0.0;
       if (sl < 24) {
@@ -179,16 +189,24 @@ __global__ __launch_bounds__(kBigThreads) void k_sweep_big(const mpt_rom R,
         const int i = kBPi[q], j = kBPj[q];
         const double2* Y = kind == 0 ? sKa : (kind == 1 ? sCa : (kind == 2 ? sAa : sHa));
         for (int r = 0; r < M; ++r) acc += cmulc(sX[i][r], Y[j * kBigMaxM + r]).x;
-      } else if (sl < 42) {
-        const int u = (sl - 24) >> 1, i = u / 3, j = u % 3;
+      } else if (sl < 33) {  // Re g_i^H a_j
+        const int u = sl - 24, i = u / 3, j = u % 3;
         double2 s2 = make_double2(0.0, 0.0);
         for (int r = 0; r < M; ++r) s2 = cfmac(s2, gv[i * M + r], sX[j][r]);
-        acc = ((sl - 24) & 1) ? s2.y : s2.x;
-      } else {
-        const int u = (sl - 42) >> 1, i = u / 3, j = u % 3;
+        acc = s2.x;
+      } else if (sl < 42) {  // Re (F a_j)_i
+        const int u = sl - 33, i = u / 3, j = u % 3;
         double2 s2 = make_double2(0.0, 0.0);
         for (int r = 0; r < M; ++r) s2 = cfma(s2, G[(size_t)i * ldG + 3 + M + r], sX[j][r]);
-        acc = ((sl - 42) & 1) ? s2.y : s2.x;
+        acc = s2.x;
+      } else if (sl < 51) {  // Im (B a_j)_i
+        const int u = sl - 42, i = u / 3, j = u % 3;
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int r = 0; r < M; ++r) s2 = cfma(s2, G[(size_t)i * ldG + 3 + r], sX[j][r]);
+        acc = s2.y;
+      } else {  // Re a_i^H D' a_i
+        const int i = sl - 51;
+        for (int r = 0; r < M; ++r) acc += cmulc(sX[i][r], sDa[i * kBigMaxM + r]).x;
       }
       sQ[sl] = acc;
     }
@@ -200,8 +218,7 @@ __global__ __launch_bounds__(kBigThreads) void k_sweep_big(const mpt_rom R,
       if (po < 6) {
         v = R.N0[3 * i + j] - 0.25 * a3 * sQ[pp];
       } else if (po < 12) {
-        v = 0.25 * a3 * om *
-            (R.E[3 * i + j] + sQ[6 + pp] + sQ[24 + 2 * (3 * i + j)] + sQ[24 + 2 * (3 * j + i)]);
+        v = 0.25 * a3 * om * (R.E[3 * i + j] + sQ[6 + pp] + sQ[24 + 3 * i + j] + sQ[24 + 3 * j + i]);
       } else {
         double cr[3];
 #pragma unroll
@@ -210,10 +227,13 @@ __global__ __launch_bounds__(kBigThreads) void k_sweep_big(const mpt_rom R,
           const int b = t == 0 ? i : (t == 1 ? j : j);
           const int q = bpair(a, b);
           const double Wab = G[(size_t)a * ldG + b].x;
-          cr[t] = om * om * (Wab + sQ[42 + 2 * (3 * a + b)] + sQ[42 + 2 * (3 * b + a)] + sQ[18 + q]) -
-                  om * (sQ[24 + 2 * (3 * a + b) + 1] + sQ[24 + 2 * (3 * b + a) + 1]) + sQ[12 + q];
+          cr[t] = om * om * (Wab + sQ[33 + 3 * a + b] + sQ[33 + 3 * b + a] + sQ[18 + q]) -
+                  om * (sQ[42 + 3 * a + b] + sQ[42 + 3 * b + a]) + sQ[12 + q];
         }
-        v = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
+        const double ni = sqrt(fmax(cr[0], 0.0)), nj = sqrt(fmax(cr[1], 0.0));
+        const double ei = sqrt(fmax(sQ[51 + i], 0.0)), ej = sqrt(fmax(sQ[51 + j], 0.0));
+        v = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]) +
+            0.25 * a3 * (ni * ej + nj * ei);
       }
       out[18 * k_om + po] = v;
     }
@@ -233,8 +253,8 @@ hipError_t sweep_big_launch(const mpt_rom& R, const double* omega, int64_t n, do
                             double* a_out, int32_t* status, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (R.M > kBigMaxM) return hipErrorInvalidValue;
-  // the mat-vec results (12 vectors of kBigMaxM) reuse the matrix region
-  const size_t lds = std::max(sweep_big_lds_bytes(R.M), (size_t)12 * kBigMaxM * sizeof(double2));
+  // the mat-vec results (15 vectors of kBigMaxM) reuse the matrix region
+  const size_t lds = std::max(sweep_big_lds_bytes(R.M), (size_t)15 * kBigMaxM * sizeof(double2));
   // one workgroup per CU fits (about 160 KB of LDS at M = 96); a grid-stride
   // loop over the frequencies
   const int64_t groups = std::min<int64_t>(n, 1024);

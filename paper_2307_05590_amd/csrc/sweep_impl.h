@@ -18,13 +18,27 @@ namespace mpt {
 
 namespace {
 
-// Slots of the reduce-scatter (64 per frequency).
+// Slots of the reduce-scatter (64 per frequency).  G_s blocks (Lemma 4.1,
+// unknowns [C w | X U | C U]): Gxx = G_s[XU, XU], H = G_s[CU, CU],
+// F = G_s[Cw, CU], B = G_s[Cw, XU], W = G_s[Cw, Cw]; D' the defect form.
 constexpr int kKQ = 0;    // Re a_i^H K_M a_j         (6 pairs)
 constexpr int kCQ = 6;    // Re a_i^H C_M a_j         (6)
-constexpr int kAQ = 12;   // Re a_i^H A0 a_j          (6)
+constexpr int kAQ = 12;   // Re a_i^H Gxx a_j         (6)
 constexpr int kHQ = 18;   // Re a_i^H H a_j           (6)
-constexpr int kGA = 24;   // g_i^H a_j  (re, im)      (9 complex)
-constexpr int kFA = 42;   // (F a_j)_i  (re, im)      (9 complex)
+constexpr int kGA = 24;   // Re g_i^H a_j             (9)
+constexpr int kFA = 33;   // Re (F a_j)_i             (9)
+constexpr int kBA = 42;   // Im (B a_j)_i             (9)
+constexpr int kDQ = 51;   // Re a_i^H D' a_i          (3)
+constexpr int kSlots = 54;
+
+// index of the reference shift of frequency om: the largest k with
+// s_ref[k] <= om (s_ref ascending, s_ref[0] = 0)
+__device__ __forceinline__ int ref_of(const mpt_rom& R, double om) {
+  int k = 0;
+  for (int j = 1; j < R.n_ref; ++j)
+    if (R.s_ref[j] <= om) k = j;
+  return k;
+}
 
 __device__ __constant__ int kPi[6] = {0, 0, 0, 1, 1, 2};
 __device__ __constant__ int kPj[6] = {0, 1, 2, 1, 2, 2};
@@ -135,6 +149,8 @@ __device__ __forceinline__ double seg_rs16(double (&v)[16], int wl) {
 //           with ms.CM1 set, also dsig (1 double) = sigma_1 dL/dsigma_1.
 //   red_lds: 64 doubles private to the segment.
 //   valid:  false for a padding segment (computes, writes nothing).
+//   out may be NULL (adjoint only); dscale multiplies dom (the chain rule of
+//   a frequency scaling applied by the caller).
 template <int MAXM, bool ADJ>
 __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, const bool valid,
                                             double* __restrict__ out, double* __restrict__ a_out,
@@ -142,7 +158,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
                                             const double* __restrict__ dout,
                                             double* __restrict__ dom, double2* lds_lu,
                                             double* red_lds, const MatSens& ms,
-                                            double* __restrict__ dsig) {
+                                            double* __restrict__ dsig, double dscale = 1.0) {
   constexpr int L = SegOf<MAXM>::L;
   const int wl = __lane_id();
   const int ll = wl & (L - 1);   // lane within the segment
@@ -153,8 +169,10 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   const double2* CM = reinterpret_cast<const double2*>(R.CM);
   const double2* KM = reinterpret_cast<const double2*>(R.KM);
   const double2* gv = reinterpret_cast<const double2*>(R.g);
-  const double2* G = reinterpret_cast<const double2*>(R.G);
   const int ldG = 2 * M + 3;
+  const int kref = ref_of(R, om);
+  const double2* G = reinterpret_cast<const double2*>(R.G) + (size_t)kref * ldG * ldG;
+  const double2* Dq = reinterpret_cast<const double2*>(R.Dp) + (size_t)kref * M * M;
 
   // ---- row `ll` of A(w) = A0 - i w C_M and r_i = i w g_i ---------------
   double2 A[MAXM];
@@ -260,13 +278,14 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   }
 
   // ---- reduced matrix-vector products, lane r holds row r -----------------
-  double2 Ka[3], Ca[3], Aa[3], Ha[3];
+  double2 Ka[3], Ca[3], Aa[3], Ha[3], Da[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    Ka[i] = Ca[i] = Aa[i] = Ha[i] = make_double2(0.0, 0.0);
+    Ka[i] = Ca[i] = Aa[i] = Ha[i] = Da[i] = make_double2(0.0, 0.0);
   }
-  // K_M, C_M, A0 and H = G[c, c] are Hermitian: lane ll reads column ll
+  // K_M, C_M, Gxx, H and D' are Hermitian: lane ll reads column ll
   // (coalesced across lanes) and conjugates
+  const double2* Xcol = G + (size_t)3 * ldG + 3 + ll;
   const double2* Hcol = G + (size_t)(3 + M) * ldG + (3 + M) + ll;
 #pragma unroll 4
   for (int j = 0; j < M; ++j) {
@@ -276,24 +295,28 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     if (act) {
       const double2 kk = cconj(KM[j * M + ll]);
       const double2 cc = cconj(CM[j * M + ll]);
-      const double2 a0 = cconj(A0[j * M + ll]);
+      const double2 gx = cconj(Xcol[(size_t)j * ldG]);
       const double2 hh = cconj(Hcol[(size_t)j * ldG]);
+      const double2 dd = cconj(Dq[j * M + ll]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         Ka[i] = cfma(Ka[i], kk, aj[i]);
         Ca[i] = cfma(Ca[i], cc, aj[i]);
-        Aa[i] = cfma(Aa[i], a0, aj[i]);
+        Aa[i] = cfma(Aa[i], gx, aj[i]);
         Ha[i] = cfma(Ha[i], hh, aj[i]);
+        Da[i] = cfma(Da[i], dd, aj[i]);
       }
     }
   }
 
-  // ---- quadratic forms: per-lane partials of 60 slots, reduced in four
+  // ---- quadratic forms: per-lane partials of 54 slots, reduced in four
   // groups of 16 (segment reduce-scatter), totals to red_lds --------------
-  double2 Fi[3];
+  double2 Fi[3], Bi[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i) {
     Fi[i] = act ? G[(size_t)i * ldG + 3 + M + ll] : make_double2(0.0, 0.0);
+    Bi[i] = act ? G[(size_t)i * ldG + 3 + ll] : make_double2(0.0, 0.0);
+  }
   auto partial = [&](int sl) -> double {
     if (sl < kGA) {
       const int q = sl % 6, kind = sl / 6;
@@ -303,14 +326,20 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
       return cmulc(x[i], y).x;
     }
     if (sl < kFA) {
-      const int u = (sl - kGA) >> 1, i = u / 3, j = u % 3;
-      const double2 ga = cmulc(gl[i], x[j]);
-      return ((sl - kGA) & 1) ? ga.y : ga.x;
+      const int u = sl - kGA, i = u / 3, j = u % 3;
+      return cmulc(gl[i], x[j]).x;
     }
-    if (sl < 60) {
-      const int u = (sl - kFA) >> 1, i = u / 3, j = u % 3;
-      const double2 fa = cmul(Fi[i], x[j]);
-      return ((sl - kFA) & 1) ? fa.y : fa.x;
+    if (sl < kBA) {
+      const int u = sl - kFA, i = u / 3, j = u % 3;
+      return cmul(Fi[i], x[j]).x;
+    }
+    if (sl < kDQ) {
+      const int u = sl - kBA, i = u / 3, j = u % 3;
+      return cmul(Bi[i], x[j]).y;
+    }
+    if (sl < kSlots) {
+      const int i = sl - kDQ;
+      return cmulc(x[i], Da[i]).x;
     }
     return 0.0;
   };
@@ -341,12 +370,12 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
         myout = R.N0[3 * i + j] - 0.25 * a3 * red_lds[kKQ + pp];
       } else if (po < 12) {
         myout = 0.25 * a3 * om *
-                (R.E[3 * i + j] + red_lds[kCQ + pp] + red_lds[kGA + 2 * (3 * i + j)] +
-                 red_lds[kGA + 2 * (3 * j + i)]);
+                (R.E[3 * i + j] + red_lds[kCQ + pp] + red_lds[kGA + 3 * i + j] +
+                 red_lds[kGA + 3 * j + i]);
         iout = myout;
       } else {
         // Re c_ab = w^2 [W_ab + Re(F a_b)_a + Re(F a_a)_b + Re a_a^H H a_b]
-        //           - w [Im g_a^H a_b + Im g_b^H a_a] + Re a_a^H A0 a_b
+        //           - w [Im (B a_b)_a + Im (B a_a)_b] + Re a_a^H Gxx a_b
         double cr[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -354,14 +383,17 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
           const int bb = t == 0 ? i : (t == 1 ? j : j);
           const int q = pair_index(a, bb);
           const double W = G[(size_t)a * ldG + bb].x;
-          cr[t] = om * om * (W + red_lds[kFA + 2 * (3 * a + bb)] + red_lds[kFA + 2 * (3 * bb + a)] +
+          cr[t] = om * om * (W + red_lds[kFA + 3 * a + bb] + red_lds[kFA + 3 * bb + a] +
                              red_lds[kHQ + q]) -
-                  om * (red_lds[kGA + 2 * (3 * a + bb) + 1] + red_lds[kGA + 2 * (3 * bb + a) + 1]) +
+                  om * (red_lds[kBA + 3 * a + bb] + red_lds[kBA + 3 * bb + a]) +
                   red_lds[kAQ + q];
         }
-        myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]);
+        const double ni = sqrt(fmax(cr[0], 0.0)), nj = sqrt(fmax(cr[1], 0.0));
+        const double ei = sqrt(fmax(red_lds[kDQ + i], 0.0)), ej = sqrt(fmax(red_lds[kDQ + j], 0.0));
+        myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]) +
+                0.25 * a3 * (ni * ej + nj * ei);
       }
-      if (valid) out[po] = myout;
+      if (valid && out != nullptr) out[po] = myout;
     }
   }
   if (valid && a_out != nullptr && act) {
@@ -435,7 +467,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
     // explicit omega-dependence of I (prefactor w): sum_p tau_p I_p / w
     if (ll >= 6 && ll < 12) acc += dout[ll] * iout / om;
     const double tot = seg_sum<L>(acc);
-    if (valid && ll == 0) *dom = tot;
+    if (valid && ll == 0) *dom = tot * dscale;
     __builtin_amdgcn_wave_barrier();
 
     // ---- sigma_1 dL/dsigma_1 for the material-1 part (C_M1, g_1, E_1) of
@@ -503,15 +535,17 @@ __global__ __launch_bounds__(256) void k_sweep(const mpt_rom R, const double* __
   const int seg = __lane_id() / L;
   double2* my_lds = ADJ ? lds + ((size_t)wave * S + seg) * MAXM * (MAXM + 1) : nullptr;
   double* my_red = red + (wave * S + seg) * 64;
+  // evaluation at w sigma / sigma0 when a conductivity is given
+  const double sc = ms.sigma ? ms.sigma[0] * ms.inv_sigma0 : 1.0;
   for (int64_t k0 = ((int64_t)blockIdx.x * wpg + wave) * S; k0 < n;
        k0 += (int64_t)gridDim.x * wpg * S) {
     const int64_t k = k0 + seg;
     const bool valid = k < n;
     const int64_t kc = valid ? k : n - 1;
-    sweep_point<MAXM, ADJ>(R, omega[kc], valid, out + 18 * kc,
+    sweep_point<MAXM, ADJ>(R, omega[kc] * sc, valid, out ? out + 18 * kc : nullptr,
                            a_out ? a_out + (size_t)kc * 6 * R.M : nullptr, status + kc,
                            ADJ ? dout + 18 * kc : nullptr, ADJ ? dom + kc : nullptr, my_lds,
-                           my_red, ms, ms.dsig ? ms.dsig + kc : nullptr);
+                           my_red, ms, ms.dsig ? ms.dsig + kc : nullptr, sc);
   }
 }
 
@@ -540,7 +574,7 @@ __global__ __launch_bounds__(256) void k_sweep_persistent(
     for (int r = 0; r < w.z; r += S) {
       const bool valid = r + seg < w.z;
       const int64_t k = (int64_t)w.y + (valid ? r + seg : w.z - 1);
-      sweep_point<MAXM, ADJ>(R, omega[k], valid, out + 18 * k, nullptr, status + k,
+      sweep_point<MAXM, ADJ>(R, omega[k], valid, out ? out + 18 * k : nullptr, nullptr, status + k,
                              ADJ ? dout + 18 * k : nullptr, ADJ ? dom + k : nullptr, my_lds,
                              my_red, MatSens{}, nullptr);
     }

@@ -26,13 +26,14 @@ class _Csr(C.Structure):
 
 
 class _Rom(C.Structure):
-    _fields_ = [("M", C.c_int32), ("pad_", C.c_int32), ("KM", C.c_void_p), ("A0", C.c_void_p),
-                ("CM", C.c_void_p), ("g", C.c_void_p), ("G", C.c_void_p), ("E", C.c_void_p),
-                ("N0", C.c_void_p), ("alpha", C.c_double), ("alpha_lb", C.c_double)]
+    _fields_ = [("M", C.c_int32), ("n_ref", C.c_int32), ("KM", C.c_void_p), ("A0", C.c_void_p),
+                ("CM", C.c_void_p), ("g", C.c_void_p), ("G", C.c_void_p), ("Dp", C.c_void_p),
+                ("s_ref", C.c_void_p), ("E", C.c_void_p), ("N0", C.c_void_p),
+                ("alpha", C.c_double), ("alpha_lb", C.c_double)]
 
 
 class _Pencil(C.Structure):
-    _fields_ = [("M", C.c_int32), ("pad_", C.c_int32), ("H", C.c_void_p), ("T", C.c_void_p),
+    _fields_ = [("M", C.c_int32), ("n_ref", C.c_int32), ("H", C.c_void_p), ("T", C.c_void_p),
                 ("f", C.c_void_p), ("Z", C.c_void_p), ("W", C.c_void_p), ("S", C.c_void_p),
                 ("alpha", C.c_double), ("alpha_lb", C.c_double)]
 
@@ -61,25 +62,30 @@ def lib():
             "mpt_max_reduced_dim": ([], I32),
             "mpt_pod_basis_ws_size": ([I64, I32], S),
             "mpt_pod_basis": ([P, P, I64, I64, I32, D, I32, P, I64, P, P, P, S], I32),
-            "mpt_project_ws_size": ([I64, I32, I64], S),
-            "mpt_project": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P,
-                             P, P, P, P, P, P, P, P, P, S], I32),
+            "mpt_project_ws_size": ([I64, I32, I64, I32], S),
+            "mpt_project": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P, P, I32, P,
+                             P, P, P, P, P, P, P, P, P, P, S], I32),
             "mpt_residual_gram_ws_size": ([I64, I32], S),
             "mpt_residual_gram": ([P, P, I64, P, I64, I64, I32, P, P, S], I32),
-            "mpt_sweep_adjoint_materials": ([P, P, P, P, P, P, I64, P, P, P, P], I32),
+            "mpt_sweep_adjoint_materials_ws_size": ([I64], S),
+            "mpt_sweep_adjoint_materials": ([P, P, P, P, P, P, I64, P, P, P, P, P, S], I32),
+            "mpt_signature": ([P, P, P, I64, P, D, P, P], I32),
+            "mpt_signature_adjoint": ([P, P, P, I64, P, D, P, P, P, P], I32),
+            "mpt_select_snapshots_ws_size": ([I32], S),
+            "mpt_sweep_batched_ws_size": ([P, I32, P, P], S),
             "mpt_spmm": ([P, P, P, I64, I32, P, I64], I32),
             "mpt_sweep": ([P, P, P, I64, P, P, P], I32),
-            "mpt_select_snapshots": ([P, P, I64, P, P, I32, I32, P, P, P], I32),
-            "mpt_sweep_batched": ([P, P, P, I32, P, P, P, P, P, I32], I32),
+            "mpt_select_snapshots": ([P, P, I64, P, P, I32, I32, P, P, P, P, S], I32),
+            "mpt_sweep_batched": ([P, P, P, I32, P, P, P, P, P, I32, P, S], I32),
             "mpt_sweep_adjoint": ([P, P, P, I64, P, P, P, P], I32),
-            "mpt_sweep_adjoint_batched": ([P, P, P, I32, P, P, P, P, P, P], I32),
-            "mpt_pencil_bytes": ([I32], S),
+            "mpt_sweep_adjoint_batched": ([P, P, P, I32, P, P, P, P, P, P, P, S], I32),
+            "mpt_pencil_bytes": ([I32, I32], S),
             "mpt_pencil_reduce": ([P, P, P, S, P], I32),
             "mpt_sweep_pencil": ([P, P, P, I64, P, P, P], I32),
-            "mpt_pencil_batched_bytes": ([P, I32], S),
+            "mpt_pencil_batched_bytes": ([P, I32, P], S),
             "mpt_tensors_fmm_ws_size": ([I64, I32], S),
             "mpt_tensors_fmm": ([P, P, P, P, P, I64, I32, P, I64, P, P, I64, P, D, P, P, S], I32),
-            "mpt_select_snapshots_threshold": ([P, P, I64, P, P, I32, D, P, P, P, P], I32),
+            "mpt_select_snapshots_threshold": ([P, P, I64, P, P, I32, D, P, P, P, P, P, S], I32),
             "mpt_tensors_im_ws_size": ([I64, I64, I32], S),
             "mpt_tensors_im": ([P, P, P, P, P, P, I64, I64, I32, P, I64, P, P, I64, P, D, P, P, S],
                                I32),
@@ -173,6 +179,10 @@ class Csr:
                     self.row_blocks, 0)
 
 
+# Stability constant of Lemma 4.1 for the reference norms X + s C_sigma
+ALPHA_LB = 2.0 / (3.0 + 10.0 ** 0.5)
+
+
 @dataclass
 class Rom:
     """Reduced model of one object (device tensors, complex128 / float64)."""
@@ -182,26 +192,34 @@ class Rom:
     A0: torch.Tensor
     CM: torch.Tensor
     g: torch.Tensor  # (3, M)
-    G: torch.Tensor  # (2M+3, 2M+3)
+    G: torch.Tensor  # (n_ref, 2M+3, 2M+3): residual Gram per reference shift
+    Dp: torch.Tensor  # (n_ref, M, M): conjugation-defect form per shift
+    s_ref: torch.Tensor  # (n_ref,) ascending, s_ref[0] = 0
     E: torch.Tensor  # (3, 3)
     N0: torch.Tensor  # (3, 3)
     alpha: float
-    alpha_lb: float = 1.0
+    alpha_lb: float = ALPHA_LB
+
+    @property
+    def n_ref(self):
+        return int(self.s_ref.numel())
 
     def struct(self):
-        _dev_check(self.KM, self.A0, self.CM, self.g, self.G, self.E, self.N0)
-        return _Rom(self.M, 0, _ptr(self.KM), _ptr(self.A0), _ptr(self.CM), _ptr(self.g),
-                    _ptr(self.G), _ptr(self.E), _ptr(self.N0), float(self.alpha),
-                    float(self.alpha_lb))
+        _dev_check(self.KM, self.A0, self.CM, self.g, self.G, self.Dp, self.s_ref, self.E, self.N0)
+        return _Rom(self.M, self.n_ref, _ptr(self.KM), _ptr(self.A0), _ptr(self.CM), _ptr(self.g),
+                    _ptr(self.G), _ptr(self.Dp), _ptr(self.s_ref), _ptr(self.E), _ptr(self.N0),
+                    float(self.alpha), float(self.alpha_lb))
 
     @classmethod
-    def from_host(cls, d, alpha, alpha_lb=1.0, device="cuda"):
-        """From host arrays: KM, A0, CM (M x M), g (3 x M), G, E, N0."""
+    def from_host(cls, d, alpha, alpha_lb=ALPHA_LB, device="cuda"):
+        """From host arrays: KM, A0, CM (M x M), g (3 x M), G (n_ref x L x L),
+        Dp (n_ref x M x M), s_ref (n_ref), E, N0."""
         t = lambda a, dt: torch.as_tensor(a, dtype=dt, device=device).contiguous()
         cd, rd = torch.complex128, torch.float64
         M = d["KM"].shape[0]
-        return cls(M, t(d["KM"], cd), t(d["A0"], cd), t(d["CM"], cd), t(d["g"], cd), t(d["G"], cd),
-                   t(d["E"], rd), t(d["N0"], rd), alpha, alpha_lb)
+        return cls(M, t(d["KM"], cd), t(d["A0"], cd), t(d["CM"], cd), t(d["g"], cd),
+                   t(d["G"], cd), t(d["Dp"], cd), t(d["s_ref"], rd), t(d["E"], rd), t(d["N0"], rd),
+                   alpha, alpha_lb)
 
 
 def mpt_spmm(K: Csr, U: torch.Tensor) -> torch.Tensor:
@@ -215,7 +233,7 @@ def mpt_spmm(K: Csr, U: torch.Tensor) -> torch.Tensor:
 
 
 def mpt_residual_gram(Z: torch.Tensor, XinvZ: torch.Tensor) -> torch.Tensor:
-    """Residual Gram G = (Z^H Y + Y^H Z) / 2 with Y = X^{-1} Z (Lemma 4.1):
+    """Residual Gram G_s = (Z^H Y + Y^H Z) / 2 with Y = (X + s C)^{-1} Z (Lemma 4.1):
     Z and Y are N x (2M+3) complex128 on the device; returns G (2M+3)^2."""
     h = handle(Z.device)
     _dev_check(Z)
@@ -247,29 +265,35 @@ def mpt_pod_basis(D: torch.Tensor, tol_sigma: float, M_cap: int):
     return U[:, :M.value].contiguous(), sigma, M.value
 
 
-def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, S, alpha_lb=1.0, keep_Y=False):
-    """a2: Galerkin projection and residual Gram -> Rom (and optionally Y = K U)."""
+def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref, alpha_lb=ALPHA_LB,
+                keep_Y=False):
+    """a2: Galerkin projection and the certificate data (one residual Gram and
+    defect form per reference shift in s_ref) -> Rom (and optionally Y = K U).
+    Vt, lam: eigenvectors (rows) and eigenvalues of the conductor block of
+    X^{-1} scaled by sqrt(c) on both sides."""
     h = handle(U.device)
-    _dev_check(c, w, o, vol, U, cond, S)
+    _dev_check(c, w, o, vol, U, cond, Vt, lam, s_ref)
     N, M = U.shape
     nc = cond.numel()
+    nr = s_ref.numel()
     dev = U.device
     cd, rd = torch.complex128, torch.float64
     KM = torch.empty((M, M), dtype=cd, device=dev)
     A0 = torch.empty_like(KM)
     CM = torch.empty_like(KM)
     g = torch.empty((3, M), dtype=cd, device=dev)
-    G = torch.empty((2 * M + 3, 2 * M + 3), dtype=cd, device=dev)
+    G = torch.empty((nr, 2 * M + 3, 2 * M + 3), dtype=cd, device=dev)
+    Dp = torch.empty((nr, M, M), dtype=cd, device=dev)
     E = torch.empty((3, 3), dtype=rd, device=dev)
     N0 = torch.empty((3, 3), dtype=rd, device=dev)
     Y = torch.empty((N, M), dtype=cd, device=dev) if keep_Y else None
-    ws = torch.empty(lib().mpt_project_ws_size(N, M, nc), dtype=torch.uint8, device=dev)
+    ws = torch.empty(lib().mpt_project_ws_size(N, M, nc, nr), dtype=torch.uint8, device=dev)
     k = K.struct()
     h._check(lib().mpt_project(h.h, C.byref(k), _ptr(c), float(eps_h), _ptr(w), _ptr(o), _ptr(vol),
-                               float(alpha), _ptr(U), M, M, _ptr(cond), nc, _ptr(S), _ptr(KM),
-                               _ptr(A0), _ptr(CM), _ptr(g), _ptr(G), _ptr(E), _ptr(N0), _ptr(Y),
-                               _ptr(ws), ws.numel()))
-    rom = Rom(M, KM, A0, CM, g, G, E, N0, float(alpha), float(alpha_lb))
+                               float(alpha), _ptr(U), M, M, _ptr(cond), nc, _ptr(Vt), _ptr(lam),
+                               nr, _ptr(s_ref), _ptr(KM), _ptr(A0), _ptr(CM), _ptr(g), _ptr(G),
+                               _ptr(Dp), _ptr(E), _ptr(N0), _ptr(Y), _ptr(ws), ws.numel()))
+    rom = Rom(M, KM, A0, CM, g, G, Dp, s_ref, E, N0, float(alpha), float(alpha_lb))
     return (rom, Y) if keep_Y else rom
 
 
@@ -311,9 +335,9 @@ class Pencil:
 def mpt_pencil_reduce(rom: Rom) -> Pencil:
     """Reduce (A0, C_M) to Hessenberg-triangular form (asynchronous)."""
     h = handle(rom.A0.device)
-    nb = lib().mpt_pencil_bytes(rom.M)
+    nb = lib().mpt_pencil_bytes(rom.M, rom.n_ref)
     if nb == 0:
-        raise MptError(f"the pencil form takes 1 <= M <= 64 (M = {rom.M})")
+        raise MptError(f"the pencil form takes 1 <= M <= 96 (M = {rom.M})")
     buf = torch.empty(nb, dtype=torch.uint8, device=rom.A0.device)
     r = rom.struct()
     st = _Pencil()
@@ -376,8 +400,10 @@ def mpt_select_snapshots(omega, out, snap, n_star):
     new = torch.empty(n_star, dtype=torch.float64, device=dev)
     lam = torch.empty(snap.numel() - 1, dtype=torch.float64, device=dev)
     Lmax = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(lib().mpt_select_snapshots_ws_size(snap.numel()), dtype=torch.uint8, device=dev)
     h._check(lib().mpt_select_snapshots(h.h, _ptr(omega), omega.numel(), _ptr(out), _ptr(snap),
-                                        snap.numel(), n_star, _ptr(new), _ptr(lam), _ptr(Lmax)))
+                                        snap.numel(), n_star, _ptr(new), _ptr(lam), _ptr(Lmax),
+                                        _ptr(ws), ws.numel()))
     return new, lam, Lmax
 
 
@@ -392,9 +418,11 @@ def mpt_select_snapshots_threshold(omega, out, snap, theta):
     cnt = torch.empty(1, dtype=torch.int32, device=dev)
     lam = torch.empty(ni, dtype=torch.float64, device=dev)
     Lmax = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(lib().mpt_select_snapshots_ws_size(snap.numel()), dtype=torch.uint8, device=dev)
     h._check(lib().mpt_select_snapshots_threshold(h.h, _ptr(omega), omega.numel(), _ptr(out),
                                                   _ptr(snap), snap.numel(), float(theta), _ptr(new),
-                                                  _ptr(cnt), _ptr(lam), _ptr(Lmax)))
+                                                  _ptr(cnt), _ptr(lam), _ptr(Lmax), _ptr(ws),
+                                                  ws.numel()))
     return new, cnt, lam, Lmax
 
 
@@ -413,6 +441,20 @@ class Dictionary:
         self.off = (C.c_int64 * (self.n_obj + 1))(*off)
         self.offsets = off
         self.omega = torch.cat([w.to(device=device, dtype=torch.float64) for w in omegas]).contiguous()
+        self._ws = {}
+
+    def workspace(self, tune=None):
+        """Device workspace of the batched sweeps for a tuning (kept: a
+        recorded graph refers to it)."""
+        key = None if tune is None else tuple(int(x) for x in tune)
+        if key not in self._ws:
+            t = None if tune is None else _Tuning(key[0], key[1], key[2], 0)
+            n = lib().mpt_sweep_batched_ws_size(self._structs, self.n_obj, self.off,
+                                                 C.byref(t) if t is not None else None)
+            if n == 0:
+                raise MptError("bad dictionary for the batched sweep")
+            self._ws[key] = torch.empty(n, dtype=torch.uint8, device=self.omega.device)
+        return self._ws[key]
 
 
 def mpt_sweep_batched(dic: Dictionary, tune=None, use_graph=True, out=None, status=None):
@@ -426,9 +468,11 @@ def mpt_sweep_batched(dic: Dictionary, tune=None, use_graph=True, out=None, stat
     t = None
     if tune is not None:
         t = _Tuning(int(tune[0]), int(tune[1]), int(tune[2]), 0)
+    ws = dic.workspace(tune)
     h._check(lib().mpt_sweep_batched(h.h, dic._structs, _ptr(dic.dev_structs), dic.n_obj, dic.off,
                                      _ptr(dic.omega), _ptr(out), _ptr(status),
-                                     C.byref(t) if t is not None else None, int(bool(use_graph))))
+                                     C.byref(t) if t is not None else None, int(bool(use_graph)),
+                                     _ptr(ws), ws.numel()))
     return out, status
 
 
@@ -443,9 +487,9 @@ def mpt_sweep_pencil_batched(dic: Dictionary, out=None, status=None, buf=None):
         out = torch.empty((n, 18), dtype=torch.float64, device=dev)
     if status is None:
         status = torch.empty(n, dtype=torch.int32, device=dev)
-    nb = lib().mpt_pencil_batched_bytes(dic._structs, dic.n_obj)
+    nb = lib().mpt_pencil_batched_bytes(dic._structs, dic.n_obj, dic.off)
     if nb == 0:
-        raise MptError("the pencil form takes 1 <= M <= 64 for every object")
+        raise MptError("the pencil form takes 1 <= M <= 96 for every object")
     if buf is None or buf.numel() < nb:
         buf = torch.empty(nb, dtype=torch.uint8, device=dev)
     h._check(lib().mpt_sweep_pencil_batched(h.h, dic._structs, dic.n_obj, dic.off, _ptr(dic.omega),
@@ -480,10 +524,13 @@ def mpt_sweep_adjoint_materials(rom: Rom, part1: Rom, omega, dout):
     dom = torch.empty(n, dtype=torch.float64, device=omega.device)
     sds = torch.empty(2, dtype=torch.float64, device=omega.device)
     st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    ws = torch.empty(lib().mpt_sweep_adjoint_materials_ws_size(n), dtype=torch.uint8,
+                     device=omega.device)
     r = rom.struct()
     h._check(lib().mpt_sweep_adjoint_materials(h.h, C.byref(r), _ptr(part1.CM), _ptr(part1.g),
                                                _ptr(part1.E), _ptr(omega), n, _ptr(dout),
-                                               _ptr(dom), _ptr(sds), _ptr(st)))
+                                               _ptr(dom), _ptr(sds), _ptr(st), _ptr(ws),
+                                               ws.numel()))
     return dom, sds, st
 
 
@@ -493,38 +540,66 @@ def mpt_sweep_adjoint_batched(dic: Dictionary, dout):
     dom = torch.empty(n, dtype=torch.float64, device=dic.omega.device)
     sds = torch.empty(dic.n_obj, dtype=torch.float64, device=dic.omega.device)
     st = torch.empty(n, dtype=torch.int32, device=dic.omega.device)
+    ws = dic.workspace(None)
     h._check(lib().mpt_sweep_adjoint_batched(h.h, dic._structs, _ptr(dic.dev_structs), dic.n_obj,
                                              dic.off, _ptr(dic.omega), _ptr(dout), _ptr(dom),
-                                             _ptr(sds), _ptr(st)))
+                                             _ptr(sds), _ptr(st), _ptr(ws), ws.numel()))
     return dom, sds, st
+
+
+def mpt_signature(rom: Rom, omega, sigma, sigma0):
+    """Sweep outputs (n x 18) at conductivity sigma (device tensor, 1 value)
+    for a model projected at sigma0, and status."""
+    h = handle(omega.device)
+    _dev_check(omega, sigma)
+    n = omega.numel()
+    out = torch.empty((n, 18), dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    r = rom.struct()
+    h._check(lib().mpt_signature(h.h, C.byref(r), _ptr(omega), n, _ptr(sigma), float(sigma0),
+                                 _ptr(out), _ptr(st)))
+    return out, st
+
+
+def mpt_signature_adjoint(rom: Rom, omega, sigma, sigma0, dout):
+    """(dL/domega (n), dL/dsigma (1), status) for upstream gradients dout."""
+    h = handle(omega.device)
+    _dev_check(omega, sigma, dout)
+    n = omega.numel()
+    dom = torch.empty(n, dtype=torch.float64, device=omega.device)
+    dsg = torch.empty(1, dtype=torch.float64, device=omega.device)
+    st = torch.empty(n, dtype=torch.int32, device=omega.device)
+    r = rom.struct()
+    h._check(lib().mpt_signature_adjoint(h.h, C.byref(r), _ptr(omega), n, _ptr(sigma),
+                                         float(sigma0), _ptr(dout), _ptr(dom), _ptr(dsg),
+                                         _ptr(st)))
+    return dom, dsg, st
 
 
 class SweepFn(torch.autograd.Function):
     """Differentiable signature sweep of one object.
 
     forward(omega, sigma) -> (n, 12) [R~ (6) | I (6)] at conductivity sigma, the
-    reduced model having been projected at sigma0 (C_M, g, E scale with sigma,
-    basis frozen).  The model depends on omega * sigma only, so the sweep runs
-    at omega * sigma / sigma0; backward runs the adjoint kernel."""
+    reduced model having been projected at sigma0; the scaling and the chain
+    rule run in the library (mpt_signature, mpt_signature_adjoint)."""
 
     @staticmethod
     def forward(ctx, omega, sigma, rom, sigma0):
-        scale = sigma.detach() / sigma0
-        w_eff = (omega.detach() * scale).contiguous()
-        out, st = mpt_sweep(rom, w_eff)
-        ctx.save_for_backward(omega, sigma, w_eff)
-        ctx.rom, ctx.sigma0 = rom, sigma0
+        om = omega.detach().contiguous()
+        sg = sigma.detach().reshape(1).contiguous()
+        out, st = mpt_signature(rom, om, sg, sigma0)
+        ctx.save_for_backward(om, sg)
+        ctx.rom, ctx.sigma0, ctx.sig_shape = rom, sigma0, sigma.shape
         return out[:, :12]
 
     @staticmethod
     def backward(ctx, grad):
-        omega, sigma, w_eff = ctx.saved_tensors
-        dout = torch.zeros((omega.numel(), 18), dtype=torch.float64, device=omega.device)
+        om, sg = ctx.saved_tensors
+        dout = torch.zeros((om.numel(), 18), dtype=torch.float64, device=om.device)
         dout[:, :12] = grad
-        dom_eff, sds, _ = mpt_sweep_adjoint(ctx.rom, w_eff, dout.contiguous())
-        scale = sigma.detach() / ctx.sigma0
-        g_omega = dom_eff * scale if ctx.needs_input_grad[0] else None
-        g_sigma = (sds[0] / sigma.detach()).reshape(sigma.shape) if ctx.needs_input_grad[1] else None
+        dom, dsg, _ = mpt_signature_adjoint(ctx.rom, om, sg, ctx.sigma0, dout)
+        g_omega = dom if ctx.needs_input_grad[0] else None
+        g_sigma = dsg.reshape(ctx.sig_shape) if ctx.needs_input_grad[1] else None
         return g_omega, g_sigma, None, None
 
 

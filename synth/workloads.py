@@ -120,6 +120,13 @@ def log_grid(lo, hi, n):
     return np.logspace(np.log10(lo), np.log10(hi), int(n))
 
 
+def reference_shifts(lo, hi, per_decade=2):
+    """Reference shifts of the certificate's norms X + s C_sigma: 0, then
+    lo * 10^(k / per_decade) up to hi (the frequency band of the outputs)."""
+    n = int(np.floor(per_decade * np.log10(hi / lo) + 1e-9)) + 1
+    return np.r_[0.0, lo * 10.0 ** (np.arange(n) / per_decade)]
+
+
 @dataclass
 class Problem:
     """Everything the hot path consumes for one object (host arrays, FP64)."""
@@ -139,6 +146,16 @@ class Problem:
     @property
     def w(self) -> np.ndarray:
         return self.ops.x + self.o
+
+    @property
+    def s_ref(self) -> np.ndarray:
+        return reference_shifts(*self.wl.omega_range)
+
+    def cond_spectrum(self):
+        """(lam, Vt): eigenvalues and eigenvectors (rows) of sqrt(c) S sqrt(c)
+        on the conductor edges, S the conductor block of X^{-1}."""
+        lam, V, _ = self.solver._eig()
+        return lam, np.ascontiguousarray(V.T)
 
     @property
     def M_cap(self) -> int:

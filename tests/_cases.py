@@ -5,6 +5,7 @@ import numpy as np
 
 from synth.fullorder import FullOrderSolver
 from synth.shapes import ellipsoid, shell_sphere, sphere, cuboid
+from synth.workloads import reference_shifts
 from synth.yee import YeeGrid, build_operators
 
 
@@ -21,6 +22,12 @@ class Case:
         self.snap_res = hist[-1]
         self.S = self.fs.schur()
         self.shape = shape
+        # conductor block's eigenpairs (lam, V, sqrt(c)) and the reference
+        # shifts of the certificate over the test band [1e1, 1e6]
+        self.spec = self.fs._eig()
+        self.lam = self.spec[0]
+        self.Vt = np.ascontiguousarray(self.spec[1].T)
+        self.s_ref = reference_shifts(1e1, 1e6)
 
     def oracle_fo(self):
         from oracle.grid import FullOrder
@@ -54,3 +61,9 @@ def magnetic10():
 @functools.lru_cache(maxsize=None)
 def cube10_mu():
     return Case(10, cuboid(1.5, 1.0, 1.5, 1e7, 8.0), np.logspace(1, 6, 6))
+
+
+@functools.lru_cache(maxsize=None)
+def ellipsoid16_k32():
+    """The 16^3 ellipsoid with 32 snapshots (96 columns): room for M = 64."""
+    return Case(16, ellipsoid(1.6, 1.2, 0.9, 5.8e7), np.logspace(1, 6, 32))
