@@ -233,6 +233,21 @@ mpt_status mpt_select_snapshots(mpt_handle h, const double* omega, int64_t n, co
                                 double* new_omega, double* lambda, double* Lambda_max, void* ws,
                                 size_t ws_bytes);
 
+/* Allocation-free variant of mpt_select_snapshots, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same inputs, outputs and results
+ * without a workspace argument.  Its per-interval scratch is a static device
+ * array of the library, MPT_SELECT_STATIC_MAX_SNAP (4096) snapshot
+ * frequencies = 32 KiB per GPU, held until the process ends; n_snap above
+ * that limit is rejected (MPT_E_ARG).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (several streams or threads) race.
+ * Nothing is allocated: no hipMalloc, hipFree or allocating library routine. */
+#define MPT_SELECT_STATIC_MAX_SNAP 4096
+mpt_status mpt_select_snapshots_static(mpt_handle h, const double* omega, int64_t n,
+                                       const double* out, const double* snap, int n_snap,
+                                       int n_star, double* new_omega, double* lambda,
+                                       double* Lambda_max);
+
 /* Threshold variant of the selection (the alternative to a fixed N_* that
  * Section 4.4 names, after Hesthaven et al.): every interval whose maximum reaches
  * theta * Lambda (0 < theta <= 1) gives its argmax, at most one per interval,

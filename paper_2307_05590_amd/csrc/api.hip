@@ -7,11 +7,24 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "device_util.h"
 #include "kernels.h"
+
+// Scratch of mpt_select_snapshots_static (per-interval argmax): a static
+// device array, so that call allocates nothing.  Each GPU holds its own copy
+// until the process ends; host code uses only the per-device address that
+// hipGetSymbolAddress returns (select_scratch_ptr), never the array's name.
+static __device__ __align__(256) int64_t scratch[MPT_SELECT_STATIC_MAX_SNAP];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
 
 struct mpt_handle_s {
   int device = 0;
@@ -201,6 +214,20 @@ extern "C" mpt_status mpt_create(int device, void* hip_stream, mpt_handle* out) 
   if (hipHostMalloc(reinterpret_cast<void**>(&h->host_M), sizeof(int), 0) != hipSuccess) {
     delete h;
     return MPT_E_HIP;
+  }
+  // address of this device's copy of the static selection scratch, looked up
+  // once per device with the device current
+  if (device >= 0 && device < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        hipHostFree(h->host_M);
+        delete h;
+        return MPT_E_HIP;
+      }
+      g_scratch_ptr[device] = p;
+    }
   }
   *out = h;
   return MPT_OK;
@@ -810,6 +837,29 @@ extern "C" mpt_status mpt_select_snapshots_threshold(mpt_handle h, const double*
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(select_threshold_launch(omega, n, out, snap, n_snap, theta, new_omega, n_new, lambda,
                                  Lambda_max, reinterpret_cast<int64_t*>(ws), h->stream));
+  return MPT_OK;
+}
+
+extern "C" mpt_status mpt_select_snapshots_static(mpt_handle h, const double* omega, int64_t n,
+                                                  const double* out, const double* snap,
+                                                  int n_snap, int n_star, double* new_omega,
+                                                  double* lambda, double* Lambda_max) {
+  if (!h) return MPT_E_ARG;
+  ARG(omega && out && snap && new_omega && lambda && Lambda_max, "NULL pointer");
+  ARG(n >= 1 && n_snap >= 2 && n_star >= 1 && n_star <= 64, "bad sizes");
+  ARG(n_snap <= MPT_SELECT_STATIC_MAX_SNAP,
+      "n_snap above MPT_SELECT_STATIC_MAX_SNAP (the static scratch's size)");
+  ARG(h->device >= 0 && h->device < kMaxDevices, "device index out of range");
+  void* scr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    scr = g_scratch_ptr[h->device];
+  }
+  if (!scr) return fail(h, MPT_E_HIP, "static scratch address unknown for this device");
+  HIP_OK(hipSetDevice(h->device));
+  // every interval's slot is written before it is read: nothing to clear
+  HIP_OK(select_launch(omega, n, out, snap, n_snap, n_star, new_omega, lambda, Lambda_max,
+                       reinterpret_cast<int64_t*>(scr), h->stream));
   return MPT_OK;
 }
 

@@ -72,6 +72,7 @@ def lib():
             "mpt_signature": ([P, P, P, I64, P, D, P, P], I32),
             "mpt_signature_adjoint": ([P, P, P, I64, P, D, P, P, P, P], I32),
             "mpt_select_snapshots_ws_size": ([I32], S),
+            "mpt_select_snapshots_static": ([P, P, I64, P, P, I32, I32, P, P, P], I32),
             "mpt_sweep_batched_ws_size": ([P, I32, P, P], S),
             "mpt_spmm": ([P, P, P, I64, I32, P, I64], I32),
             "mpt_sweep": ([P, P, P, I64, P, P, P], I32),
@@ -404,6 +405,24 @@ def mpt_select_snapshots(omega, out, snap, n_star):
     h._check(lib().mpt_select_snapshots(h.h, _ptr(omega), omega.numel(), _ptr(out), _ptr(snap),
                                         snap.numel(), n_star, _ptr(new), _ptr(lam), _ptr(Lmax),
                                         _ptr(ws), ws.numel()))
+    return new, lam, Lmax
+
+
+def mpt_select_snapshots_static(omega, out, snap, n_star, new=None, lam=None, Lmax=None):
+    """a5 without a workspace (the library's static scratch; n_snap <= 4096).
+    Output tensors may be passed in, so that the call allocates nothing."""
+    h = handle(omega.device)
+    _dev_check(omega, out, snap)
+    dev = omega.device
+    if new is None:
+        new = torch.empty(n_star, dtype=torch.float64, device=dev)
+    if lam is None:
+        lam = torch.empty(snap.numel() - 1, dtype=torch.float64, device=dev)
+    if Lmax is None:
+        Lmax = torch.empty(1, dtype=torch.float64, device=dev)
+    h._check(lib().mpt_select_snapshots_static(h.h, _ptr(omega), omega.numel(), _ptr(out),
+                                               _ptr(snap), snap.numel(), n_star, _ptr(new),
+                                               _ptr(lam), _ptr(Lmax)))
     return new, lam, Lmax
 
 
