@@ -133,7 +133,7 @@ def _rom(c, M, fo=None):
 
 
 def test_mm_equals_mesh_sums():
-    """IM, FMM and MM agree up to rounding."""
+    """Section 9 (Conclusions): IM, FMM and MM give the same tensors up to rounding."""
     c = _cases.ellipsoid16()
     fo, U, rom = _rom(c, 10)
     om = np.logspace(1, 6, 7)
