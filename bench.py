@@ -50,6 +50,7 @@ FP64_MFMA_PEAK_TF = 78.6
 def cert_inputs(p, T):
     """Certificate inputs of mpt_project for a problem: the conductor block's
     eigenvectors (rows) and eigenvalues, and the reference shifts."""
+    import torch
     lam, Vt = p.cond_spectrum()
     return T(Vt, torch.float64), T(lam, torch.float64), T(p.s_ref, torch.float64)
 
