@@ -12,8 +12,18 @@ Method (exact up to rounding, then refined against the sparse operator):
     X_mu = X_1 + C_F^T diag((1/mu_f - 1)/h) C_F.
   * C_sigma is supported on the n_c conductor edges, so
     q = X^{-1}(f + i omega P D_c P^T q) reduces to a dense n_c system with the
-    conductor Schur block S = P^T X^{-1} P; one symmetric eigendecomposition
-    of D_c^{1/2} S D_c^{1/2} serves every frequency.
+    conductor Schur block S = P^T X^{-1} P.
+  * X^{-1} = T + G L^{-1} G^T / (eps h): a transverse part T (bounded) and
+    the gradients G of nodal potentials, on which K vanishes (L = G^T G, the
+    nodal Laplacian, inverted by DST-I).  The 1/(eps h) part makes S
+    ill-conditioned (its transverse information sits ~1e-5 below its
+    rounding), so the conductor system is solved in split form: with
+    nu = (i omega / eps h) G_c^T D_c z,
+        z - i omega S_T D_c z - G_c Y nu = f_c,   eps h nu - i omega G_c^T D_c z = 0,
+    S_T = P^T T P, G_c = P^T G, Y the nodal Green's function on the nodes of
+    conductor edges: no entry carries the 1/(eps h) factor.  One
+    eigendecomposition of D_c^{1/2} S_T D_c^{1/2} reduces each frequency to a
+    dense system on those nodes.
   * Iterative refinement with residuals of the sparse A(omega) brings the
     relative residual to ~1e-13.
 """
@@ -22,6 +32,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.fft as sfft
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from .yee import Operators, YeeGrid
 
@@ -88,6 +99,27 @@ class SpectralX1:
         ry = sfft.idct(sfft.dst(sfft.dst(oy, 1, axis=0, norm="ortho", workers=w), 1, axis=2, norm="ortho", workers=w), 2, axis=1, norm="ortho", workers=w)
         rz = sfft.idct(sfft.dst(sfft.dst(oz, 1, axis=0, norm="ortho", workers=w), 1, axis=1, norm="ortho", workers=w), 2, axis=2, norm="ortho", workers=w)
         return np.concatenate([rx.reshape(nx, B), ry.reshape(nx, B), rz.reshape(nx, B)], 0)
+
+
+class SpectralLaplacian:
+    """Exact inverse of the interior-node Dirichlet Laplacian L = G^T G by
+    orthonormal DST-I transforms (symbols |s|^2 with s_a = 2 sin(pi k_a/2n))."""
+
+    def __init__(self, grid: YeeGrid):
+        n, m = grid.n, grid.n - 1
+        s2 = (2.0 * np.sin(np.pi * np.arange(1, n) / (2.0 * n))) ** 2
+        self.m = m
+        self.sym = (s2[:, None, None] + s2[None, :, None] + s2[None, None, :])[..., None]
+
+    def solve(self, F: np.ndarray) -> np.ndarray:
+        m = self.m
+        one = F.ndim == 1
+        F = F.reshape(m ** 3, -1)
+        w = _workers()
+        t = sfft.dstn(F.reshape(m, m, m, -1), type=1, axes=(0, 1, 2), norm="ortho", workers=w)
+        out = sfft.idstn(t / self.sym, type=1, axes=(0, 1, 2), norm="ortho",
+                         workers=w).reshape(m ** 3, -1)
+        return out[:, 0] if one else out
 
 
 class RegionGreen:
@@ -196,18 +228,9 @@ class FullOrderSolver:
                 S -= self.Wc @ sla.lu_solve(self.cap, self.Wc.T)
             self._S = 0.5 * (S + S.T)
         if self._S is None:
-            N = self.ops.N
-            nc = self.cond.size
-            S = np.empty((nc, nc))
-            for c0 in range(0, nc, self.chunk):
-                if self.verbose and c0 % (40 * self.chunk) == 0:
-                    print(f"  conductor block: {c0}/{nc} columns", flush=True)
-                idx = self.cond[c0:c0 + self.chunk]
-                E = np.zeros((N, idx.size))
-                E[idx, np.arange(idx.size)] = 1.0
-                S[:, c0:c0 + idx.size] = self.sx.apply(E, self.chunk)[self.cond]
-            if self.F.size:
-                S -= self.Wc @ sla.lu_solve(self.cap, self.Wc.T)
+            # S = S_T + G_c Y G_c^T / (eps h) from the split data
+            sp_ = self.split()
+            S = sp_["ST"] + (sp_["GY"] @ sp_["Gc"].T) / self.ops.eps_h
             self._S = 0.5 * (S + S.T)
         return self._S
 
@@ -221,13 +244,175 @@ class FullOrderSolver:
         Y = self.xinv(np.ascontiguousarray(Z.real)) + 1j * self.xinv(np.ascontiguousarray(Z.imag))
         return np.ascontiguousarray(Z), np.ascontiguousarray(Y)
 
+    # ---- transverse / longitudinal split -------------------------------
+    def tmu(self, V):
+        """T_mu V: the transverse part of X^{-1} V (permeability included).
+        The Woodbury correction lives in the range of C^T, so it only
+        changes the transverse part."""
+        U = self.sx.apply(V, self.chunk, transverse=True)
+        if self.F.size:
+            z = sla.lu_solve(self.cap, self.CF @ U)
+            U = U - self.sx.apply(self.CFT @ z, self.chunk, transverse=True)
+        return U
+
+    def split(self):
+        """Conductor data of the split form (built once): S_T, G_c, G_c Y,
+        the eigenpairs of D_c^{1/2} S_T D_c^{1/2} and the per-frequency
+        reduction onto the nodes of conductor edges."""
+        if getattr(self, "_sp", None) is not None:
+            return self._sp
+        from scipy.sparse.csgraph import connected_components
+
+        ops = self.ops
+        g = ops.grid
+        cond = self.cond
+        nc = cond.size
+        G = g.gradient()
+        lap = SpectralLaplacian(g)
+        ST = np.empty((nc, nc))
+        for c0 in range(0, nc, self.chunk):
+            if self.verbose and c0 % (40 * self.chunk) == 0:
+                print(f"  conductor block (transverse): {c0}/{nc} columns", flush=True)
+            idx = cond[c0:c0 + self.chunk]
+            E = np.zeros((ops.N, idx.size))
+            E[idx, np.arange(idx.size)] = 1.0
+            ST[:, c0:c0 + idx.size] = self.sx.apply(E, self.chunk, transverse=True)[cond]
+        if self.F.size:  # the permeability correction is transverse
+            ST -= self.Wc @ sla.lu_solve(self.cap, self.Wc.T)
+        ST = 0.5 * (ST + ST.T)
+        Gcond = G[cond].tocsc()
+        cn = np.flatnonzero(np.diff(Gcond.indptr) > 0)  # nodes of conductor edges
+        Gc = Gcond[:, cn].toarray()
+        Gcond = Gcond.tocsr()
+        GY = np.empty((nc, cn.size))  # G_c Y, Y = L^{-1} on those nodes
+        for c0 in range(0, cn.size, 4 * self.chunk):
+            nd = cn[c0:c0 + 4 * self.chunk]
+            E = np.zeros((G.shape[1], nd.size))
+            E[nd, np.arange(nd.size)] = 1.0
+            GY[:, c0:c0 + nd.size] = Gcond @ lap.solve(E)
+        ncomp, lab = connected_components(sp.csr_matrix(np.abs(Gc).T @ np.abs(Gc)), directed=False)
+        Cc = np.zeros((cn.size, ncomp))
+        Cc[np.arange(cn.size), lab] = 1.0
+        Cc /= np.linalg.norm(Cc, axis=0)
+        d = np.sqrt(ops.c[cond])
+        lam, V = np.linalg.eigh(d[:, None] * ST * d[None, :])
+        self._sp = {"G": G, "lap": lap, "ST": ST, "Gc": Gc, "GY": GY, "cn": cn, "Cc": Cc,
+                    "d": d, "lam": lam, "V": V, "P1": (Gc.T * d[None, :]) @ V,
+                    "P2": V.T @ (d[:, None] * GY)}
+        return self._sp
+
+    def _split_solve(self, fc, omega):
+        """(z, nu) of  z - i w S_T D z - G_c Y nu = f_c,  eps_h nu - i w G_c^T D z = 0
+        for each column of f_c (n_c, B) with its own omega; one dense
+        factorisation per distinct omega on the nodes of conductor edges.
+        Constant potentials on each connected conductor piece have no
+        gradient there, so nu has no component along them: that direction of
+        the reduced matrix (eigenvalue eps h) is lifted to its scale."""
+        sp_ = self.split()
+        lam, V, d, P1, P2, Cc = (sp_[k] for k in ("lam", "V", "d", "P1", "P2", "Cc"))
+        omega = np.asarray(omega, dtype=np.float64)
+        fh = V.T @ (d[:, None] * fc)
+        Z = np.empty(fc.shape, dtype=np.complex128)
+        NU = np.empty((P1.shape[0], fc.shape[1]), dtype=np.complex128)
+        eye = np.eye(P1.shape[0])
+        for om in np.unique(omega):
+            cols = np.flatnonzero(omega == om)
+            R = 1.0 / (1.0 - 1j * om * lam)
+            Mw = -1j * om * ((P1 * R.real[None, :]) @ P2 + 1j * ((P1 * R.imag[None, :]) @ P2))
+            gam = max(np.abs(Mw).sum(1).max(), self.ops.eps_h)
+            Mw += self.ops.eps_h * eye + gam * (Cc @ Cc.T)
+            rhs = 1j * om * (P1 @ (R[:, None] * fh[:, cols]))
+            nu = sla.solve(Mw, rhs)
+            Z[:, cols] = (V @ (R[:, None] * (fh[:, cols] + P2 @ nu))) / d[:, None]
+            NU[:, cols] = nu
+        return Z, NU
+
+    def _split_field(self, Z, NU, omega, base=None):
+        """base + i w T_mu(C z) + G L^{-1} E nu: the full field from the
+        conductor unknowns."""
+        sp_ = self.split()
+        ops = self.ops
+        CZ = np.zeros((ops.N, Z.shape[1]), dtype=np.complex128)
+        CZ[self.cond] = ops.c[self.cond][:, None] * Z
+        En = np.zeros((sp_["G"].shape[1], Z.shape[1]), dtype=np.complex128)
+        En[sp_["cn"]] = NU
+        out = 1j * np.asarray(omega)[None, :] * self.tmu(CZ) + sp_["G"] @ sp_["lap"].solve(En)
+        return out if base is None else base + out
+
+    def _split_correction(self, res, omega):
+        """A(omega)^{-1} res in split form: u = X^{-1} res, then the conductor
+        system with f_c = u_c and d = u + i w X^{-1} C z."""
+        sp_ = self.split()
+        u = self.tmu(res) + sp_["G"] @ sp_["lap"].solve(sp_["G"].T @ res) / self.ops.eps_h
+        Z, NU = self._split_solve(u[self.cond], omega)
+        return self._split_field(Z, NU, omega, base=u)
+
     def _eig(self):
+        """Eigenpairs (lam, V, d) of D_c^{1/2} S D_c^{1/2}, d = sqrt(c) on the
+        conductor edges."""
         if not hasattr(self, "_lam"):
-            S = self.schur()
-            d = np.sqrt(self.ops.c[self.cond])
-            lam, V = np.linalg.eigh(d[:, None] * S * d[None, :])
+            if self.green is None:
+                lam, V = self._eig_split()
+                d = self.split()["d"]
+            else:
+                S = self.schur()
+                d = np.sqrt(self.ops.c[self.cond])
+                lam, V = np.linalg.eigh(d[:, None] * S * d[None, :])
             self._lam, self._V, self._d = lam, V, d
         return self._lam, self._V, self._d
+
+    def _eig_split(self):
+        """Eigenpairs of M = M_T + H Y H^T / (eps h) (M_T = D^{1/2} S_T D^{1/2},
+        H = D^{1/2} G_c) to the accuracy of each eigenvalue's own scale.
+
+        A dense eigensolver on M perturbs every eigenvector by eps ||M|| / gap,
+        which is ~1e-5 for the transverse pairs here.  Instead: in orthonormal
+        bases of null(H^T) (divergence-free conductor currents) and range(H),
+        M = [[A, B], [B^T, C + E / eps_h]].  The invariant subspace of the
+        small eigenvalues is span [I; X] with X solving the Riccati equation
+        (C + E/eps_h) X = -B^T + X A + X B X (a contraction by
+        ||(C + E/eps_h)^{-1}|| ||A||, so a few fixed-point steps converge);
+        [I; X] and [-X^T; I] are exactly orthogonal, and each block is
+        diagonalised on its own scale."""
+        sp_ = self.split()
+        d, ST, Gc, GY = sp_["d"], sp_["ST"], sp_["Gc"], sp_["GY"]
+        eh = self.ops.eps_h
+        MT = d[:, None] * ST * d[None, :]
+        H = d[:, None] * Gc
+        Uh, sv, _ = np.linalg.svd(H, full_matrices=True)
+        r = Gc.shape[1] - sp_["Cc"].shape[1]  # rank: one constant per conductor piece
+        QR, QN = Uh[:, :r], Uh[:, r:]
+        E = QR.T @ ((d[:, None] * GY) @ (H.T @ QR))
+        E = 0.5 * (E + E.T)
+        A = QN.T @ MT @ QN
+        Bm = QN.T @ MT @ QR
+        Cbig = QR.T @ MT @ QR + E / eh
+        Cbig = 0.5 * (Cbig + Cbig.T)
+        cf = sla.cho_factor(Cbig)
+        X = np.zeros((r, QN.shape[1]))
+        for _ in range(8):
+            Xn = sla.cho_solve(cf, -Bm.T + X @ A + X @ (Bm @ X))
+            done = np.abs(Xn - X).max() <= 1e-15 * max(np.abs(Xn).max(), 1e-300)
+            X = Xn
+            if done:
+                break
+
+        def isqrt(Nm):
+            w, Q = np.linalg.eigh(Nm)
+            return (Q / np.sqrt(w)[None, :]) @ Q.T
+
+        N1 = isqrt(np.eye(X.shape[1]) + X.T @ X)
+        N2 = isqrt(np.eye(r) + X @ X.T)
+        A1 = N1 @ (A + Bm @ X + X.T @ Bm.T + X.T @ (Cbig @ X)) @ N1
+        A2 = N2 @ (Cbig - X @ Bm - Bm.T @ X.T + X @ (A @ X.T)) @ N2
+        l1, W1 = np.linalg.eigh(0.5 * (A1 + A1.T))
+        l2, W2 = np.linalg.eigh(0.5 * (A2 + A2.T))
+        V1 = (QN + QR @ X) @ (N1 @ W1)
+        V2 = (QR - QN @ X.T) @ (N2 @ W2)
+        lam = np.r_[l1, l2]
+        V = np.concatenate([V1, V2], 1)
+        order = np.argsort(lam)
+        return lam[order], np.ascontiguousarray(V[:, order])
 
     def _csolve(self, u_c, omega):
         """Solve (I - i w S D_c) q_c = u_c for each column (own omega)."""
@@ -245,6 +430,8 @@ class FullOrderSolver:
 
     def snapshots(self, omegas, w, tol=1e-13, max_iter=8, verbose=False, gmres_cycles=8):
         """Full-order q_i(omega_k); returns D (N, 3K) = [q_1(w_1..K)|q_2|q_3] and residuals."""
+        if self.green is None:
+            return self._snapshots_split(omegas, w, tol, max_iter, verbose)
         ops = self.ops
         omegas = np.asarray(omegas, dtype=np.float64)
         K = omegas.size
@@ -291,6 +478,40 @@ class FullOrderSolver:
             Q[:, sl], h2 = self._gmres(r[:, sl], Q[:, sl], om[sl], tol, cycles=gmres_cycles,
                                        verbose=verbose)
             hist.append(h2)
+        return Q, hist
+
+    def _snapshots_split(self, omegas, w, tol, max_iter, verbose):
+        """Snapshots by the split conductor system.  With z = w_c + q_c the
+        equation q = i w X^{-1} C (w + q) becomes z - i w S D z = w_c on the
+        conductor and q = i w X^{-1} C z, free of the 1/(eps h) cancellation
+        that the right-hand side i w C w would carry; refinement steps solve
+        A d = residual in the same split form."""
+        ops = self.ops
+        omegas = np.asarray(omegas, dtype=np.float64)
+        K = omegas.size
+        om = np.tile(omegas, 3)  # column j -> direction j // K, frequency j % K
+        W = np.repeat(w, K, axis=1)
+        r = 1j * om[None, :] * (ops.c[:, None] * W)
+        Z, NU = self._split_solve(W[self.cond].astype(np.complex128), om)
+        Q = self._split_field(Z, NU, om)
+        rn = np.linalg.norm(r, axis=0)
+        hist = []
+        prev, Qprev = np.inf, None
+        for it in range(max_iter):
+            res = r - self.apply_A(Q, om)
+            rel = np.linalg.norm(res, axis=0) / rn
+            hist.append(float(rel.max()))
+            if verbose:
+                print(f"  refine {it}: max rel residual {rel.max():.3e}", flush=True)
+            if rel.max() <= tol:
+                break
+            if rel.max() > 0.5 * prev:  # at the rounding floor
+                if rel.max() > prev:
+                    Q = Qprev
+                    hist.append(float(prev))
+                break
+            prev, Qprev = rel.max(), Q
+            Q = Q + self._split_correction(res, om)
         return Q, hist
 
     def _gmres(self, b, x, om, tol, m=30, cycles=8, verbose=False):

@@ -17,9 +17,10 @@ Draw order per object: shape type, dimensions, rotation, sigma_*, mu_r, M, n_ome
   5 shell64       64^3 grid, steel core r < 0.6 (mu_r 50, sigma 6e6) in an
                   aluminium shell r < 1 (sigma 3.5e7); 48 initial snapshots on
                   [1e1,1e7] + 3 adaptive rounds x 2; TOL 1e-8, M <= 96; 1e5
-                  output omegas on [1e1,1e7].  At the high end of sigma omega
-                  the host refinement stalls; the snapshots keep its best
-                  iterate (the residual is recorded in Problem.snap_residual).
+                  output omegas on [1e1,1e7].
+Snapshots of objects with their own spectral solves (1, 2, 5) are solved in
+the split transverse/longitudinal form to a relative residual of 1e-12 or
+better at every frequency; the largest is recorded in Problem.snap_residual.
 All use alpha = 1e-2 m, eps = 1e-10 and the box [-5,5]^3.
 """
 from __future__ import annotations
@@ -53,7 +54,7 @@ class Workload:
     n_omega_range: tuple | None = None
     adapt_rounds: int = 0
     n_star: int = 2
-    gmres_cycles: int = 8  # host snapshot solver budget once refinement stalls
+    gmres_cycles: int = 8  # GMRES budget of the shared-Green path once refinement stalls
 
 
 WORKLOADS = {
@@ -64,7 +65,7 @@ WORKLOADS = {
     "adjoint48": Workload(4, "adjoint48", 48, 64, 16, (1e1, 1e6), 1e-8, 32, 2000, (1e1, 1e6),
                           m_range=(8, 32)),
     "shell64": Workload(5, "shell64", 64, 1, 48, (1e1, 1e7), 1e-8, 96, 100_000, (1e1, 1e7),
-                        adapt_rounds=3, gmres_cycles=0),
+                        adapt_rounds=3),
 }
 
 

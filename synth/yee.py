@@ -162,6 +162,34 @@ class YeeGrid:
         C.sum_duplicates()
         return C
 
+    def gradient(self) -> sp.csr_matrix:
+        """Interior-edge-by-interior-node incidence G (entries +-1): the edge
+        line integrals of the gradient of a nodal potential that vanishes on
+        the boundary.  Interior node (i,j,k), i,j,k in [1,n-1], has index
+        ((i-1)(n-1) + j-1)(n-1) + k-1.  C G = 0 and G^T G is the 7-point
+        Dirichlet Laplacian."""
+        n, m = self.n, self.n - 1
+
+        def node(i, j, k):
+            ok = (i >= 1) & (i <= m) & (j >= 1) & (j <= m) & (k >= 1) & (k <= m)
+            return np.where(ok, ((i - 1) * m + (j - 1)) * m + (k - 1), -1)
+
+        rows, cols, vals = [], [], []
+        ranges = [(self.ex, (np.arange(n), np.arange(1, n), np.arange(1, n))),
+                  (self.ey, (np.arange(1, n), np.arange(n), np.arange(1, n))),
+                  (self.ez, (np.arange(1, n), np.arange(1, n), np.arange(n)))]
+        for ax, (index, axes) in enumerate(ranges):
+            i, j, k = [a.ravel() for a in np.meshgrid(*axes, indexing="ij")]
+            e = index(i, j, k)
+            d = np.eye(3, dtype=np.int64)[ax]
+            for sign, nd in ((1.0, node(i + d[0], j + d[1], k + d[2])), (-1.0, node(i, j, k))):
+                keep = nd >= 0
+                rows.append(e[keep])
+                cols.append(nd[keep])
+                vals.append(np.full(keep.sum(), sign))
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(self.N, m ** 3))
+
     def rotation_field_dofs(self) -> np.ndarray:
         """(N, 3): column m holds the edge line integrals of e_m x xi.
 
