@@ -1,32 +1,38 @@
 """Benchmark of the MPT reduced-order hot path on one MI355X.
 
-A step is one pass of the whole hot path over the 48^3 single-object workload
-(seeded ellipsoid, sigma 1.5e7, N = 318,096 edge unknowns, 32 snapshots x 3
-directions, TOL 1e-8, M <= 48, 10^4 output frequencies on [1e1, 1e6]):
-  a1 POD basis of D (318,096 x 96 complex)      mpt_pod_basis
-  a2 Galerkin projection + residual Gram         mpt_project
-  a3+a4 sweep: reduced solves, tensors, certificates for 10^4 omegas   mpt_sweep
+Default line: the 64^3 two-material sphere (shell64; steel core mu_r 50,
+sigma 6e6 in an aluminium shell sigma 3.5e7; N = 762,048 edge unknowns; 48
+initial snapshots x 3 directions, TOL 1e-8, M <= 96, 10^5 output frequencies
+on [1e1, 1e7]).  Three adaptive rounds (Algorithm 1) add two frequencies each
+from the certificates (host full-order solves at the chosen frequencies,
+untimed; Lambda / |B_alpha| reported per round against TOL_Delta = 1e-3); then
+a step is one pass of the whole hot path at the final snapshot set:
+  a1 POD basis of D (762,048 x 162 complex)      mpt_pod_basis
+  a2 Galerkin projection + certificate data      mpt_project
+  a3+a4 sweep: reduced solves, tensors, certificates for 10^5 omegas
+        (Hessenberg-triangular pencil form)      mpt_pencil_reduce + mpt_sweep_pencil
   a5 adaptive snapshot selection                 mpt_select_snapshots
-Inputs (snapshots, operator, conductor block) are generated on the host before
-timing and are resident in HBM.  value = output frequencies (tensor +
-certificate each) per second of step time.
+Inputs are generated on the host before timing and are resident in HBM.
+value = output frequencies (tensor + certificate each) per second of step
+time.  The 48^3 single-object step (ellipsoid48, 10^4 omegas, LU sweep) is
+measured after it and reported under "extra".
 
-Two more forms sit beside the plain path (each prints its own JSON line):
+Other forms, each printing its own line:
+  --form plain     the 48^3 single-object step alone
   --form batched   256-object dictionary on 32^3 grids (M ~ U{8..48}, 500-4000
-                   omegas each): one persistent, graph-captured, autotuned launch
-                   (mpt_sweep_batched) against the plain per-object path
+                   omegas each): batched pencil sweep (or the persistent,
+                   graph-captured, autotuned LU launch) against per-object calls
   --form adjoint   64 ellipsoids on 48^3 (M ~ U{8..32}, 2000 omegas): forward
                    sweep + adjoint sweep (dJ/domega, dJ/dsigma) of
                    J = sum |I_ij|^2 + |R~_ij - N0_ij|^2, batched and per object
-For these forms the dictionary's snapshots are refined to 1e-6 relative
-residual (the reduced models stay Galerkin projections of the full operator).
-
-  --form adaptive  64^3 two-material sphere: three adaptive rounds (Algorithm 1)
-                   with host solves at the selected frequencies, then the hot
-                   path at the final snapshot set (M <= 96, 10^5 omegas)
+  --form fmm       full matrix and integration methods on q = U a (48^3)
+  --extras         with the default form: also the batched and adjoint lines
+                   under "extra"
+For the dictionaries the snapshots are refined to 1e-6 relative residual (the
+reduced models stay Galerkin projections of the full operator).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--form plain|batched|adjoint|adaptive] [--objects N]
+                       [--form adaptive|plain|batched|adjoint|fmm] [--objects N]
 """
 from __future__ import annotations
 
@@ -107,10 +113,11 @@ def measured_traffic(kind):
 
 
 def sweep_flops(M):
-    """Algorithmic FP64 flops per (object, omega): complex LU 8/3 M^3, forming A
-    4 M^2, three solves 24 M^2, four reduced mat-vecs on three vectors 96 M^2,
-    quadratic forms and certificate dots O(M)."""
-    return 8.0 / 3.0 * M ** 3 + 4 * M ** 2 + 24 * M ** 2 + 96 * M ** 2 + 200 * M
+    """The per-omega flop count of the sweep as the method states it: complex
+    LU 8/3 M^3, forming A 4 M^2, three solves 24 M^2, K_M a and C_M a 48 M^2,
+    the certificate's mat-vecs with the (2M+3)-square residual Gram 24 (2M+3)^2,
+    i.e. F(M) = 8/3 M^3 + 76 M^2 + 96 (M + 1.5)^2."""
+    return 8.0 / 3.0 * M ** 3 + 76 * M ** 2 + 96 * (M + 1.5) ** 2
 
 
 def pencil_sweep_flops(M):
@@ -137,37 +144,79 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--form", choices=["plain", "batched", "adjoint", "adaptive", "fmm"],
-                    default="plain")
+                    default="adaptive")
     ap.add_argument("--objects", type=int, default=0, help="dictionary size (default: the workload's)")
     ap.add_argument("--sweep", choices=["lu", "pencil"], default=None,
                     help="per-frequency LU of the reduced system, or the Hessenberg-triangular "
-                         "pencil form (reduced once per step); default: lu for one object, "
-                         "pencil for the dictionary")
+                         "pencil form (reduced once per step); default: lu for the 48^3 object, "
+                         "pencil for the 64^3 object and the dictionary")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="adaptive form only: skip the 48^3 plain step reported beside it")
+    ap.add_argument("--extras", action="store_true",
+                    help="adaptive form: also run the batched and adjoint dictionaries")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
-    if args.sweep is None:
-        args.sweep = "pencil" if args.form in ("batched", "adaptive") else "lu"
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    sweep_arg = args.sweep
+    if args.sweep is None:
+        args.sweep = "pencil" if args.form in ("batched", "adaptive") else "lu"
 
     import torch
 
     from paper_2307_05590_amd import mpt
-    from synth import make_problem
 
     mpt.lib()
     dev = torch.device("cuda:0")
     if args.calibrate:
         copy_calibration(dev)
-    if args.form == "adaptive":
-        return bench_adaptive(args)
     if args.form == "fmm":
-        return bench_fmm(args)
-    if args.form != "plain":
-        return bench_dictionary(args)
+        line = bench_fmm(args)
+    elif args.form == "plain":
+        line = bench_plain(args)
+    elif args.form in ("batched", "adjoint"):
+        line = bench_dictionary(args)
+    else:
+        line = bench_adaptive(args)
+        extra = {}
+        if not args.no_extras:
+            torch.cuda.empty_cache()
+            sub = argparse.Namespace(**vars(args))
+            sub.form, sub.no_cpu = "plain", True
+            sub.sweep = sweep_arg or "lu"
+            extra["ellipsoid48_plain"] = summary(bench_plain(sub))
+        if args.extras:
+            for form in ("batched", "adjoint"):
+                torch.cuda.empty_cache()
+                sub = argparse.Namespace(**vars(args))
+                sub.form, sub.no_cpu = form, True
+                sub.sweep = sweep_arg or ("pencil" if form == "batched" else "lu")
+                extra[("dictionary32_" if form == "batched" else "adjoint48_") + form] = \
+                    summary(bench_dictionary(sub))
+        if extra:
+            line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+def summary(line):
+    """The figures of another form's line, to sit under the headline's extra key."""
+    keep = ("metric", "value", "unit", "ms_per_step", "config", "stages_ms", "roofline", "spmm",
+            "plain_path", "alt_path", "snap_residual")
+    return {k: line[k] for k in keep if k in line}
+
+
+def bench_plain(args):
+    """The 48^3 single-object step (ellipsoid48): POD, projection, sweep and
+    selection over 10^4 omegas."""
+    import torch
+
+    from paper_2307_05590_amd import mpt
+    from synth import make_problem
+
+    dev = torch.device("cuda:0")
     t0 = time.time()
     log("generating the ellipsoid48 workload (full-order snapshots on the host) ...")
     p = make_problem("ellipsoid48", verbose=True)
@@ -293,9 +342,10 @@ def main():
                  "frac": round(spmm_gbs / HBM_PEAK_GBS, 4), "launch_ms": round(spmm_ms, 4),
                  "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M),
                  "traffic": measured_traffic("spmm")},
+        "snap_residual": float(p.snap_residual),
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 COPY_BYTES = 1 << 30
@@ -490,7 +540,7 @@ def bench_dictionary(args):
                      "traffic": None, "launch_ms": round(kernel_ms, 4)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def fmm_bytes(N, nnz, M, n_omega):
@@ -594,7 +644,7 @@ def bench_fmm(args):
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(nbytes), "launch_ms": round(ms, 4)},
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def cpu_baseline_dictionary(kept, form, budget_s):
@@ -632,16 +682,30 @@ def cpu_baseline_dictionary(kept, form, budget_s):
                       f"over {done} frequencies in {t:.1f} s"}
 
 
+TOL_DELTA = 1e-3  # Algorithm 1's stopping tolerance in the adaptive sphere study
+
+
+def pod_flops(N, m, M):
+    """Flops of the two-pass POD on MFMA: two Hermitian Grams 4 m^2 N each, the
+    rotation D V 8 m^2 N and the basis U = Q W 8 m M N (complex multiply-add =
+    8 real flops; a Hermitian output counts half)."""
+    return 2 * 4.0 * m * m * N + 8.0 * m * m * N + 8.0 * m * M * N
+
+
 def bench_adaptive(args):
     """Adaptive POD (Algorithm 1) on the 64^3 two-material sphere (steel core
     mu_r 50, sigma 6e6 in an aluminium shell sigma 3.5e7): 48 initial
     snapshots, three rounds of POD + projection + sweep with certificates over
     10^5 omegas + selection of two new frequencies, each followed by host
     full-order solves at those frequencies (untimed), then the timed step: one
-    pass of the hot path at the final snapshot set (M <= 96)."""
+    pass of the hot path at the final snapshot set (M <= 96).  Each round
+    reports Lambda / |B_alpha| against TOL_Delta = 1e-3; the rounds run to
+    the workload's count whatever the rule says, so that the timed work is
+    fixed."""
     import torch
 
     from paper_2307_05590_amd import mpt
+    from paper_2307_05590_amd.adaptive import adaptive_pod
     from synth import make_problem
 
     dev = torch.device("cuda:0")
@@ -649,8 +713,9 @@ def bench_adaptive(args):
     log("shell64: 48 initial snapshots on the 64^3 grid (host) ...")
     p = make_problem("shell64", verbose=True)
     ops = p.ops
-    log(f"generated in {time.time() - t0:.0f} s: N={ops.N} nnz={ops.K.nnz} "
-        f"n_c={ops.cond_idx.size} D={p.D.shape}")
+    t_gen = time.time() - t0
+    log(f"generated in {t_gen:.0f} s: N={ops.N} nnz={ops.K.nnz} n_c={ops.cond_idx.size} "
+        f"D={p.D.shape} max snapshot residual {p.snap_residual:.1e}")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     K = mpt.Csr.from_scipy(ops.K, dev, row_blocks=3)
     c = T(ops.c, torch.float64)
@@ -661,104 +726,174 @@ def bench_adaptive(args):
     S = cert_inputs(p, T)
     omega = T(p.omega, torch.float64)
     tol, cap, nstar = p.wl.tol_sigma, p.wl.m_cap, p.wl.n_star
+    pencil = args.sweep == "pencil"
+
+    def project(U):
+        return mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, *S)
+
+    def solve(new):
+        t1 = time.time()
+        Q = p.add_snapshots(new)
+        log(f"  host snapshots at {new} in {time.time() - t1:.0f} s "
+            f"(max residual so far {p.snap_residual:.1e})")
+        return T(Q, torch.complex128)
+
+    D, snap_h, rounds, _ = adaptive_pod(
+        T(p.D, torch.complex128), p.snap_omega, omega, solve, project, tol_sigma=tol, m_cap=cap,
+        n_star=nstar, volume=ops.volume, tol_delta=TOL_DELTA, max_rounds=p.wl.adapt_rounds,
+        stop=False, sweep=args.sweep, log=log)
+    torch.cuda.synchronize()
+    snap = T(np.sort(snap_h), torch.float64)
+    stages = ["pod", "project", "reduce", "sweep", "select"] if pencil else \
+        ["pod", "project", "sweep", "select"]
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def step(D, snap, record=None, form=None):
-        e = [ev() for _ in range(5)]
+    def step(record=None, form=None):
+        e = [ev() for _ in range(len(stages) + 1)]
         e[0].record()
         U, sig, M = mpt.mpt_pod_basis(D, tol, cap)
         e[1].record()
-        rom = mpt.mpt_project(K, c, ops.eps_h, w, o, vol, ops.alpha, U, cond, *S)
+        rom = project(U)
         e[2].record()
         if (form or args.sweep) == "pencil":
-            out, st = mpt.mpt_sweep_pencil(mpt.mpt_pencil_reduce(rom), omega)
+            pen = mpt.mpt_pencil_reduce(rom)
+            e[3].record()
+            out, st = mpt.mpt_sweep_pencil(pen, omega)
         else:
+            e[3].record()
             out, st = mpt.mpt_sweep(rom, omega)
-        e[3].record()
+        e[len(stages) - 1].record()
         new, lam, Lmax = mpt.mpt_select_snapshots(omega, out, snap, nstar)
-        e[4].record()
+        e[len(stages)].record()
         if record is not None:
             record.append(e)
-        return M, sig, out, st, new, Lmax
+        return M, out, st, U
 
-    rounds = []
-    for r in range(p.wl.adapt_rounds):
-        D = T(p.D, torch.complex128)
-        snap = T(np.sort(p.snap_omega), torch.float64)
-        rec = []
-        M, sig, out, st, new, Lmax = step(D, snap, rec)
-        torch.cuda.synchronize()
-        assert int(st.abs().max()) == 0, "singular reduced system"
-        new_h = new.cpu().numpy()
-        new_h = new_h[np.isfinite(new_h)]
-        ms = [rec[0][i].elapsed_time(rec[0][i + 1]) for i in range(4)]
-        rounds.append({"columns": int(p.D.shape[1]), "M": int(M), "Lambda": float(Lmax.item()),
-                       "new_omega": [float(x) for x in new_h], "gpu_ms": round(sum(ms), 3)})
-        log(f"round {r + 1}: {p.D.shape[1]} columns, M={M}, Lambda={Lmax.item():.3e}, "
-            f"new omega {new_h}, GPU {sum(ms):.2f} ms (pod/project/sweep/select {ms})")
-        del D
-        t1 = time.time()
-        p.add_snapshots(new_h)
-        log(f"  host snapshots at the new frequencies in {time.time() - t1:.0f} s")
-    D = T(p.D, torch.complex128)
-    snap = T(np.sort(p.snap_omega), torch.float64)
     for _ in range(args.warmup):
-        step(D, snap)
+        step()
     torch.cuda.synchronize()
     rec = []
     t1 = time.perf_counter()
     for _ in range(args.steps):
-        M, sig, out, st, new, Lmax = step(D, snap, rec)
+        M, out, st, U = step(rec)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
     assert int(st.abs().max()) == 0, "singular reduced system"
-    stages = ["pod", "project", "sweep", "select"]
     ms = {s_: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in rec])) for i, s_ in
           enumerate(stages)}
     n_omega = omega.numel()
+    ms_step = 1e3 * elapsed / args.steps
     value = n_omega / (elapsed / args.steps)
-    pencil = args.sweep == "pencil"
-    fpu = pencil_sweep_flops(M) if pencil else sweep_flops(M)
-    sweep_tf = fpu * n_omega / (ms["sweep"] * 1e-3) / 1e12
-    log(f"final: {p.D.shape[1]} columns, M={M}, ms/step {1e3 * elapsed / args.steps:.3f}, {ms}")
+    log(f"final: {D.shape[1]} columns, M={M}, ms/step {ms_step:.3f}, {ms}")
     # the other sweep form on the same final snapshot set, for comparison
     alt_form = "lu" if pencil else "pencil"
-    step(D, snap, form=alt_form)
+    step(form=alt_form)
     torch.cuda.synchronize()
     arec = []
     for _ in range(args.steps):
-        step(D, snap, arec, form=alt_form)
+        step(arec, form=alt_form)
     torch.cuda.synchronize()
-    alt_sweep = float(np.mean([e[2].elapsed_time(e[3]) for e in arec]))
-    alt_step = float(np.mean([e[0].elapsed_time(e[4]) for e in arec]))
-    cpu = None if args.no_cpu else cpu_baseline(p, args.cpu_seconds)
+    alt_sweep = float(np.mean([e[2].elapsed_time(e[4]) for e in arec]))
+    alt_step = float(np.mean([e[0].elapsed_time(e[len(stages)]) for e in arec]))
+    # the SpMM of the projection on its own (HBM roofline)
+    for _ in range(3):
+        mpt.mpt_spmm(K, U)
+    torch.cuda.synchronize()
+    es, ee = ev(), ev()
+    es.record()
+    for _ in range(10):
+        mpt.mpt_spmm(K, U)
+    ee.record()
+    torch.cuda.synchronize()
+    spmm_ms = es.elapsed_time(ee) / 10
+    spmm_gbs = spmm_bytes(ops.N, ops.K.nnz, M) / (spmm_ms * 1e-3) / 1e9
+
+    sweep_ms = ms["reduce"] + ms["sweep"] if pencil else ms["sweep"]
+    F = sweep_flops(M)
+    stage_tf = F * n_omega / (sweep_ms * 1e-3) / 1e12
+    m_cols = int(D.shape[1])
+    pod_tf = pod_flops(ops.N, m_cols, M) / (ms["pod"] * 1e-3) / 1e12
+    kern = {"kernel": "k_sweep_pencil (Hessenberg-triangular solves, MFMA quadratic forms, "
+                      "tensors, certificates)",
+            "flops_per_unit": pencil_sweep_flops(M), "launch_ms": round(ms["sweep"], 4)} if pencil \
+        else {"kernel": "k_sweep_big" if M > 64 else "k_sweep", "flops_per_unit": sweep_flops(M),
+              "launch_ms": round(ms["sweep"], 4)}
+    kern["achieved"] = round(kern["flops_per_unit"] * n_omega / (ms["sweep"] * 1e-3) / 1e12, 3)
+    kern["frac"] = round(kern["achieved"] / FP64_MFMA_PEAK_TF, 4)
+    kern["unit"] = "TFLOP/s"
+    cpu = None if args.no_cpu else cpu_baselines(p, args.cpu_seconds)
     line = {
         "metric": "MPT tensors/sec (3x3 + error cert per omega per object)",
         "value": round(value, 1), "unit": "tensors/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "shell64: steel core (mu_r 50, sigma 6e6) in an aluminium shell "
                                "(sigma 3.5e7) on a 64^3 Yee grid, 48 + 3x2 adaptive snapshots, "
                                "TOL 1e-8, M<=96, 1e5 omegas",
-                   "N": int(ops.N), "nnz": int(ops.K.nnz), "n_snap": int(p.snap_omega.size),
-                   "M": int(M), "n_omega": int(n_omega), "rounds": rounds},
+                   "N": int(ops.N), "nnz": int(ops.K.nnz), "n_c": int(ops.cond_idx.size),
+                   "n_snap": int(snap_h.size), "columns": m_cols, "M": int(M),
+                   "n_omega": int(n_omega), "volume_B_alpha": ops.volume, "rounds": rounds},
+        "snap_residual": float(p.snap_residual),
+        "host_generation_s": round(t_gen, 1),
         "stages_ms": {k: round(v, 4) for k, v in ms.items()},
+        "dominant_stage": max(ms, key=ms.get),
         "sweep_form": args.sweep,
         "alt_path": {"sweep_form": alt_form, "sweep_ms": round(alt_sweep, 4),
                      "step_ms_gpu": round(alt_step, 4)},
-        "roofline": {"kernel": ("pencil reduction + sweep on the Hessenberg-triangular pencil"
-                                if pencil else
-                                "sweep (M > 64: LDS-resident system, one workgroup per omega)"
-                                if M > 64 else "sweep (k_sweep)"),
-                     "bound": "mfma" if pencil else "alu",
-                     "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF, "unit": "TFLOP/s",
-                     "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4), "traffic": None,
-                     "flops_per_unit": fpu, "units_per_launch": int(n_omega),
-                     "launch_ms": round(ms["sweep"], 4)},
+        "roofline": {"kernel": ("sweep stage a3+a4: k_pencil_reduce + k_pencil_z + k_sweep_pencil"
+                                if pencil else kern["kernel"]),
+                     "bound": "mfma", "achieved": round(stage_tf, 3), "peak": FP64_MFMA_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": round(stage_tf / FP64_MFMA_PEAK_TF, 4),
+                     "traffic": None, "flops_per_unit": round(F),
+                     "flops_basis": "F(M) = 8/3 M^3 + 76 M^2 + 96 (M+1.5)^2 per omega",
+                     "units_per_launch": int(n_omega), "launch_ms": round(sweep_ms, 4)},
+        "stage_rooflines": {
+            "sweep_kernel": kern,
+            "pod": {"kernels": "k_gram_chunk x2, eigen chain, k_rotate x2", "bound": "mfma",
+                    "flops": pod_flops(ops.N, m_cols, M), "achieved": round(pod_tf, 3),
+                    "unit": "TFLOP/s", "frac": round(pod_tf / FP64_MFMA_PEAK_TF, 4),
+                    "ms": round(ms["pod"], 4)},
+            "spmm": {"kernel": "k_spmm (Y = K U)", "bound": "hbm", "achieved": round(spmm_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(spmm_gbs / HBM_PEAK_GBS, 4),
+                     "launch_ms": round(spmm_ms, 4),
+                     "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M)}},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), and the number of CPUs it reports."""
+    import subprocess
+    name = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                name = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baselines(p, budget_s):
+    """The oracle's step on the host at every thread the BLAS pool has and at
+    one thread (each with its own budget), with the CPU model."""
+    from threadpoolctl import threadpool_limits
+
+    log("CPU oracle baseline (all threads) ...")
+    many = cpu_baseline(p, budget_s)
+    log(f"  {many['value']} tensors/s on {many['cores']} threads; one thread ...")
+    with threadpool_limits(limits=1):
+        one = cpu_baseline(p, budget_s)
+    log(f"  {one['value']} tensors/s on one thread")
+    name, ncpu = cpu_model()
+    many["one_thread"] = {"value": one["value"], "cores": one["cores"], "sample": one["sample"]}
+    many["cpu_model"] = name
+    many["nproc"] = ncpu
+    return many
 
 
 def cpu_baseline(p, budget_s):

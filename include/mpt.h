@@ -119,11 +119,13 @@ typedef struct {
  * (FP64 MFMA Gram and rotation): pass 1 eigen-decomposes D^H D by Householder
  * tridiagonalisation, multisection and inverse iteration, pass 2 the Gram of
  * the rotated snapshots by Jacobi (relative accuracy of the small singular
- * values).  Then truncation: M = #{s_m/s_1 >= tol_sigma},
+ * values).  Then truncation: M = #{s_m/s_1 >= max(tol_sigma, 1e-12)},
  * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
- * a cluster).  Writes U (N x M_cap, ldU >= M_cap; columns >= M are zero),
- * sigma (ncol, descending).  *M_out is a HOST pointer: the call synchronises
- * the stream to return M.  ncol <= 192.
+ * a cluster).  Relative singular values under 1e-12 are rounding noise of
+ * FP64 data, so a fixed-rank request (tol_sigma = 0) stops at the numerical
+ * rank.  Writes U (N x M_cap, ldU >= M_cap; columns >= M are zero), sigma
+ * (ncol, descending).  *M_out is a HOST pointer: the call synchronises the
+ * stream to return M.  ncol <= 192.
  */
 size_t mpt_pod_basis_ws_size(int64_t N, int ncol);
 mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N, int ncol,

@@ -35,10 +35,17 @@ ALPHA_LB = 2.0 / (3.0 + np.sqrt(10.0))
 
 
 # ---------------------------------------------------------------- POD (a1)
+RANK_FLOOR = 1e-12  # relative singular values below this are rounding noise
+
+
 def truncation_rank(s, tol, m_cap, cluster=1e-8) -> int:
-    """M from the singular values s (descending), Section 4.1 with the cap."""
+    """M from the singular values s (descending), Section 4.1 with the cap.
+    A tolerance below RANK_FLOOR counts as RANK_FLOOR: singular values under
+    1e-12 s_1 carry no content of D in FP64 (a backward-stable SVD moves every
+    one by ~1e-16 s_1), so even a fixed-rank request (tol = 0) stops at the
+    numerical rank."""
     s = np.asarray(s, float)
-    M = int(np.count_nonzero(s / s[0] >= tol))
+    M = int(np.count_nonzero(s / s[0] >= max(tol, RANK_FLOOR)))
     M = min(M, int(m_cap), s.size)
     while 0 < M < s.size and s[M] / s[M - 1] > 1.0 - cluster:
         M -= 1

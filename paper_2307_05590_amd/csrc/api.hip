@@ -259,6 +259,9 @@ extern "C" int mpt_max_reduced_dim(void) { return 96; }
 constexpr int kJacobiSweeps = 40;
 // absolute rotation floor of the pass-2 Jacobi (times max |g_ii|)
 constexpr double kJacobiFloor = 1e-30;
+// relative singular values below this are rounding noise of FP64 data: the
+// truncation never keeps them, even for a fixed-rank request (tol_sigma = 0)
+constexpr double kRankFloor = 1e-12;
 
 static void pod_layout(int64_t N, int m, size_t* off) {
   // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 jacobi record, 9 end
@@ -306,7 +309,6 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   int* info = reinterpret_cast<int*>(w + off[6]);
   int* Mdev = reinterpret_cast<int*>(w + off[7]);
   void* jws = w + off[8];
-  const double tol2 = 4.0 * m * 2.220446049250313e-16;
   hipStream_t st = h->stream;
   // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
@@ -315,10 +317,11 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
   // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
   HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps, tol2, kJacobiFloor, st));
+  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps,
+                       4.0 * m * 2.220446049250313e-16, kJacobiFloor, st));
   hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
-                     reinterpret_cast<const double2*>(V0), m, tol_sigma, Mc, sigma,
-                     reinterpret_cast<double2*>(W), Mdev);
+                     reinterpret_cast<const double2*>(V0), m, std::max(tol_sigma, kRankFloor), Mc,
+                     sigma, reinterpret_cast<double2*>(W), Mdev);
   HIP_OK(hipGetLastError());
   // U = Q1 W (columns >= M are zero); remaining columns up to M_cap cleared
   HIP_OK(rotate_launch(Q1, m, N, m, W, Mc, Mc, U, ldU, st));

@@ -163,7 +163,8 @@ class Problem:
         return self.draw.M_fixed if self.draw.M_fixed is not None else self.wl.m_cap
 
     def add_snapshots(self, new_omega, tol=1e-12):
-        """Full-order solves at new frequencies; appends to D (Alg. 1 update step)."""
+        """Full-order solves at new frequencies; appends to D (Alg. 1 update
+        step) and returns the new columns [q_1(new) | q_2(new) | q_3(new)]."""
         Q, hist = self.solver.snapshots(np.asarray(new_omega, float), self.w, tol=tol, max_iter=12,
                                         gmres_cycles=self.wl.gmres_cycles)
         K0 = self.snap_omega.size
@@ -175,6 +176,7 @@ class Problem:
         self.D = np.ascontiguousarray(np.concatenate(blocks, 1))
         self.snap_omega = np.concatenate([self.snap_omega, np.asarray(new_omega, float)])
         self.snap_residual = max(self.snap_residual, hist[-1])
+        return Q
 
 
 # half-width of the box that contains every object of a dictionary workload

@@ -492,7 +492,12 @@ def test_pod_basis_matches_svd(mpt, case, tol, cap):
     sig = sig.cpu().numpy()
     U = U.cpu().numpy()
     assert M == M_o
-    assert np.all(np.abs(sig - s_o) <= 1e-10 * s_o + 1e-13 * s_o[0])
+    # singular values from the truncation's cut up are resolved; the rest are
+    # only bounded by it (pass 2 does not rotate pairs of columns far below)
+    cut = max(tol, R.RANK_FLOOR) * s_o[0]
+    live = s_o >= cut
+    assert np.all(np.abs(sig - s_o)[live] <= 1e-10 * s_o[live] + 1e-13 * s_o[0])
+    assert np.all(sig[~live] < cut)
     assert np.abs(U.conj().T @ U - np.eye(M)).max() <= 1e-12
     Pg = U @ (U.conj().T @ D)
     Po = U_o @ (U_o.conj().T @ D)
@@ -769,6 +774,18 @@ def _gpu_rom(mpt, p, tol, cap):
     return rom, U.cpu().numpy()
 
 
+def _gpu_rom_on(mpt, p, U):
+    """GPU projection of a generated problem onto a given host basis U."""
+    ops = p.ops
+    lam, Vt = p.cond_spectrum()
+    return mpt.mpt_project(mpt.Csr.from_scipy(ops.K, row_blocks=3), _dev(ops.c, torch.float64),
+                           ops.eps_h, _dev(p.w, torch.float64),
+                           _dev(p.o, torch.float64) if np.any(p.o) else None,
+                           _dev(ops.vol, torch.float64), ops.alpha, _dev(U, torch.complex128),
+                           _dev(ops.cond_idx, torch.int32), _dev(Vt, torch.float64),
+                           _dev(lam, torch.float64), _dev(p.s_ref, torch.float64))
+
+
 def _oracle_on(p, U):
     """The oracle's reduced model on the GPU's basis U (same span, same basis)."""
     from oracle.grid import FullOrder
@@ -904,10 +921,15 @@ def test_batched_adjoint_matches_oracle(mpt, adj48):
 def test_shell64_m96_matches_oracle(mpt):
     """The 64^3 two-material sphere at M = 96 (the largest reduced model):
     the LDS sweep for M > 64 and the pencil form, both against the oracle on
-    the same basis at every 400th of 10^5 frequencies."""
+    the same basis at every 400th of 10^5 frequencies.  The 144 snapshots have
+    numerical rank 45 at TOL 1e-8 (and the POD stops at the numerical rank),
+    so the basis here is the first 96 left singular vectors of a host SVD:
+    orthonormal, the last ones spanning directions of tiny singular value,
+    and the reduced model the Galerkin projection onto them."""
     from synth import make_problem
     p = make_problem("shell64", verbose=True)
-    rom, U = _gpu_rom(mpt, p, p.wl.tol_sigma, p.wl.m_cap)
+    U = np.linalg.svd(p.D, full_matrices=False)[0][:, :96]
+    rom = _gpu_rom_on(mpt, p, U)
     assert rom.M == 96
     om = p.omega[::400]
     w = _dev(om, torch.float64)
@@ -1036,8 +1058,13 @@ def test_full_size_ellipsoid48_sampled(mpt):
     U_o, s_o, M_o = R.pod_basis(p.D, tol, cap)
     assert M == M_o
     s_g = sig.cpu().numpy()
-    k = int(np.sum(s_o / s_o[0] >= 1e-10))
-    assert np.all(np.abs(s_g[:k] - s_o[:k]) <= 1e-9 * s_o[:k])
+    # the oracle's LAPACK SVD moves each singular value by up to ~eps ||D||
+    # (Weyl), so small ones are compared to that floor as well
+    k = int(np.sum(s_o / s_o[0] >= max(tol, R.RANK_FLOOR)))
+    dsig = np.abs(s_g[:k] - s_o[:k])
+    print(f"full size sigma: max |d sigma| / sigma_1 {dsig.max() / s_o[0]:.1e} "
+          f"(sigma_M / sigma_1 = {s_o[k - 1] / s_o[0]:.1e})", flush=True)
+    assert np.all(dsig <= 1e-9 * s_o[:k] + 64 * 2.2e-16 * s_o[0])
     rom_o, cert_o, _ = oracle_rom(fo, U_o, p.w, p.o, spec, ops.cond_idx, s_ref)
     ref, a_o = R.sweep(rom_o, om, cert_o, ops.alpha)
     sc = term_scales(ref, om, rom_o["N0"], rom_o["E"], ops.alpha)

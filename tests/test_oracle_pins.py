@@ -111,6 +111,18 @@ def test_truncation_rule_examples():
     assert R.truncation_rank(s, 1e-10, 99) == 6
 
 
+def test_fixed_rank_stops_at_the_numerical_rank():
+    """tol = 0 keeps every singular value down to the rounding floor of FP64
+    and none below: a rank-5 matrix of 12 columns gives M = 5, and the basis
+    spans its column space."""
+    rng = np.random.default_rng(3)
+    A = (rng.standard_normal((400, 5)) + 1j * rng.standard_normal((400, 5))) @ \
+        (rng.standard_normal((5, 12)) * np.logspace(0, -9, 5)[:, None])
+    U, s, M = R.pod_basis(A, 0.0, 12)
+    assert M == 5 and s[5] / s[0] < 1e-14 and s[4] / s[0] > 1e-11
+    assert np.abs(U @ (U.conj().T @ A) - A).max() <= 1e-13 * np.abs(A).max()
+
+
 def test_pod_basis_reconstructs_and_is_orthonormal():
     c = _cases.ellipsoid16()
     U, s, M = R.pod_basis(c.D, 1e-6, 99)
