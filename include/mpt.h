@@ -115,11 +115,16 @@ typedef struct {
  *     "Form D_i" / "obtain the TSVDs").
  * D: N x ncol complex (ldD >= ncol), the joint snapshot matrix
  *    [q_1(w_1..K) | q_2(...) | q_3(...)].
- * Thin SVD by two passes of Gram / Hermitian eigen-decomposition / rotation
+ * Thin SVD by passes of Gram / Hermitian eigen-decomposition / rotation
  * (FP64 MFMA Gram and rotation): pass 1 eigen-decomposes D^H D by Householder
- * tridiagonalisation, multisection and inverse iteration, pass 2 the Gram of
- * the rotated snapshots by Jacobi (relative accuracy of the small singular
- * values).  Then truncation: M = #{s_m/s_1 >= max(tol_sigma, 1e-12)},
+ * tridiagonalisation, multisection and inverse iteration; the columns D V_T
+ * of its tail (eigenvalues under 1e-8 of the largest, which pass 1 leaves
+ * mixed) get the same treatment on their own Gram; pass 2 diagonalises the
+ * Gram of the rotated snapshots by Jacobi (relative accuracy of the small
+ * singular values), leaving out columns whose norms are under 1e-13 of the
+ * largest (reported by their norms).  The call synchronises the stream
+ * twice on the way to size these steps.
+ * Then truncation: M = #{s_m/s_1 >= max(tol_sigma, 1e-12)},
  * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
  * a cluster).  Relative singular values under 1e-12 are rounding noise of
  * FP64 data, so a fixed-rank request (tol_sigma = 0) stops at the numerical

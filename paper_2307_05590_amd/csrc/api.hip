@@ -82,21 +82,101 @@ namespace mpt {
 
 // sort eigenvalues (descending), singular values, truncation rank and the
 // scaled rotation W (m x Mcap): W[:, j] = V[:, idx_j] / sigma_j for j < M
-__global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __restrict__ V, int m,
-                               double tol, int Mcap, double* __restrict__ sigma,
-                               double2* __restrict__ W, int* __restrict__ Mout) {
+// Number of pass-1 eigenvalues (ascending) under h times the largest: the
+// tail whose eigenvectors pass 1 leaves mixed (absolute accuracy eps lam_max).
+__global__ void k_pod_tail(const double* __restrict__ lam, int m, double h, int* __restrict__ nt) {
+  if (threadIdx.x == 0) {
+    int n = 0;
+    while (n < m && lam[n] < h * lam[m - 1]) ++n;
+    nt[0] = n;
+  }
+}
+
+// V' = [V0_T VT | V0_H]: the tail columns of the pass-1 eigenvectors turned
+// by the eigenvectors VT (nt x nt) of the tail's own Gram
+__global__ void k_pod_tail_mix(const double2* __restrict__ V0, int m, int nt,
+                               const double2* __restrict__ VT, double2* __restrict__ Vout) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * m; e += gridDim.x * blockDim.x) {
+    const int r = e / m, j = e % m;
+    double2 acc = make_double2(0.0, 0.0);
+    if (j < nt) {
+      for (int k = 0; k < nt; ++k) acc = cfma(acc, V0[(size_t)r * m + k], VT[(size_t)k * nt + j]);
+    } else {
+      acc = V0[(size_t)r * m + j];
+    }
+    Vout[e] = acc;
+  }
+}
+
+// Columns of the rotated snapshots that enter the Jacobi: squared norm >=
+// floor * the largest (the others lie under the numerical rank floor and
+// no truncation keeps them).  Compacts their Gram into Gc (n' x n', in
+// index order) and lists them in live.
+__global__ void k_pod_live(const double2* __restrict__ G, int m, double floor,
+                           double2* __restrict__ Gc, int* __restrict__ live,
+                           int* __restrict__ nlive) {
   __shared__ int idx[192];
+  __shared__ int cnt;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double dmax = 0.0;
+    for (int j = 0; j < m; ++j) dmax = fmax(dmax, G[(size_t)j * m + j].x);
+    int n = 0;
+    for (int j = 0; j < m; ++j)
+      if (dmax > 0.0 && G[(size_t)j * m + j].x >= floor * dmax) idx[n++] = j;
+    cnt = n;
+    nlive[0] = n;
+  }
+  __syncthreads();
+  const int n = cnt;
+  for (int e = t; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    Gc[e] = G[(size_t)idx[r] * m + idx[c]];
+  }
+  for (int j = t; j < n; j += blockDim.x) live[j] = idx[j];
+}
+
+// Singular values of all m columns (the Jacobi's n eigenvalues and the left-
+// out columns' squared norms), sorted descending; M by the truncation rule;
+// W (m x Mcap) = the kept eigenvectors scattered back to the m columns of the
+// rotated snapshots and divided by their singular values.
+__global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __restrict__ V,
+                               int n, const int* __restrict__ live,
+                               const double2* __restrict__ G, int m, double tol, int Mcap,
+                               double* __restrict__ sigma, double2* __restrict__ W,
+                               int* __restrict__ Mout) {
+  __shared__ int src[192];   // sorted entry -> eigenpair (>= 0) or -1 - left-out column
   __shared__ double sv[192];
+  __shared__ double val[192];
+  __shared__ int code[192];
+  __shared__ int pos[192];   // column -> its row of V, or -1 when left out
   __shared__ int Msh;
   const int t = threadIdx.x;
+  if (t < m) pos[t] = -1;
+  __syncthreads();
+  if (t < n) pos[live[t]] = t;
+  __syncthreads();
+  if (t == 0) {  // entries: the n eigenvalues, then the left-out columns in order
+    int k = n;
+    for (int j = 0; j < m; ++j)
+      if (pos[j] < 0) {
+        val[k] = G[(size_t)j * m + j].x;
+        code[k++] = -1 - j;
+      }
+  }
+  if (t < n) {
+    val[t] = lam[t];
+    code[t] = t;
+  }
+  __syncthreads();
   if (t < m) {
-    const double li = lam[t];
+    const double li = val[t];
     int rank = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = lam[j];
+      const double lj = val[j];
       if (lj > li || (lj == li && j < t)) ++rank;
     }
-    idx[rank] = t;
+    src[rank] = code[t];
     sv[rank] = sqrt(fmax(li, 0.0));
   }
   __syncthreads();
@@ -108,6 +188,11 @@ __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __
         if (sv[j] / s1 >= tol) ++M;
     M = min(M, min(Mcap, m));
     while (M > 0 && M < m && sv[M] / sv[M - 1] > 1.0 - 1e-8) --M;
+    for (int j = 0; j < M; ++j)  // a left-out column is never kept
+      if (src[j] < 0) {
+        M = j;
+        break;
+      }
     Msh = M;
     *Mout = M;
   }
@@ -116,12 +201,12 @@ __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __
   for (int e = t; e < m * Mcap; e += blockDim.x) {
     const int r = e / Mcap, j = e % Mcap;
     double2 v = make_double2(0.0, 0.0);
-    if (j < Msh) {
-      const double2 x = V[r * m + idx[j]];
+    if (j < Msh && pos[r] >= 0) {
+      const double2 x = V[(size_t)pos[r] * n + src[j]];
       const double inv = 1.0 / sv[j];
       v = make_double2(x.x * inv, x.y * inv);
     }
-    W[r * Mcap + j] = v;
+    W[(size_t)r * Mcap + j] = v;
   }
 }
 
@@ -211,7 +296,7 @@ extern "C" mpt_status mpt_create(int device, void* hip_stream, mpt_handle* out) 
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       ncu > 0)
     h->n_cu = ncu;
-  if (hipHostMalloc(reinterpret_cast<void**>(&h->host_M), sizeof(int), 0) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->host_M), 4 * sizeof(int), 0) != hipSuccess) {
     delete h;
     return MPT_E_HIP;
   }
@@ -263,8 +348,16 @@ constexpr double kJacobiFloor = 1e-30;
 // truncation never keeps them, even for a fixed-rank request (tol_sigma = 0)
 constexpr double kRankFloor = 1e-12;
 
+// pass-1 eigenvalues under this times the largest form the tail that gets a
+// Gram and an eigen-decomposition of its own before pass 2
+constexpr double kTailRel = 1e-8;
+// pass-2 columns with squared norms under this times the largest stay out of
+// the Jacobi: their singular values lie under 1e-13 s_1, below kRankFloor
+constexpr double kLiveFloor = 1e-26;
+
 static void pod_layout(int64_t N, int m, size_t* off) {
-  // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 jacobi record, 9 end
+  // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 eigen ws,
+  // 9 compact Gram, 10 live columns, 11 end
   size_t o = 0;
   off[0] = o; o = align256(o + (size_t)m * m * 16);
   off[1] = o; o = align256(o + (size_t)m * m * 16);
@@ -275,14 +368,16 @@ static void pod_layout(int64_t N, int m, size_t* off) {
   off[6] = o; o = align256(o + 64);
   off[7] = o; o = align256(o + 64);
   off[8] = o; o = align256(o + std::max(jacobi_ws_size(m, kJacobiSweeps), tridiag_ws_size(m)));
-  off[9] = o;
+  off[9] = o; o = align256(o + (size_t)m * m * 16);
+  off[10] = o; o = align256(o + (size_t)m * 4);
+  off[11] = o;
 }
 
 extern "C" size_t mpt_pod_basis_ws_size(int64_t N, int ncol) {
   if (N <= 0 || ncol <= 0) return 0;
-  size_t off[10];
+  size_t off[12];
   pod_layout(N, ncol, off);
-  return off[9];
+  return off[11];
 }
 
 extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N,
@@ -297,7 +392,7 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(hipSetDevice(h->device));
   const int m = ncol;
   const int Mc = std::min(M_cap, m);
-  size_t off[10];
+  size_t off[12];
   pod_layout(N, m, off);
   char* w = reinterpret_cast<char*>(ws);
   double* G0 = reinterpret_cast<double*>(w + off[0]);
@@ -309,18 +404,51 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   int* info = reinterpret_cast<int*>(w + off[6]);
   int* Mdev = reinterpret_cast<int*>(w + off[7]);
   void* jws = w + off[8];
+  double* Gc = reinterpret_cast<double*>(w + off[9]);
+  int* live = reinterpret_cast<int*>(w + off[10]);
   hipStream_t st = h->stream;
-  // pass 1: G0 = D^H D, eigenvectors V0, Q1 = D V0
+  // pass 1: G0 = D^H D, eigenvectors V0 (absolute accuracy eps lam_max)
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
   HIP_OK(hipMemsetAsync(info, 0, 4 * sizeof(int), st));
   HIP_OK(tridiag_eig_launch(G0, m, V0, lam, jws, st));
-  HIP_OK(rotate_launch(D, ldD, N, m, V0, m, m, Q1, m, st));
-  // pass 2 on the rotated snapshots (graded Gram): G1 = Q1^H Q1
+  // the tail (pass-1 eigenvalues under kTailRel lam_max) is an arbitrary
+  // mixture of the small singular directions: its columns D V0_T get a Gram
+  // and an eigen-decomposition of their own, which resolves them on their
+  // scale, so that the pass-2 Gram is close to diagonal and the Jacobi
+  // converges in a few sweeps
+  hipLaunchKernelGGL(k_pod_tail, dim3(1), dim3(64), 0, st, lam, m, kTailRel, Mdev + 1);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(h->host_M + 1, Mdev + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const int nt = h->host_M[1];
+  const double* Vr = V0;
+  if (nt >= 2) {
+    HIP_OK(rotate_launch(D, ldD, N, m, V0, m, nt, Q1, nt, st));            // D V0_T
+    HIP_OK(gram_launch(Q1, nt, Q1, nt, N, nt, nt, Gc, nt, gws, st));        // its Gram
+    HIP_OK(tridiag_eig_launch(Gc, nt, W, lam, jws, st));                    // VT
+    hipLaunchKernelGGL(k_pod_tail_mix, dim3((m * m + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(V0), m, nt,
+                       reinterpret_cast<const double2*>(W), reinterpret_cast<double2*>(G0));
+    HIP_OK(hipGetLastError());
+    Vr = G0;
+  }
+  HIP_OK(rotate_launch(D, ldD, N, m, Vr, m, m, Q1, m, st));                 // Q1 = D V'
+  // pass 2 on the rotated snapshots (graded Gram): Jacobi on the columns
+  // above the floor (relative accuracy of the small singular values)
   HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
-  HIP_OK(jacobi_launch(G0, m, V0, lam, info + 1, jws, kJacobiSweeps,
-                       4.0 * m * 2.220446049250313e-16, kJacobiFloor, st));
+  hipLaunchKernelGGL(k_pod_live, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(G0), m, kLiveFloor,
+                     reinterpret_cast<double2*>(Gc), live, Mdev + 1);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(h->host_M + 1, Mdev + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const int nl = h->host_M[1];
+  if (nl > 0)
+    HIP_OK(jacobi_launch(Gc, nl, V0, lam, info + 1, jws, kJacobiSweeps,
+                         4.0 * nl * 2.220446049250313e-16, kJacobiFloor, st));
   hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
-                     reinterpret_cast<const double2*>(V0), m, std::max(tol_sigma, kRankFloor), Mc,
+                     reinterpret_cast<const double2*>(V0), nl, live,
+                     reinterpret_cast<const double2*>(G0), m, std::max(tol_sigma, kRankFloor), Mc,
                      sigma, reinterpret_cast<double2*>(W), Mdev);
   HIP_OK(hipGetLastError());
   // U = Q1 W (columns >= M are zero); remaining columns up to M_cap cleared
