@@ -122,15 +122,15 @@ typedef struct {
  * mixed) get the same treatment on their own Gram; pass 2 diagonalises the
  * Gram of the rotated snapshots by Jacobi (relative accuracy of the small
  * singular values), leaving out columns whose norms are under 1e-13 of the
- * largest (reported by their norms).  The call synchronises the stream
- * twice on the way to size these steps.
+ * largest (reported by their norms).
  * Then truncation: M = #{s_m/s_1 >= max(tol_sigma, 1e-12)},
  * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
  * a cluster).  Relative singular values under 1e-12 are rounding noise of
  * FP64 data, so a fixed-rank request (tol_sigma = 0) stops at the numerical
  * rank.  Writes U (N x M_cap, ldU >= M_cap; columns >= M are zero), sigma
  * (ncol, descending).  *M_out is a HOST pointer: the call synchronises the
- * stream to return M.  ncol <= 192.
+ * stream to learn M (as it does twice before to size its steps); U is then
+ * formed on the stream, complete in stream order.  ncol <= 192.
  */
 size_t mpt_pod_basis_ws_size(int64_t N, int ncol);
 mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N, int ncol,

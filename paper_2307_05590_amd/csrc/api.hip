@@ -451,16 +451,19 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
                      reinterpret_cast<const double2*>(G0), m, std::max(tol_sigma, kRankFloor), Mc,
                      sigma, reinterpret_cast<double2*>(W), Mdev);
   HIP_OK(hipGetLastError());
-  // U = Q1 W (columns >= M are zero); remaining columns up to M_cap cleared
-  HIP_OK(rotate_launch(Q1, m, N, m, W, Mc, Mc, U, ldU, st));
-  if (M_cap > Mc) HIP_OK(hipMemset2DAsync(reinterpret_cast<char*>(U) + (size_t)Mc * 16, ldU * 16, 0,
-                                          (size_t)(M_cap - Mc) * 16, N, st));
+  // M to the host, then U = Q1 W on the M kept columns; columns M..M_cap-1
+  // cleared
   HIP_OK(hipMemcpyAsync(h->host_M, Mdev, sizeof(int), hipMemcpyDeviceToHost, st));
   int hinfo[4] = {0, 0, 0, 0};
   HIP_OK(hipMemcpyAsync(hinfo, info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  *M_out = *h->host_M;
+  const int M = *h->host_M;
   if (hinfo[0] < 0 || hinfo[1] < 0) return fail(h, MPT_E_NOTPD, "Jacobi did not converge");
+  if (M > 0) HIP_OK(rotate_launch(Q1, m, N, m, W, Mc, M, U, ldU, st));
+  if (M_cap > M)
+    HIP_OK(hipMemset2DAsync(reinterpret_cast<char*>(U) + (size_t)M * 16, ldU * 16, 0,
+                            (size_t)(M_cap - M) * 16, N, st));
+  *M_out = M;
   return MPT_OK;
 }
 

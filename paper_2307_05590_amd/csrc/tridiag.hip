@@ -305,59 +305,83 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_tri_invit(const double* __re
 }
 
 // 5. two passes of modified Gram-Schmidt over the rows of Z in decreasing
-// eigenvalue order (lam ascending, so row n-1 first)
-template <bool SHARED>
-__global__ __launch_bounds__(kTriThreads) void k_tri_mgs(double* __restrict__ Zg, int n) {
-  extern __shared__ double zs[];
-  double* Z = SHARED ? zs : Zg;
-  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
-  if (SHARED)
-    for (int i = tid; i < n * n; i += blockDim.x) Z[i] = Zg[i];
-  __syncthreads();
+// eigenvalue order (lam ascending, so row n-1 first).  Z lives in registers:
+// row r belongs to wave r % 16 (slot r / 16), lane l holds its columns l,
+// l + 64 and l + 128.  A step normalises the pivot row in its wave, passes
+// it through LDS (double-buffered, one barrier per step) and every wave
+// removes its projection from its own rows below the pivot, with one wave
+// reduction per row.
+constexpr int kMgsWaves = 16;
+constexpr int kMgsSlots = (kTriMaxN + kMgsWaves - 1) / kMgsWaves;
+constexpr int kMgsCols = (kTriMaxN + 63) / 64;
+
+__global__ __launch_bounds__(64 * kMgsWaves) void k_tri_mgs(double* __restrict__ Zg, int n) {
+  __shared__ double piv[2][kTriMaxN];
+  const int lane = __lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double z[kMgsSlots][kMgsCols];
+#pragma unroll
+  for (int s = 0; s < kMgsSlots; ++s)
+#pragma unroll
+    for (int k = 0; k < kMgsCols; ++k) {
+      const int r = s * kMgsWaves + wave, c = k * 64 + lane;
+      z[s][k] = (r < n && c < n) ? Zg[(size_t)r * n + c] : 0.0;
+    }
   for (int pass = 0; pass < 2; ++pass) {
-    for (int s = 0; s < n; ++s) {
-      const int j = n - 1 - s;
-      const double* zj = Z + (size_t)j * n;
-      double nr = 0.0;
-      for (int i = lane; i < n; i += 64) nr += zj[i] * zj[i];
-      const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
-      // rows jj = wave, wave + nw, ... below j, three at a time so that
-      // their reductions overlap
-      for (int jj = wave; jj < j; jj += 3 * nw) {
-        const int j1 = jj + nw, j2 = jj + 2 * nw;
-        double* z0 = Z + (size_t)jj * n;
-        double* z1 = Z + (size_t)(j1 < j ? j1 : jj) * n;
-        double* z2 = Z + (size_t)(j2 < j ? j2 : jj) * n;
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-        for (int i = lane; i < n; i += 64) {
-          const double zi = zj[i];
-          d0 += zi * z0[i];
-          d1 += zi * z1[i];
-          d2 += zi * z2[i];
-        }
-        d0 = row16_sum(d0);
-        d1 = row16_sum(d1);
-        d2 = row16_sum(d2);
-        d0 = ((bcast(d0, 0) + bcast(d0, 16)) + (bcast(d0, 32) + bcast(d0, 48))) * inv * inv;
-        d1 = ((bcast(d1, 0) + bcast(d1, 16)) + (bcast(d1, 32) + bcast(d1, 48))) * inv * inv;
-        d2 = ((bcast(d2, 0) + bcast(d2, 16)) + (bcast(d2, 32) + bcast(d2, 48))) * inv * inv;
-        for (int i = lane; i < n; i += 64) {
-          const double zi = zj[i];
-          z0[i] -= d0 * zi;
-          if (j1 < j) z1[i] -= d1 * zi;
-          if (j2 < j) z2[i] -= d2 * zi;
-        }
+    for (int j = n - 1; j >= 0; --j) {
+      const int buf = j & 1;
+      if (wave == j % kMgsWaves) {
+        const int sj = j / kMgsWaves;
+        double nr = 0.0;
+#pragma unroll
+        for (int s = 0; s < kMgsSlots; ++s)
+          if (s == sj)
+#pragma unroll
+            for (int k = 0; k < kMgsCols; ++k) nr += z[s][k] * z[s][k];
+        const double inv = 1.0 / sqrt(fmax(wave_sum(nr), 1e-300));
+#pragma unroll
+        for (int s = 0; s < kMgsSlots; ++s)
+          if (s == sj)
+#pragma unroll
+            for (int k = 0; k < kMgsCols; ++k) {
+              z[s][k] *= inv;
+              const int c = k * 64 + lane;
+              if (c < n) piv[buf][c] = z[s][k];
+            }
       }
       __syncthreads();
-      if (wave == j % nw)
-        for (int i = lane; i < n; i += 64) Z[(size_t)j * n + i] *= inv;
-      // the scaled row j is read again only after the next barrier
+      double pj[kMgsCols];
+#pragma unroll
+      for (int k = 0; k < kMgsCols; ++k) {
+        const int c = k * 64 + lane;
+        pj[k] = c < n ? piv[buf][c] : 0.0;
+      }
+      double d[kMgsSlots];
+#pragma unroll
+      for (int s = 0; s < kMgsSlots; ++s) {
+        d[s] = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMgsCols; ++k) d[s] += z[s][k] * pj[k];
+      }
+#pragma unroll
+      for (int s = 0; s < kMgsSlots; ++s) {
+        const int r = s * kMgsWaves + wave;
+        if (r < j) {  // wave-uniform
+          const double ds = wave_sum(d[s]);
+#pragma unroll
+          for (int k = 0; k < kMgsCols; ++k) z[s][k] -= ds * pj[k];
+        }
+      }
     }
     __syncthreads();
   }
-  if (SHARED)
-    for (int i = tid; i < n * n; i += blockDim.x) Zg[i] = Z[i];
+#pragma unroll
+  for (int s = 0; s < kMgsSlots; ++s)
+#pragma unroll
+    for (int k = 0; k < kMgsCols; ++k) {
+      const int r = s * kMgsWaves + wave, c = k * 64 + lane;
+      if (r < n && c < n) Zg[(size_t)r * n + c] = z[s][k];
+    }
 }
 
 // 6. V[:, j] = H_0 ... H_{n-3} Phi z_j; V row-major n x n (V[i n + j])
@@ -466,11 +490,7 @@ hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, vo
   hipLaunchKernelGGL(k_tri_invit, dim3(nb), dim3(64 * kTriWaves), 0, st, d, e, lam, n, Z);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const size_t lds_z = (size_t)n * n * sizeof(double);
-  if (lds_z <= kTriLdsBudget)
-    hipLaunchKernelGGL((k_tri_mgs<true>), dim3(1), dim3(kTriThreads), lds_z, st, Z, n);
-  else
-    hipLaunchKernelGGL((k_tri_mgs<false>), dim3(1), dim3(kTriThreads), 0, st, Z, n);
+  hipLaunchKernelGGL(k_tri_mgs, dim3(1), dim3(64 * kMgsWaves), 0, st, Z, n);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_tri_back, dim3(nb), dim3(64 * kTriWaves), 0, st, Z, ph, Hv, gam, n,
