@@ -93,6 +93,17 @@ typedef struct {
  * Hermitian by definition and must be stored Hermitian: the sweep reads row r
  * of these matrices as the conjugate of column r (one coalesced load per
  * column).  mpt_project stores them exactly Hermitian.  1 <= n_ref <= 64.
+ *
+ * Per-direction form (one basis per direction, Section 4.1: a TSVD of each
+ * D_i; eqs. (podprealmpt), (podpimagmpt) with the cross blocks
+ * K^M_ij = U_i^H K U_j, C^M_ij, U_i^H C w_j): dirs = (M_1, M_2, M_3), all
+ * >= 1 with sum M, and every matrix above is that of the concatenated basis
+ * [U_1 U_2 U_3] (whose diagonal blocks are the per-direction matrices and
+ * whose off-diagonal blocks are the cross blocks), except Dp, which then
+ * holds n_ref x 3 matrices (mpt_project_dirs).  Direction i is solved in its
+ * own basis, (A_ii - i w C_ii) a_i = i w (U_i^H C w_i), and placed in the slots
+ * of U_i.  dirs = (0, 0, 0) is the joint form.  Only mpt_sweep takes the
+ * per-direction form (M <= 64); the other entry points reject it.
  */
 typedef struct {
   int32_t M;
@@ -108,6 +119,8 @@ typedef struct {
   const double* N0;
   double alpha;
   double alpha_lb;
+  int32_t dirs[3];  /* per-direction block sizes, or 0, 0, 0 (joint) */
+  int32_t pad_;
 } mpt_rom;
 
 /* ----------------------------------------------------------------------
@@ -171,6 +184,26 @@ mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double e
                        double* KM, double* A0, double* CM, double* g, double* G, double* Dp,
                        double* E, double* N0, double* Y, void* ws, size_t ws_bytes);
 
+/* The same projection onto a concatenated per-direction basis
+ * U = [U_1 U_2 U_3] (dirs: HOST array of the three widths, each >= 1, sum M;
+ * the per-direction form of mpt_rom).  Every output is mpt_project's for U,
+ * except Dp (n_ref x 3 x M x M): for shift k and target direction i,
+ * Dp[k][i] is block diagonal with the blocks D'_{i<-j} = D_{i<-j} / 2 +
+ * 4 eps h U_j^H U_j (j = 1..3, M_j x M_j), where a^H D_{i<-j} a is the squared
+ * distance in the norm of X + s C from conj(U_j a) to span(U_i):
+ *   D_{i<-j} = A_s,jj - conj(T_ij^H A_s,ii^{-1} T_ij),
+ *   A_s,ii = U_i^H (X + s C) U_i,  T_ij = U_i^H (X + s C) conj(U_j).
+ * Galerkin orthogonality of direction i's error holds against span(U_i)
+ * only, so the certificate's linear term for the pair (i, j) uses e_{j->i} =
+ * (a_j^H D'_{i<-j} a_j)^(1/2).  ws: mpt_project_ws_size bytes.  1 <= M <= 64. */
+mpt_status mpt_project_dirs(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                            const double* w, const double* o, const double* vol, double alpha,
+                            const double* U, int64_t ldU, int M, const int32_t* dirs,
+                            const int32_t* cond, int64_t n_c, const double* Vt,
+                            const double* lam, int n_ref, const double* s_ref, double* KM,
+                            double* A0, double* CM, double* g, double* G, double* Dp, double* E,
+                            double* N0, double* Y, void* ws, size_t ws_bytes);
+
 /* Residual Gram of Lemma 4.1 for one reference shift s from columns prepared
  * by the caller:
  *   G_s = (P + P^H) / 2,  P = Z^H Y over the N rows,
@@ -210,6 +243,11 @@ mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, int64_t ldU
  *   Delta bounds |R~ - R~^PODP|_ij and |I - I^PODP|_ij (the second term
  *   covers the part of the error that Galerkin orthogonality leaves linear in
  *   the residual when span(U) is not closed under conjugation).
+ * Per-direction form (rom->dirs set, M <= 64): a_i solves direction i's own
+ * system (A0 - i w CM restricted to block i, right-hand side i w g_i
+ * restricted to block i) and is zero outside block i; the tensors and the
+ * Grams use the full matrices of the concatenated basis, and the linear term
+ * is a^3/4 (n_i e_{j->i} + n_j e_{i->j}), e_{j->i} = (a_j^H Dp[s][i] a_j)^(1/2).
  * a_out (n_omega x 3 x M complex) receives a_i when non-NULL.
  * status[k] (device) = 0, or MPT_E_SINGULAR when a pivot was zero or
  * non-finite.  The call does not synchronise: it returns MPT_OK once the work

@@ -65,13 +65,21 @@ mpt_status fail(mpt_handle h, mpt_status s, const std::string& m) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-mpt_status check_rom(mpt_handle h, const mpt_rom* R) {
+// allow_dirs: the entry point takes the per-direction form (mpt_sweep only)
+mpt_status check_rom(mpt_handle h, const mpt_rom* R, bool allow_dirs = false) {
   ARG(R != nullptr, "rom is NULL");
   ARG(R->M >= 1 && R->M <= 96, "rom M must be in [1, 96]");
   ARG(R->KM && R->A0 && R->CM && R->g && R->G && R->Dp && R->s_ref && R->E && R->N0,
       "rom has a NULL matrix");
   ARG(R->n_ref >= 1 && R->n_ref <= 64, "rom n_ref must be in [1, 64]");
   ARG(R->alpha > 0.0 && R->alpha_lb > 0.0, "rom alpha and alpha_lb must be positive");
+  if (R->dirs[0] != 0 || R->dirs[1] != 0 || R->dirs[2] != 0) {
+    if (!allow_dirs) return fail(h, MPT_E_UNSUPPORTED, "a per-direction rom needs mpt_sweep");
+    ARG(R->dirs[0] >= 1 && R->dirs[1] >= 1 && R->dirs[2] >= 1 &&
+            R->dirs[0] + R->dirs[1] + R->dirs[2] == R->M,
+        "rom dirs must hold three widths >= 1 that sum to M");
+    ARG(R->M <= 64, "the per-direction form takes M <= 64");
+  }
   return MPT_OK;
 }
 
@@ -508,13 +516,14 @@ extern "C" mpt_status mpt_spmm(mpt_handle h, const mpt_csr* K, const double* U, 
   return MPT_OK;
 }
 
-extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
-                                  const double* w, const double* o, const double* vol,
-                                  double alpha, const double* U, int64_t ldU, int M,
-                                  const int32_t* cond, int64_t n_c, const double* Vt,
-                                  const double* lam, int n_ref, const double* s_ref, double* KM,
-                                  double* A0, double* CM, double* g, double* G, double* Dp,
-                                  double* E, double* N0, double* Y, void* ws, size_t ws_bytes) {
+// dirs: NULL (joint basis) or the three per-direction widths (host)
+static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                               const double* w, const double* o, const double* vol, double alpha,
+                               const double* U, int64_t ldU, int M, const int32_t* dirs,
+                               const int32_t* cond, int64_t n_c, const double* Vt,
+                               const double* lam, int n_ref, const double* s_ref, double* KM,
+                               double* A0, double* CM, double* g, double* G, double* Dp, double* E,
+                               double* N0, double* Y, void* ws, size_t ws_bytes) {
   if (!h) return MPT_E_ARG;
   ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && Vt && lam && s_ref,
       "NULL input");
@@ -575,8 +584,36 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
   HIP_OK(hipGetLastError());
   // certificate data per reference shift: G_s and D'_s (Lemma 4.1)
   HIP_OK(cert_launch(Yb, ldY, U, ldU, N, M, Zc, n_c, Vt, lam, n_ref, s_ref, A0, CM, UhU, eps_h,
-                     G, Dp, cws, st));
+                     dirs, G, Dp, cws, st));
   return MPT_OK;
+}
+
+extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                                  const double* w, const double* o, const double* vol,
+                                  double alpha, const double* U, int64_t ldU, int M,
+                                  const int32_t* cond, int64_t n_c, const double* Vt,
+                                  const double* lam, int n_ref, const double* s_ref, double* KM,
+                                  double* A0, double* CM, double* g, double* G, double* Dp,
+                                  double* E, double* N0, double* Y, void* ws, size_t ws_bytes) {
+  return project_impl(h, K, c, eps_h, w, o, vol, alpha, U, ldU, M, nullptr, cond, n_c, Vt, lam,
+                      n_ref, s_ref, KM, A0, CM, g, G, Dp, E, N0, Y, ws, ws_bytes);
+}
+
+extern "C" mpt_status mpt_project_dirs(mpt_handle h, const mpt_csr* K, const double* c,
+                                       double eps_h, const double* w, const double* o,
+                                       const double* vol, double alpha, const double* U,
+                                       int64_t ldU, int M, const int32_t* dirs,
+                                       const int32_t* cond, int64_t n_c, const double* Vt,
+                                       const double* lam, int n_ref, const double* s_ref,
+                                       double* KM, double* A0, double* CM, double* g, double* G,
+                                       double* Dp, double* E, double* N0, double* Y, void* ws,
+                                       size_t ws_bytes) {
+  if (!h) return MPT_E_ARG;
+  ARG(dirs && dirs[0] >= 1 && dirs[1] >= 1 && dirs[2] >= 1 && dirs[0] + dirs[1] + dirs[2] == M,
+      "dirs must hold three widths >= 1 that sum to M");
+  ARG(M <= 64, "the per-direction form takes M <= 64");
+  return project_impl(h, K, c, eps_h, w, o, vol, alpha, U, ldU, M, dirs, cond, n_c, Vt, lam,
+                      n_ref, s_ref, KM, A0, CM, g, G, Dp, E, N0, Y, ws, ws_bytes);
 }
 
 // ----------------------------------------- residual Gram from X^{-1} Z
@@ -620,7 +657,7 @@ extern "C" mpt_status mpt_residual_gram(mpt_handle h, const double* Z, int64_t l
 extern "C" mpt_status mpt_sweep(mpt_handle h, const mpt_rom* rom, const double* omega,
                                 int64_t n_omega, double* out, double* a_out, int32_t* status) {
   if (!h) return MPT_E_ARG;
-  mpt_status s = check_rom(h, rom);
+  mpt_status s = check_rom(h, rom, true);
   if (s != MPT_OK) return s;
   ARG(n_omega >= 0, "n_omega < 0");
   ARG(n_omega == 0 || (omega && out && status), "NULL omega/out/status");

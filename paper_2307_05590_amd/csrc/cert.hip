@@ -114,34 +114,46 @@ __global__ void k_conj_copy(const double2* __restrict__ x, int64_t cnt, double2*
   if (e < cnt) y[e] = cconj(x[e]);
 }
 
-// D'_s for one shift per workgroup (blockIdx.x = shift k):
+// D'_s for one shift and one target direction per workgroup (blockIdx.x =
+// shift k, blockIdx.y = direction b of nd; nd = 1 for the joint basis):
 //   A_s = A0 + s C_M = L L^H (Cholesky), T_s = T_X + s T_C,
 //   Y = L^{-1} T_s,  D_s = A_s - conj(Y^H Y),  D'_s = D_s / 2 + 4 eps_h U^H U,
-// stored Hermitian.  Lw, Yw: M x M work matrices per shift (global memory).
-// TC is read at offset 3 of an (M+3)-column Gram (its U block).
+// stored Hermitian.  For the per-direction form the solve is restricted to
+// block b of the concatenated basis (rows and columns [e[b], e[b+1])): A_s
+// becomes the identity outside that block and T_s loses its other rows, so
+// Y^H Y = T_b:^H A_s,bb^{-1} T_b:, and D' is kept on the diagonal blocks only
+// (the blocks D'_{b<-j}).  Lw, Yw: M x M work matrices per (shift, b), global
+// memory.  TC is read at offset 3 of an (M+3)-column Gram (its U block).
 __global__ __launch_bounds__(256) void k_defect(int M, const double* __restrict__ s_ref,
                                                 const double2* __restrict__ A0,
                                                 const double2* __restrict__ CM,
                                                 const double2* __restrict__ TX,
                                                 const double2* __restrict__ TCg,
                                                 const double2* __restrict__ UhU, double eps_h,
-                                                double2* __restrict__ Lwa,
+                                                int4 eb, double2* __restrict__ Lwa,
                                                 double2* __restrict__ Ywa,
                                                 double2* __restrict__ Dp) {
-  const int k = blockIdx.x;
+  const int k = blockIdx.x, b = blockIdx.y, nd = gridDim.y;
   const double s = s_ref[k];
   const int L = M + 3;
-  double2* Lw = Lwa + (size_t)k * M * M;
-  double2* Yw = Ywa + (size_t)k * M * M;
-  double2* D = Dp + (size_t)k * M * M;
+  const size_t slot = (size_t)k * nd + b;
+  double2* Lw = Lwa + slot * M * M;
+  double2* Yw = Ywa + slot * M * M;
+  double2* D = Dp + slot * M * M;
+  // block bounds eb.x = 0 <= eb.y <= eb.z <= eb.w = M; direction of an index
+  auto blk = [&](int r) { return r < eb.y ? 0 : (r < eb.z ? 1 : 2); };
+  const int lo = nd == 1 ? 0 : (b == 0 ? 0 : (b == 1 ? eb.y : eb.z));
+  const int hi = nd == 1 ? M : (b == 0 ? eb.y : (b == 1 ? eb.z : M));
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sinv;
-  for (int e = tid; e < M * M; e += nt) {
-    const int i = e / M, j = e % M;
-    const double2 a = A0[e], c = CM[e];
-    Lw[e] = make_double2(fma(s, c.x, a.x), fma(s, c.y, a.y));
-    const double2 tx = TX[e], tc = TCg[(3 + i) * L + 3 + j];
-    Yw[e] = make_double2(fma(s, tc.x, tx.x), fma(s, tc.y, tx.y));
+  for (int q = tid; q < M * M; q += nt) {
+    const int i = q / M, j = q % M;
+    const bool in_i = i >= lo && i < hi, in_j = j >= lo && j < hi;
+    const double2 a = A0[q], c = CM[q];
+    Lw[q] = (in_i && in_j) ? make_double2(fma(s, c.x, a.x), fma(s, c.y, a.y))
+                           : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    const double2 tx = TX[q], tc = TCg[(3 + i) * L + 3 + j];
+    Yw[q] = in_i ? make_double2(fma(s, tc.x, tx.x), fma(s, tc.y, tx.y)) : make_double2(0.0, 0.0);
   }
   // right-looking Cholesky, lower triangle
   for (int c = 0; c < M; ++c) {
@@ -183,19 +195,20 @@ __global__ __launch_bounds__(256) void k_defect(int M, const double* __restrict_
   }
   __syncthreads();
   // X = A_s - conj(Y^H Y), D' = X / 2 + 4 eps_h U^H U, into Lw (no longer needed)
-  for (int e = tid; e < M * M; e += nt) {
-    const int p = e / M, q = e % M;
+  for (int q0 = tid; q0 < M * M; q0 += nt) {
+    const int p = q0 / M, q = q0 % M;
     double2 acc = make_double2(0.0, 0.0);
     for (int r = 0; r < M; ++r) acc = cfma(acc, cconj(Yw[r * M + p]), Yw[r * M + q]);
-    const double2 a = A0[e], c = CM[e], u = UhU[e];
+    const double2 a = A0[q0], c = CM[q0], u = UhU[q0];
     const double xr = fma(s, c.x, a.x) - acc.x, xi = fma(s, c.y, a.y) + acc.y;
-    Lw[e] = make_double2(fma(0.5, xr, 4.0 * eps_h * u.x), fma(0.5, xi, 4.0 * eps_h * u.y));
+    Lw[q0] = make_double2(fma(0.5, xr, 4.0 * eps_h * u.x), fma(0.5, xi, 4.0 * eps_h * u.y));
   }
   __syncthreads();
-  for (int e = tid; e < M * M; e += nt) {
-    const int p = e / M, q = e % M;
+  for (int q0 = tid; q0 < M * M; q0 += nt) {
+    const int p = q0 / M, q = q0 % M;
     const double2 u = Lw[p * M + q], t = Lw[q * M + p];
-    D[e] = make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y));
+    D[q0] = (nd == 1 || blk(p) == blk(q)) ? make_double2(0.5 * (u.x + t.x), 0.5 * (u.y - t.y))
+                                          : make_double2(0.0, 0.0);
   }
 }
 
@@ -206,15 +219,15 @@ size_t cert_ws_size(int64_t N, int M, int64_t nc, int n_ref) {
          al((size_t)nc * L * 16) * 2 +            // B, conj(Zc)
          al((size_t)n_ref * 3 * L * L * 16) +     // weighted Grams
          al((size_t)L * L * 16) * 2 +             // T_X, T_C (Gram of Zc, conj Zc)
-         al((size_t)n_ref * M * M * 16) * 2 +     // Cholesky / solve work
+         al((size_t)n_ref * 3 * M * M * 16) * 2 + // Cholesky / solve work (per direction)
          al(gram_ws_size(N > nc ? N : nc, L, L)) + al(rcgemm_ws_size(nc, L));
 }
 
 hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ldU, int64_t N,
                        int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
                        int n_ref, const double* s_ref, const double* A0, const double* CM,
-                       const double* UhU, double eps_h, double* G, double* Dp, void* ws,
-                       hipStream_t st) {
+                       const double* UhU, double eps_h, const int32_t* dirs, double* G,
+                       double* Dp, void* ws, hipStream_t st) {
   const int L = M + 3;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   char* p = reinterpret_cast<char*>(ws);
@@ -224,8 +237,8 @@ hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ld
   double2* Wg = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * L * L * 16);
   double2* TX = reinterpret_cast<double2*>(p); p += al((size_t)L * L * 16);
   double2* TC = reinterpret_cast<double2*>(p); p += al((size_t)L * L * 16);
-  double2* Lw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * M * M * 16);
-  double2* Yw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * M * M * 16);
+  double2* Lw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * M * M * 16);
+  double2* Yw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * M * M * 16);
   void* gws = p;
   hipError_t e;
   // B = Vt Zc, then the weighted Grams and G_s per shift
@@ -262,9 +275,11 @@ hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ld
                          reinterpret_cast<double*>(TC), L, gws, st)) != hipSuccess)
       return e;
   }
-  hipLaunchKernelGGL(k_defect, dim3((unsigned)n_ref), dim3(256), 0, st, M, s_ref,
+  const int nd = dirs ? 3 : 1;
+  const int4 eb = dirs ? make_int4(0, dirs[0], dirs[0] + dirs[1], M) : make_int4(0, M, M, M);
+  hipLaunchKernelGGL(k_defect, dim3((unsigned)n_ref, (unsigned)nd), dim3(256), 0, st, M, s_ref,
                      reinterpret_cast<const double2*>(A0), reinterpret_cast<const double2*>(CM),
-                     TX, TC, reinterpret_cast<const double2*>(UhU), eps_h, Lw, Yw,
+                     TX, TC, reinterpret_cast<const double2*>(UhU), eps_h, eb, Lw, Yw,
                      reinterpret_cast<double2*>(Dp));
   return hipGetLastError();
 }

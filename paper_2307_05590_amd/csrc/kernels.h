@@ -86,8 +86,8 @@ size_t cert_ws_size(int64_t N, int M, int64_t nc, int n_ref);
 hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ldU, int64_t N,
                        int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
                        int n_ref, const double* s_ref, const double* A0, const double* CM,
-                       const double* UhU, double eps_h, double* G, double* Dp, void* ws,
-                       hipStream_t st);
+                       const double* UhU, double eps_h, const int32_t* dirs, double* G,
+                       double* Dp, void* ws, hipStream_t st);
 
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
 //   by cyclic two-sided Jacobi in one workgroup; V (n x n)

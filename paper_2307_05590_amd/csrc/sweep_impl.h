@@ -28,8 +28,9 @@ constexpr int kHQ = 18;   // Re a_i^H H a_j           (6)
 constexpr int kGA = 24;   // Re g_i^H a_j             (9)
 constexpr int kFA = 33;   // Re (F a_j)_i             (9)
 constexpr int kBA = 42;   // Im (B a_j)_i             (9)
-constexpr int kDQ = 51;   // Re a_i^H D' a_i          (3)
-constexpr int kSlots = 54;
+constexpr int kDQ = 51;   // Re a_i^H D' a_i (3); per-direction form:
+                          // Re a_j^H D'_{i<-j} a_j at kDQ + 3 i + j (9)
+constexpr int kSlots = 60;
 
 // index of the reference shift of frequency om: the largest k with
 // s_ref[k] <= om (s_ref ascending, s_ref[0] = 0)
@@ -165,6 +166,11 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   const int base = wl - ll;      // first lane of the segment
   const int M = R.M;
   const bool act = ll < M;
+  // per-direction form (one basis per direction, concatenated): block bounds
+  // e1, e2 of the three directions; pd is uniform over the launch
+  const bool pd = R.dirs[0] > 0;
+  const int e1 = R.dirs[0], e2 = R.dirs[0] + R.dirs[1];
+  const int bl = ll < e1 ? 0 : (ll < e2 ? 1 : 2);  // this lane's direction block
   const double2* A0 = reinterpret_cast<const double2*>(R.A0);
   const double2* CM = reinterpret_cast<const double2*>(R.CM);
   const double2* KM = reinterpret_cast<const double2*>(R.KM);
@@ -172,14 +178,16 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
   const int ldG = 2 * M + 3;
   const int kref = ref_of(R, om);
   const double2* G = reinterpret_cast<const double2*>(R.G) + (size_t)kref * ldG * ldG;
-  const double2* Dq = reinterpret_cast<const double2*>(R.Dp) + (size_t)kref * M * M;
+  const double2* Dq = reinterpret_cast<const double2*>(R.Dp) + (size_t)kref * (pd ? 3 : 1) * M * M;
 
   // ---- row `ll` of A(w) = A0 - i w C_M and r_i = i w g_i ---------------
   double2 A[MAXM];
 #pragma unroll
   for (int j = 0; j < MAXM; ++j) {
     double2 v = make_double2(0.0, 0.0);
-    if (act && j < M) {
+    // per-direction: each direction's system lives in its own diagonal block
+    const bool inblk = !pd || (j < e1 ? 0 : (j < e2 ? 1 : 2)) == bl;
+    if (act && j < M && inblk) {
       // A0 and C_M are Hermitian: row ll is the conjugate of column ll, read
       // with one coalesced load per j across the lanes
       const double2 a0 = cconj(A0[j * M + ll]);
@@ -193,7 +201,7 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     gl[i] = act ? gv[i * M + ll] : make_double2(0.0, 0.0);
-    b[i] = make_double2(-om * gl[i].y, om * gl[i].x);
+    b[i] = (pd && bl != i) ? make_double2(0.0, 0.0) : make_double2(-om * gl[i].y, om * gl[i].x);
   }
 
   // ---- LU with partial pivoting (max |re|+|im|, lowest row on ties) -------
@@ -297,14 +305,22 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
       const double2 cc = cconj(CM[j * M + ll]);
       const double2 gx = cconj(Xcol[(size_t)j * ldG]);
       const double2 hh = cconj(Hcol[(size_t)j * ldG]);
-      const double2 dd = cconj(Dq[j * M + ll]);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         Ka[i] = cfma(Ka[i], kk, aj[i]);
         Ca[i] = cfma(Ca[i], cc, aj[i]);
         Aa[i] = cfma(Aa[i], gx, aj[i]);
         Ha[i] = cfma(Ha[i], hh, aj[i]);
-        Da[i] = cfma(Da[i], dd, aj[i]);
+      }
+      if (!pd) {
+        const double2 dd = cconj(Dq[j * M + ll]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Da[i] = cfma(Da[i], dd, aj[i]);
+      } else {  // D'_i applied to this lane's own direction's solution
+        const double2 ab = bl == 0 ? aj[0] : (bl == 1 ? aj[1] : aj[2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          Da[i] = cfma(Da[i], cconj(Dq[((size_t)i * M + j) * M + ll]), ab);
       }
     }
   }
@@ -338,8 +354,10 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
       return cmul(Bi[i], x[j]).y;
     }
     if (sl < kSlots) {
-      const int i = sl - kDQ;
-      return cmulc(x[i], Da[i]).x;
+      const int u = sl - kDQ;
+      if (!pd) return u < 3 ? cmulc(x[u], Da[u]).x : 0.0;
+      const int i = u / 3, j = u % 3;  // target basis i, source direction j
+      return bl == j ? cmulc(x[j], Da[i]).x : 0.0;
     }
     return 0.0;
   };
@@ -389,9 +407,12 @@ __device__ __forceinline__ void sweep_point(const mpt_rom& R, const double om, c
                   red_lds[kAQ + q];
         }
         const double ni = sqrt(fmax(cr[0], 0.0)), nj = sqrt(fmax(cr[1], 0.0));
-        const double ei = sqrt(fmax(red_lds[kDQ + i], 0.0)), ej = sqrt(fmax(red_lds[kDQ + j], 0.0));
+        // e for (n_i, direction j) and (n_j, direction i): e_j and e_i of the
+        // joint form, e_{j->i} and e_{i->j} of the per-direction form
+        const double eji = sqrt(fmax(red_lds[pd ? kDQ + 3 * i + j : kDQ + j], 0.0));
+        const double eij = sqrt(fmax(red_lds[pd ? kDQ + 3 * j + i : kDQ + i], 0.0));
         myout = a3 / (8.0 * R.alpha_lb) * (2.0 * cr[0] + 2.0 * cr[1] - 2.0 * cr[2]) +
-                0.25 * a3 * (ni * ej + nj * ei);
+                0.25 * a3 * (ni * eji + nj * eij);
       }
       if (valid && out != nullptr) out[po] = myout;
     }

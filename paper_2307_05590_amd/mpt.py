@@ -29,7 +29,8 @@ class _Rom(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_ref", C.c_int32), ("KM", C.c_void_p), ("A0", C.c_void_p),
                 ("CM", C.c_void_p), ("g", C.c_void_p), ("G", C.c_void_p), ("Dp", C.c_void_p),
                 ("s_ref", C.c_void_p), ("E", C.c_void_p), ("N0", C.c_void_p),
-                ("alpha", C.c_double), ("alpha_lb", C.c_double)]
+                ("alpha", C.c_double), ("alpha_lb", C.c_double), ("dirs", C.c_int32 * 3),
+                ("pad_", C.c_int32)]
 
 
 class _Pencil(C.Structure):
@@ -65,6 +66,8 @@ def lib():
             "mpt_project_ws_size": ([I64, I32, I64, I32], S),
             "mpt_project": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P, P, I32, P,
                              P, P, P, P, P, P, P, P, P, P, S], I32),
+            "mpt_project_dirs": ([P, P, P, D, P, P, P, D, P, I64, I32, P, P, I64, P, P, I32, P,
+                                  P, P, P, P, P, P, P, P, P, P, S], I32),
             "mpt_residual_gram_ws_size": ([I64, I32], S),
             "mpt_residual_gram": ([P, P, I64, P, I64, I64, I32, P, P, S], I32),
             "mpt_sweep_adjoint_materials_ws_size": ([I64], S),
@@ -200,6 +203,7 @@ class Rom:
     N0: torch.Tensor  # (3, 3)
     alpha: float
     alpha_lb: float = ALPHA_LB
+    dirs: tuple = (0, 0, 0)  # per-direction block widths, or zeros (joint basis)
 
     @property
     def n_ref(self):
@@ -209,7 +213,7 @@ class Rom:
         _dev_check(self.KM, self.A0, self.CM, self.g, self.G, self.Dp, self.s_ref, self.E, self.N0)
         return _Rom(self.M, self.n_ref, _ptr(self.KM), _ptr(self.A0), _ptr(self.CM), _ptr(self.g),
                     _ptr(self.G), _ptr(self.Dp), _ptr(self.s_ref), _ptr(self.E), _ptr(self.N0),
-                    float(self.alpha), float(self.alpha_lb))
+                    float(self.alpha), float(self.alpha_lb), (C.c_int32 * 3)(*self.dirs), 0)
 
     @classmethod
     def from_host(cls, d, alpha, alpha_lb=ALPHA_LB, device="cuda"):
@@ -296,6 +300,38 @@ def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref, alp
                                _ptr(Dp), _ptr(E), _ptr(N0), _ptr(Y), _ptr(ws), ws.numel()))
     rom = Rom(M, KM, A0, CM, g, G, Dp, s_ref, E, N0, float(alpha), float(alpha_lb))
     return (rom, Y) if keep_Y else rom
+
+
+def mpt_project_dirs(K: Csr, c, eps_h, w, o, vol, alpha, Us, cond, Vt, lam, s_ref,
+                     alpha_lb=ALPHA_LB):
+    """a2 for one basis per direction: Us = (U_1, U_2, U_3) -> Rom of the
+    concatenated basis with dirs = their widths (Dp: n_ref x 3 x M x M)."""
+    U = torch.cat(list(Us), 1).contiguous()
+    h = handle(U.device)
+    _dev_check(c, w, o, vol, U, cond, Vt, lam, s_ref)
+    N, M = U.shape
+    dirs = tuple(int(u.shape[1]) for u in Us)
+    nc = cond.numel()
+    nr = s_ref.numel()
+    dev = U.device
+    cd, rd = torch.complex128, torch.float64
+    KM = torch.empty((M, M), dtype=cd, device=dev)
+    A0 = torch.empty_like(KM)
+    CM = torch.empty_like(KM)
+    g = torch.empty((3, M), dtype=cd, device=dev)
+    G = torch.empty((nr, 2 * M + 3, 2 * M + 3), dtype=cd, device=dev)
+    Dp = torch.empty((nr, 3, M, M), dtype=cd, device=dev)
+    E = torch.empty((3, 3), dtype=rd, device=dev)
+    N0 = torch.empty((3, 3), dtype=rd, device=dev)
+    ws = torch.empty(lib().mpt_project_ws_size(N, M, nc, nr), dtype=torch.uint8, device=dev)
+    k = K.struct()
+    dv = (C.c_int32 * 3)(*dirs)
+    h._check(lib().mpt_project_dirs(h.h, C.byref(k), _ptr(c), float(eps_h), _ptr(w), _ptr(o),
+                                    _ptr(vol), float(alpha), _ptr(U), M, M, dv, _ptr(cond), nc,
+                                    _ptr(Vt), _ptr(lam), nr, _ptr(s_ref), _ptr(KM), _ptr(A0),
+                                    _ptr(CM), _ptr(g), _ptr(G), _ptr(Dp), _ptr(E), _ptr(N0),
+                                    None, _ptr(ws), ws.numel()))
+    return Rom(M, KM, A0, CM, g, G, Dp, s_ref, E, N0, float(alpha), float(alpha_lb), dirs), U
 
 
 def mpt_sweep(rom: Rom, omega: torch.Tensor, want_a: bool = False):
