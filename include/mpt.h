@@ -131,11 +131,14 @@ typedef struct {
  * Thin SVD by passes of Gram / Hermitian eigen-decomposition / rotation
  * (FP64 MFMA Gram and rotation): pass 1 eigen-decomposes D^H D by Householder
  * tridiagonalisation, multisection and inverse iteration; the columns D V_T
- * of its tail (eigenvalues under 1e-8 of the largest, which pass 1 leaves
- * mixed) get the same treatment on their own Gram; pass 2 diagonalises the
- * Gram of the rotated snapshots by Jacobi (relative accuracy of the small
- * singular values), leaving out columns whose norms are under 1e-13 of the
- * largest (reported by their norms).
+ * of its tail (eigenvalues under 1e-10 of the largest, which pass 1 leaves
+ * mixed) get the same treatment on their own Gram, whose eigenvalues under
+ * 64 eps of its largest (singular values under ~1.2e-12 s_1) it cannot
+ * resolve: those directions leave the basis computation (reported by those
+ * eigenvalues); pass 2 diagonalises the Gram of the remaining rotated
+ * snapshots by Jacobi (relative accuracy of the small singular values),
+ * leaving out columns whose norms are under 1e-13 of the largest (reported
+ * by their norms).
  * Then truncation: M = #{s_m/s_1 >= max(tol_sigma, 1e-12)},
  * capped at M_cap, and lowered while s_{M+1}/s_M > 1 - 1e-8 (never splits
  * a cluster).  Relative singular values under 1e-12 are rounding noise of

@@ -116,6 +116,17 @@ __global__ void k_pod_tail_mix(const double2* __restrict__ V0, int m, int nt,
   }
 }
 
+// C[:, c0:c1] = 0 for the N rows of a row-major matrix (leading dimension ldc)
+__global__ void k_zero_cols(double2* __restrict__ C, int64_t ldc, int64_t N, int c0, int c1) {
+  const int w = c1 - c0;
+  const int64_t tot = N * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / w;
+    C[r * ldc + c0 + (int)(e - r * w)] = make_double2(0.0, 0.0);
+  }
+}
+
 // Columns of the rotated snapshots that enter the Jacobi: squared norm >=
 // floor * the largest (the others lie under the numerical rank floor and
 // no truncation keeps them).  Compacts their Gram into Gc (n' x n', in
@@ -144,33 +155,50 @@ __global__ void k_pod_live(const double2* __restrict__ G, int m, double floor,
   for (int j = t; j < n; j += blockDim.x) live[j] = idx[j];
 }
 
-// Singular values of all m columns (the Jacobi's n eigenvalues and the left-
-// out columns' squared norms), sorted descending; M by the truncation rule;
-// W (m x Mcap) = the kept eigenvectors scattered back to the m columns of the
+// Number of tail eigenvalues (ascending, nt of them) under rel times the
+// largest: directions the tail's own eigen-decomposition cannot resolve
+__global__ void k_pod_dead(const double* __restrict__ lam, int nt, double rel, int* __restrict__ nd) {
+  if (threadIdx.x == 0) {
+    int n = 0;
+    while (n < nt && lam[n] < rel * lam[nt - 1]) ++n;
+    nd[0] = n;
+  }
+}
+
+// Singular values of all nq + nd directions - the Jacobi's n eigenvalues, the
+// squared norms of the nq - n columns it left out, and the nd unresolved tail
+// eigenvalues lamd - sorted descending; M by the truncation rule; W (nq x
+// Mcap) = the kept eigenvectors scattered back to the nq columns of the
 // rotated snapshots and divided by their singular values.
 __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __restrict__ V,
                                int n, const int* __restrict__ live,
-                               const double2* __restrict__ G, int m, double tol, int Mcap,
+                               const double2* __restrict__ G, int nq,
+                               const double* __restrict__ lamd, int nd, double tol, int Mcap,
                                double* __restrict__ sigma, double2* __restrict__ W,
                                int* __restrict__ Mout) {
-  __shared__ int src[192];   // sorted entry -> eigenpair (>= 0) or -1 - left-out column
+  __shared__ int src[192];   // sorted entry -> eigenpair (>= 0) or < 0 for the others
   __shared__ double sv[192];
   __shared__ double val[192];
   __shared__ int code[192];
   __shared__ int pos[192];   // column -> its row of V, or -1 when left out
   __shared__ int Msh;
   const int t = threadIdx.x;
-  if (t < m) pos[t] = -1;
+  const int m = nq + nd;
+  if (t < nq) pos[t] = -1;
   __syncthreads();
   if (t < n) pos[live[t]] = t;
   __syncthreads();
-  if (t == 0) {  // entries: the n eigenvalues, then the left-out columns in order
+  if (t == 0) {  // entries: the n eigenvalues, the left-out columns, the tail remainder
     int k = n;
-    for (int j = 0; j < m; ++j)
+    for (int j = 0; j < nq; ++j)
       if (pos[j] < 0) {
-        val[k] = G[(size_t)j * m + j].x;
-        code[k++] = -1 - j;
+        val[k] = G[(size_t)j * nq + j].x;
+        code[k++] = -1;
       }
+    for (int j = 0; j < nd; ++j) {
+      val[k] = lamd[j];
+      code[k++] = -1;
+    }
   }
   if (t < n) {
     val[t] = lam[t];
@@ -196,7 +224,7 @@ __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __
         if (sv[j] / s1 >= tol) ++M;
     M = min(M, min(Mcap, m));
     while (M > 0 && M < m && sv[M] / sv[M - 1] > 1.0 - 1e-8) --M;
-    for (int j = 0; j < M; ++j)  // a left-out column is never kept
+    for (int j = 0; j < M; ++j)  // only resolved directions are kept
       if (src[j] < 0) {
         M = j;
         break;
@@ -206,7 +234,7 @@ __global__ void k_pod_finalize(const double* __restrict__ lam, const double2* __
   }
   __syncthreads();
   if (t < m) sigma[t] = sv[t];
-  for (int e = t; e < m * Mcap; e += blockDim.x) {
+  for (int e = t; e < nq * Mcap; e += blockDim.x) {
     const int r = e / Mcap, j = e % Mcap;
     double2 v = make_double2(0.0, 0.0);
     if (j < Msh && pos[r] >= 0) {
@@ -358,14 +386,19 @@ constexpr double kRankFloor = 1e-12;
 
 // pass-1 eigenvalues under this times the largest form the tail that gets a
 // Gram and an eigen-decomposition of its own before pass 2
-constexpr double kTailRel = 1e-8;
+constexpr double kTailRel = 1e-10;
+// tail eigenvalues under this times the tail's largest are beyond what its
+// eigen-decomposition resolves (absolute accuracy ~eps of the largest):
+// their directions stay out of pass 2 (singular values under
+// sqrt(64 eps kTailRel) s_1 ~ 1.2e-12 s_1, at the rank floor)
+constexpr double kDeadRel = 64.0 * 2.220446049250313e-16;
 // pass-2 columns with squared norms under this times the largest stay out of
 // the Jacobi: their singular values lie under 1e-13 s_1, below kRankFloor
 constexpr double kLiveFloor = 1e-26;
 
 static void pod_layout(int64_t N, int m, size_t* off) {
   // 0 G0, 1 V0, 2 lam, 3 Q1, 4 gram ws, 5 W, 6 info, 7 Mdev, 8 eigen ws,
-  // 9 compact Gram, 10 live columns, 11 end
+  // 9 compact Gram, 10 live columns, 11 unresolved tail eigenvalues, 12 end
   size_t o = 0;
   off[0] = o; o = align256(o + (size_t)m * m * 16);
   off[1] = o; o = align256(o + (size_t)m * m * 16);
@@ -378,14 +411,15 @@ static void pod_layout(int64_t N, int m, size_t* off) {
   off[8] = o; o = align256(o + std::max(jacobi_ws_size(m, kJacobiSweeps), tridiag_ws_size(m)));
   off[9] = o; o = align256(o + (size_t)m * m * 16);
   off[10] = o; o = align256(o + (size_t)m * 4);
-  off[11] = o;
+  off[11] = o; o = align256(o + (size_t)m * 8);
+  off[12] = o;
 }
 
 extern "C" size_t mpt_pod_basis_ws_size(int64_t N, int ncol) {
   if (N <= 0 || ncol <= 0) return 0;
-  size_t off[12];
+  size_t off[13];
   pod_layout(N, ncol, off);
-  return off[11];
+  return off[12];
 }
 
 extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, int64_t N,
@@ -400,7 +434,7 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(hipSetDevice(h->device));
   const int m = ncol;
   const int Mc = std::min(M_cap, m);
-  size_t off[12];
+  size_t off[13];
   pod_layout(N, m, off);
   char* w = reinterpret_cast<char*>(ws);
   double* G0 = reinterpret_cast<double*>(w + off[0]);
@@ -414,6 +448,7 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   void* jws = w + off[8];
   double* Gc = reinterpret_cast<double*>(w + off[9]);
   int* live = reinterpret_cast<int*>(w + off[10]);
+  double* lamd = reinterpret_cast<double*>(w + off[11]);
   hipStream_t st = h->stream;
   // pass 1: G0 = D^H D, eigenvectors V0 (absolute accuracy eps lam_max)
   HIP_OK(gram_launch(D, ldD, D, ldD, N, m, m, G0, m, gws, st));
@@ -430,22 +465,32 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(hipStreamSynchronize(st));
   const int nt = h->host_M[1];
   const double* Vr = V0;
+  int nd = 0;  // unresolved tail directions, left out from here on
   if (nt >= 2) {
     HIP_OK(rotate_launch(D, ldD, N, m, V0, m, nt, Q1, nt, st));            // D V0_T
     HIP_OK(gram_launch(Q1, nt, Q1, nt, N, nt, nt, Gc, nt, gws, st));        // its Gram
-    HIP_OK(tridiag_eig_launch(Gc, nt, W, lam, jws, st));                    // VT
+    HIP_OK(tridiag_eig_launch(Gc, nt, W, lam, jws, st));                    // VT, ascending
     hipLaunchKernelGGL(k_pod_tail_mix, dim3((m * m + 255) / 256), dim3(256), 0, st,
                        reinterpret_cast<const double2*>(V0), m, nt,
                        reinterpret_cast<const double2*>(W), reinterpret_cast<double2*>(G0));
     HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_pod_dead, dim3(1), dim3(64), 0, st, lam, nt, kDeadRel, Mdev + 2);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(h->host_M + 2, Mdev + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    nd = h->host_M[2];
+    if (nd > 0)
+      HIP_OK(hipMemcpyAsync(lamd, lam, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     Vr = G0;
   }
-  HIP_OK(rotate_launch(D, ldD, N, m, Vr, m, m, Q1, m, st));                 // Q1 = D V'
+  // Q1 = D V' over the resolved directions (columns nd.. of V')
+  const int nq = m - nd;
+  HIP_OK(rotate_launch(D, ldD, N, m, Vr + 2 * nd, m, nq, Q1, nq, st));
   // pass 2 on the rotated snapshots (graded Gram): Jacobi on the columns
   // above the floor (relative accuracy of the small singular values)
-  HIP_OK(gram_launch(Q1, m, Q1, m, N, m, m, G0, m, gws, st));
+  HIP_OK(gram_launch(Q1, nq, Q1, nq, N, nq, nq, G0, nq, gws, st));
   hipLaunchKernelGGL(k_pod_live, dim3(1), dim3(256), 0, st,
-                     reinterpret_cast<const double2*>(G0), m, kLiveFloor,
+                     reinterpret_cast<const double2*>(G0), nq, kLiveFloor,
                      reinterpret_cast<double2*>(Gc), live, Mdev + 1);
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(h->host_M + 1, Mdev + 1, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -456,8 +501,9 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
                          4.0 * nl * 2.220446049250313e-16, kJacobiFloor, st));
   hipLaunchKernelGGL(k_pod_finalize, dim3(1), dim3(256), 0, st, lam,
                      reinterpret_cast<const double2*>(V0), nl, live,
-                     reinterpret_cast<const double2*>(G0), m, std::max(tol_sigma, kRankFloor), Mc,
-                     sigma, reinterpret_cast<double2*>(W), Mdev);
+                     reinterpret_cast<const double2*>(G0), nq, lamd, nd,
+                     std::max(tol_sigma, kRankFloor), Mc, sigma,
+                     reinterpret_cast<double2*>(W), Mdev);
   HIP_OK(hipGetLastError());
   // M to the host, then U = Q1 W on the M kept columns; columns M..M_cap-1
   // cleared
@@ -467,10 +513,14 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
   HIP_OK(hipStreamSynchronize(st));
   const int M = *h->host_M;
   if (hinfo[0] < 0 || hinfo[1] < 0) return fail(h, MPT_E_NOTPD, "Jacobi did not converge");
-  if (M > 0) HIP_OK(rotate_launch(Q1, m, N, m, W, Mc, M, U, ldU, st));
-  if (M_cap > M)
-    HIP_OK(hipMemset2DAsync(reinterpret_cast<char*>(U) + (size_t)M * 16, ldU * 16, 0,
-                            (size_t)(M_cap - M) * 16, N, st));
+  if (M > 0) HIP_OK(rotate_launch(Q1, nq, N, nq, W, Mc, M, U, ldU, st));
+  if (M_cap > M) {
+    const int64_t tot = N * (M_cap - M);
+    const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_cols, dim3(blocks), dim3(256), 0, st, reinterpret_cast<double2*>(U),
+                       ldU, N, M, M_cap);
+    HIP_OK(hipGetLastError());
+  }
   *M_out = M;
   return MPT_OK;
 }

@@ -23,6 +23,9 @@ namespace mpt {
 // fragments (clamped, branch-free) and issues 4 RI RJ MFMAs.  Blocks of a
 // Hermitian product that lie entirely below the diagonal are skipped; the
 // partial sums of every chunk are reduced in a fixed order (deterministic).
+// With 2 x 2 blocks (the POD's large Hermitian Grams) a complex product takes
+// three real MFMAs instead of four (Gauss: P1 = ar br, P2 = ai bi,
+// P3 = (ar - ai)(br + bi); re = P1 + P2, im = P3 - P1 + P2), on 12 waves.
 constexpr int kGramMaxChunks = 512;
 
 struct GramPlan {
@@ -76,8 +79,8 @@ static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
   return g;
 }
 
-template <int RI, int RJ>
-__global__ __launch_bounds__(1024) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
+template <int RI, int RJ, bool G3>
+__global__ __launch_bounds__(G3 ? 768 : 1024) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
                                                      const double2* __restrict__ B, int64_t ldb,
                                                      int64_t N, int m, int n, int64_t rows,
                                                      int herm1, int nb1, int nb2,
@@ -113,13 +116,16 @@ __global__ __launch_bounds__(1024) void k_gram_chunk(const double2* __restrict__
     }
     const double2* Bs = self ? A : B;
     const int64_t ldbs = self ? lda : ldb;
-    double4_t accr[RI][RJ], acci[RI][RJ];
+    // G3: three real products per complex one (P1 = ar br, P2 = ai bi,
+    // P3 = (ar - ai)(br + bi); re = P1 + P2, im = P3 - P1 + P2)
+    double4_t accr[RI][RJ], acci[RI][RJ], acc3[G3 ? RI : 1][G3 ? RJ : 1];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
 #pragma unroll
       for (int q = 0; q < RJ; ++q) {
         accr[r][q] = double4_t{0, 0, 0, 0};
         acci[r][q] = double4_t{0, 0, 0, 0};
+        if (G3) acc3[G3 ? r : 0][G3 ? q : 0] = double4_t{0, 0, 0, 0};
       }
     for (int64_t k0 = r0; k0 < r1; k0 += 4) {
       const int64_t row = k0 + (lane >> 4);
@@ -140,11 +146,28 @@ __global__ __launch_bounds__(1024) void k_gram_chunk(const double2* __restrict__
       for (int r = 0; r < RI; ++r)
 #pragma unroll
         for (int q = 0; q < RJ; ++q) {
-          // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
-          accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);
-          accr[r][q] = mfma(fa[r].y, fb[q].y, accr[r][q]);
-          acci[r][q] = mfma(fa[r].x, fb[q].y, acci[r][q]);
-          acci[r][q] = mfma(-fa[r].y, fb[q].x, acci[r][q]);
+          if (G3) {
+            accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);  // P1
+            acci[r][q] = mfma(fa[r].y, fb[q].y, acci[r][q]);  // P2
+            acc3[G3 ? r : 0][G3 ? q : 0] =
+                mfma(fa[r].x - fa[r].y, fb[q].x + fb[q].y, acc3[G3 ? r : 0][G3 ? q : 0]);
+          } else {
+            // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
+            accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);
+            accr[r][q] = mfma(fa[r].y, fb[q].y, accr[r][q]);
+            acci[r][q] = mfma(fa[r].x, fb[q].y, acci[r][q]);
+            acci[r][q] = mfma(-fa[r].y, fb[q].x, acci[r][q]);
+          }
+        }
+    }
+    if (G3) {
+#pragma unroll
+      for (int r = 0; r < RI; ++r)
+#pragma unroll
+        for (int q = 0; q < RJ; ++q) {
+          const double4_t p1 = accr[r][q], p2 = acci[r][q], p3 = acc3[G3 ? r : 0][G3 ? q : 0];
+          accr[r][q] = p1 + p2;
+          acci[r][q] = (p3 - p1) + p2;
         }
     }
     double2* P = second ? part2 + (size_t)blockIdx.x * m * m : part1 + (size_t)blockIdx.x * m * n;
@@ -235,14 +258,21 @@ hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t l
     const dim3 grid((unsigned)g.chunks), block(64 * g.waves);
     const double2* Ac = reinterpret_cast<const double2*>(A);
     const double2* Bc = reinterpret_cast<const double2*>(B);
+    // the 2 x 2 blocks (the large Hermitian Grams) use three real products
+    // per complex one, on 12 waves (their accumulators need 128 registers)
+    const dim3 grid3((unsigned)g.chunks), block3(64 * (g.waves < 12 ? g.waves : 12));
+#define MPT_GC3(RI, RJ)                                                                   \
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, true>), grid3, block3, 0, st, Ac, lda, Bc, ldb, N, \
+                     m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
 #define MPT_GC(RI, RJ)                                                                      \
-  hipLaunchKernelGGL((k_gram_chunk<RI, RJ>), grid, block, 0, st, Ac, lda, Bc, ldb, N, m, n, \
-                     g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
-    if (g.RI == 2) MPT_GC(2, 2);
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false>), grid, block, 0, st, Ac, lda, Bc, ldb, N, \
+                     m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
+    if (g.RI == 2) MPT_GC3(2, 2);
     else if (g.RJ == 3) MPT_GC(1, 3);
     else if (g.RJ == 2) MPT_GC(1, 2);
     else MPT_GC(1, 1);
 #undef MPT_GC
+#undef MPT_GC3
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else {

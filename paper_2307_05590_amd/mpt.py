@@ -107,6 +107,13 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _ld(t):
+    """Leading dimension of a row-major matrix view (unit column stride)."""
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise MptError("expected a row-major matrix with unit column stride")
+    return max(int(t.stride(0)), int(t.shape[1]))
+
+
 class Handle:
     """One libmpt handle bound to a device and (by default) torch's current stream."""
 
@@ -158,6 +165,14 @@ def _dev_check(*ts):
     for t in ts:
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise MptError("libmpt expects contiguous CUDA tensors")
+
+
+def _dev_check_rows(t):
+    """A CUDA row-major matrix whose rows may be longer than its columns
+    (passed with its leading dimension)."""
+    if not t.is_cuda:
+        raise MptError("libmpt expects CUDA tensors")
+    _ld(t)
 
 
 @dataclass
@@ -229,11 +244,11 @@ class Rom:
 
 def mpt_spmm(K: Csr, U: torch.Tensor) -> torch.Tensor:
     h = handle(U.device)
-    _dev_check(U)
-    M = U.shape[1]
-    Y = torch.empty_like(U)
+    _dev_check_rows(U)
+    N, M = U.shape
+    Y = torch.empty((N, M), dtype=U.dtype, device=U.device)
     k = K.struct()
-    h._check(lib().mpt_spmm(h.h, C.byref(k), _ptr(U), M, M, _ptr(Y), M))
+    h._check(lib().mpt_spmm(h.h, C.byref(k), _ptr(U), _ld(U), M, _ptr(Y), M))
     return Y
 
 
@@ -257,7 +272,8 @@ def mpt_residual_gram(Z: torch.Tensor, XinvZ: torch.Tensor) -> torch.Tensor:
 
 
 def mpt_pod_basis(D: torch.Tensor, tol_sigma: float, M_cap: int):
-    """a1: returns (U (N x M), sigma (ncol), M).  Synchronises to read M."""
+    """a1: returns (U (N x M, a view of rows of length M_cap), sigma (ncol), M).
+    Synchronises to read M."""
     h = handle(D.device)
     _dev_check(D)
     N, ncol = D.shape
@@ -267,7 +283,7 @@ def mpt_pod_basis(D: torch.Tensor, tol_sigma: float, M_cap: int):
     M = C.c_int(0)
     h._check(lib().mpt_pod_basis(h.h, _ptr(D), ncol, N, ncol, float(tol_sigma), int(M_cap), _ptr(U),
                                  M_cap, _ptr(sigma), C.byref(M), _ptr(ws), ws.numel()))
-    return U[:, :M.value].contiguous(), sigma, M.value
+    return U[:, :M.value], sigma, M.value
 
 
 def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref, alpha_lb=ALPHA_LB,
@@ -277,7 +293,8 @@ def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref, alp
     Vt, lam: eigenvectors (rows) and eigenvalues of the conductor block of
     X^{-1} scaled by sqrt(c) on both sides."""
     h = handle(U.device)
-    _dev_check(c, w, o, vol, U, cond, Vt, lam, s_ref)
+    _dev_check(c, w, o, vol, cond, Vt, lam, s_ref)
+    _dev_check_rows(U)
     N, M = U.shape
     nc = cond.numel()
     nr = s_ref.numel()
@@ -295,7 +312,7 @@ def mpt_project(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref, alp
     ws = torch.empty(lib().mpt_project_ws_size(N, M, nc, nr), dtype=torch.uint8, device=dev)
     k = K.struct()
     h._check(lib().mpt_project(h.h, C.byref(k), _ptr(c), float(eps_h), _ptr(w), _ptr(o), _ptr(vol),
-                               float(alpha), _ptr(U), M, M, _ptr(cond), nc, _ptr(Vt), _ptr(lam),
+                               float(alpha), _ptr(U), _ld(U), M, _ptr(cond), nc, _ptr(Vt), _ptr(lam),
                                nr, _ptr(s_ref), _ptr(KM), _ptr(A0), _ptr(CM), _ptr(g), _ptr(G),
                                _ptr(Dp), _ptr(E), _ptr(N0), _ptr(Y), _ptr(ws), ws.numel()))
     rom = Rom(M, KM, A0, CM, g, G, Dp, s_ref, E, N0, float(alpha), float(alpha_lb))
@@ -398,7 +415,8 @@ def mpt_sweep_pencil(pen: Pencil, omega: torch.Tensor, want_a: bool = False):
 def mpt_tensors_fmm(K: Csr, c, w, U, cond, a, omega, N0, alpha, ws=None):
     """Full matrix method on q = U a: (n x 12 [R~ | I], ws)."""
     h = handle(U.device)
-    _dev_check(c, w, U, cond, a, omega, N0)
+    _dev_check(c, w, cond, a, omega, N0)
+    _dev_check_rows(U)
     N, M = U.shape
     n = omega.numel()
     out = torch.empty((n, 12), dtype=torch.float64, device=U.device)
@@ -406,7 +424,7 @@ def mpt_tensors_fmm(K: Csr, c, w, U, cond, a, omega, N0, alpha, ws=None):
     if ws is None or ws.numel() < nb:
         ws = torch.empty(nb, dtype=torch.uint8, device=U.device)
     k = K.struct()
-    h._check(lib().mpt_tensors_fmm(h.h, C.byref(k), _ptr(c), _ptr(w), _ptr(U), M, M, _ptr(cond),
+    h._check(lib().mpt_tensors_fmm(h.h, C.byref(k), _ptr(c), _ptr(w), _ptr(U), _ld(U), M, _ptr(cond),
                                    cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0), float(alpha),
                                    _ptr(out), _ptr(ws), ws.numel()))
     return out, ws
@@ -415,7 +433,8 @@ def mpt_tensors_fmm(K: Csr, c, w, U, cond, a, omega, N0, alpha, ws=None):
 def mpt_tensors_im(curl: Csr, face_w, c, w, U, cond, a, omega, N0, alpha, ws=None):
     """Integration-method analogue (sums over faces of the curl): (n x 12, ws)."""
     h = handle(U.device)
-    _dev_check(face_w, c, w, U, cond, a, omega, N0)
+    _dev_check(face_w, c, w, cond, a, omega, N0)
+    _dev_check_rows(U)
     N, M = U.shape
     n = omega.numel()
     out = torch.empty((n, 12), dtype=torch.float64, device=U.device)
@@ -423,8 +442,8 @@ def mpt_tensors_im(curl: Csr, face_w, c, w, U, cond, a, omega, N0, alpha, ws=Non
     if ws is None or ws.numel() < nb:
         ws = torch.empty(nb, dtype=torch.uint8, device=U.device)
     k = curl.struct()
-    h._check(lib().mpt_tensors_im(h.h, C.byref(k), _ptr(face_w), _ptr(c), _ptr(w), _ptr(U), N, M,
-                                  M, _ptr(cond), cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0),
+    h._check(lib().mpt_tensors_im(h.h, C.byref(k), _ptr(face_w), _ptr(c), _ptr(w), _ptr(U), N,
+                                  _ld(U), M, _ptr(cond), cond.numel(), _ptr(a), _ptr(omega), n, _ptr(N0),
                                   float(alpha), _ptr(out), _ptr(ws), ws.numel()))
     return out, ws
 
