@@ -538,16 +538,19 @@ static void proj_layout(int64_t N, int M, int64_t nc, int n_ref, size_t* off) {
   off[5] = o; o = align256(o + (size_t)N * 3 * 16);         // KO
   off[6] = o; o = align256(o + 9 * 16);                     // No
   off[7] = o; o = align256(o + (size_t)M * M * 16);         // U^H K U before symmetrising
-  off[8] = o; o = align256(o + std::max(gram_ws_size(gN, L, L), gram_ws_size(gN, M, M)));
-  off[9] = o; o = align256(o + cert_ws_size(N, M, nc, n_ref));
-  off[10] = o;
+  off[8] = o; o = align256(o + std::max(gram2c_ws_size(gN, L, L), gram2c_ws_size(gN, M, M)));
+  off[9] = o; o = align256(o + cert_ws_size(M, nc, n_ref));
+  off[10] = o; o = align256(o + (size_t)M * M * 16);        // U^H conj(K U)
+  off[11] = o; o = align256(o + (size_t)M * M * 16);        // U^H conj(U)
+  off[12] = o; o = align256(o + (size_t)L * L * 16);        // Zc^H conj(Zc)
+  off[13] = o;
 }
 
 extern "C" size_t mpt_project_ws_size(int64_t N, int M, int64_t n_c, int n_ref) {
   if (N <= 0 || M <= 0 || n_ref <= 0) return 0;
-  size_t off[11];
+  size_t off[14];
   proj_layout(N, M, n_c, n_ref, off);
-  return off[10];
+  return off[13];
 }
 
 static bool row_blocks_ok(const mpt_csr& K) {
@@ -588,7 +591,7 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
   hipStream_t st = h->stream;
   const int64_t N = K->n;
   const int L = M + 3;
-  size_t off[11];
+  size_t off[14];
   proj_layout(N, M, n_c, n_ref, off);
   char* wsb = reinterpret_cast<char*>(ws);
   double* Yb = Y ? Y : reinterpret_cast<double*>(wsb + off[0]);
@@ -602,11 +605,15 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
   double* KMt = reinterpret_cast<double*>(wsb + off[7]);
   void* gws = wsb + off[8];
   void* cws = wsb + off[9];
+  double* TXk = reinterpret_cast<double*>(wsb + off[10]);
+  double* TXu = reinterpret_cast<double*>(wsb + off[11]);
+  double* TCz = reinterpret_cast<double*>(wsb + off[12]);
 
-  // Y = K U; K_M = U^H Y; U^H U
+  // Y = K U; K_M = U^H Y, U^H U and, from the same products, U^H conj(Y),
+  // U^H conj(U) (the conjugation defect's T_X)
   HIP_OK(spmm_launch(*K, U, ldU, M, Yb, ldY, st));
-  HIP_OK(gram2_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, gws, st));
-  // conductor rows: Zc = sqrt(c) [w | U], P = Zc^H Zc (C_M, g, E)
+  HIP_OK(gram2c_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, TXk, M, TXu, M, gws, st));
+  // conductor rows: Zc = sqrt(c) [w | U], P = Zc^H Zc (C_M, g, E) and Zc^H conj(Zc)
   {
     const int64_t tot = n_c * L;
     hipLaunchKernelGGL(k_gather_cond, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, cond,
@@ -614,7 +621,7 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
                        reinterpret_cast<double2*>(Zc));
     HIP_OK(hipGetLastError());
   }
-  HIP_OK(gram_launch(Zc, L, Zc, L, n_c, L, L, P, L, gws, st));
+  HIP_OK(gram2c_launch(Zc, L, Zc, L, n_c, L, L, P, L, nullptr, 0, TCz, L, nullptr, 0, gws, st));
   // static tensor: o^H K o
   const double2* Nop = nullptr;
   if (o) {
@@ -633,8 +640,8 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
                      reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g), E, N0);
   HIP_OK(hipGetLastError());
   // certificate data per reference shift: G_s and D'_s (Lemma 4.1)
-  HIP_OK(cert_launch(Yb, ldY, U, ldU, N, M, Zc, n_c, Vt, lam, n_ref, s_ref, A0, CM, UhU, eps_h,
-                     dirs, G, Dp, cws, st));
+  HIP_OK(cert_launch(M, Zc, n_c, Vt, lam, n_ref, s_ref, A0, CM, UhU, TXk, TXu, TCz, eps_h, dirs,
+                     G, Dp, cws, st));
   return MPT_OK;
 }
 

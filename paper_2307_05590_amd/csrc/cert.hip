@@ -97,23 +97,6 @@ __global__ void k_ref_assemble(int M, int n_ref, const double2* __restrict__ Wg,
   }
 }
 
-// conj(Y + eps_h U) (N x M): the columns of X conj(U) for T_X = U^H X conj(U)
-__global__ void k_conj_xu(const double2* __restrict__ Y, int64_t ldY,
-                          const double2* __restrict__ U, int64_t ldU, int64_t N, int M,
-                          double eps_h, double2* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * M) return;
-  const int64_t r = e / M;
-  const int j = (int)(e % M);
-  const double2 y = Y[r * ldY + j], u = U[r * ldU + j];
-  out[e] = make_double2(fma(eps_h, u.x, y.x), -fma(eps_h, u.y, y.y));
-}
-
-__global__ void k_conj_copy(const double2* __restrict__ x, int64_t cnt, double2* __restrict__ y) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < cnt) y[e] = cconj(x[e]);
-}
-
 // D'_s for one shift and one target direction per workgroup (blockIdx.x =
 // shift k, blockIdx.y = direction b of nd; nd = 1 for the joint basis):
 //   A_s = A0 + s C_M = L L^H (Cholesky), T_s = T_X + s T_C,
@@ -127,7 +110,8 @@ __global__ void k_conj_copy(const double2* __restrict__ x, int64_t cnt, double2*
 __global__ __launch_bounds__(256) void k_defect(int M, const double* __restrict__ s_ref,
                                                 const double2* __restrict__ A0,
                                                 const double2* __restrict__ CM,
-                                                const double2* __restrict__ TX,
+                                                const double2* __restrict__ TXk,
+                                                const double2* __restrict__ TXu,
                                                 const double2* __restrict__ TCg,
                                                 const double2* __restrict__ UhU, double eps_h,
                                                 int4 eb, double2* __restrict__ Lwa,
@@ -152,7 +136,9 @@ __global__ __launch_bounds__(256) void k_defect(int M, const double* __restrict_
     const double2 a = A0[q], c = CM[q];
     Lw[q] = (in_i && in_j) ? make_double2(fma(s, c.x, a.x), fma(s, c.y, a.y))
                            : make_double2(i == j ? 1.0 : 0.0, 0.0);
-    const double2 tx = TX[q], tc = TCg[(3 + i) * L + 3 + j];
+    // T_X = U^H X conj(U) = U^H conj(K U) + eps_h U^H conj(U)
+    const double2 tk = TXk[q], tu = TXu[q], tc = TCg[(3 + i) * L + 3 + j];
+    const double2 tx = make_double2(fma(eps_h, tu.x, tk.x), fma(eps_h, tu.y, tk.y));
     Yw[q] = in_i ? make_double2(fma(s, tc.x, tx.x), fma(s, tc.y, tx.y)) : make_double2(0.0, 0.0);
   }
   // right-looking Cholesky, lower triangle
@@ -212,31 +198,25 @@ __global__ __launch_bounds__(256) void k_defect(int M, const double* __restrict_
   }
 }
 
-size_t cert_ws_size(int64_t N, int M, int64_t nc, int n_ref) {
+size_t cert_ws_size(int M, int64_t nc, int n_ref) {
   const int L = M + 3;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return al((size_t)N * M * 16) +                 // conj(X U)
-         al((size_t)nc * L * 16) * 2 +            // B, conj(Zc)
+  return al((size_t)nc * L * 16) +                // B
          al((size_t)n_ref * 3 * L * L * 16) +     // weighted Grams
-         al((size_t)L * L * 16) * 2 +             // T_X, T_C (Gram of Zc, conj Zc)
          al((size_t)n_ref * 3 * M * M * 16) * 2 + // Cholesky / solve work (per direction)
-         al(gram_ws_size(N > nc ? N : nc, L, L)) + al(rcgemm_ws_size(nc, L));
+         al(rcgemm_ws_size(nc, L));
 }
 
-hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ldU, int64_t N,
-                       int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
+hipError_t cert_launch(int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
                        int n_ref, const double* s_ref, const double* A0, const double* CM,
-                       const double* UhU, double eps_h, const int32_t* dirs, double* G,
+                       const double* UhU, const double* TXk, const double* TXu,
+                       const double* TCz, double eps_h, const int32_t* dirs, double* G,
                        double* Dp, void* ws, hipStream_t st) {
   const int L = M + 3;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   char* p = reinterpret_cast<char*>(ws);
-  double2* XUb = reinterpret_cast<double2*>(p); p += al((size_t)N * M * 16);
   double2* B = reinterpret_cast<double2*>(p); p += al((size_t)nc * L * 16);
-  double2* Zb = reinterpret_cast<double2*>(p); p += al((size_t)nc * L * 16);
   double2* Wg = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * L * L * 16);
-  double2* TX = reinterpret_cast<double2*>(p); p += al((size_t)L * L * 16);
-  double2* TC = reinterpret_cast<double2*>(p); p += al((size_t)L * L * 16);
   double2* Lw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * M * M * 16);
   double2* Yw = reinterpret_cast<double2*>(p); p += al((size_t)n_ref * 3 * M * M * 16);
   void* gws = p;
@@ -257,29 +237,13 @@ hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ld
                        reinterpret_cast<const double2*>(A0), reinterpret_cast<double2*>(G));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // T_X = U^H X conj(U) over the N rows; T_C = Zc^H conj(Zc) (its U block)
-  {
-    const int64_t cnt = N * M;
-    hipLaunchKernelGGL(k_conj_xu, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<const double2*>(Y), ldY,
-                       reinterpret_cast<const double2*>(U), ldU, N, M, eps_h, XUb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = gram_launch(U, ldU, reinterpret_cast<const double*>(XUb), M, N, M, M,
-                         reinterpret_cast<double*>(TX), M, gws, st)) != hipSuccess)
-      return e;
-    const int64_t cz = nc * L;
-    hipLaunchKernelGGL(k_conj_copy, dim3((unsigned)((cz + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<const double2*>(Zc), cz, Zb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = gram_launch(Zc, L, reinterpret_cast<const double*>(Zb), L, nc, L, L,
-                         reinterpret_cast<double*>(TC), L, gws, st)) != hipSuccess)
-      return e;
-  }
   const int nd = dirs ? 3 : 1;
   const int4 eb = dirs ? make_int4(0, dirs[0], dirs[0] + dirs[1], M) : make_int4(0, M, M, M);
   hipLaunchKernelGGL(k_defect, dim3((unsigned)n_ref, (unsigned)nd), dim3(256), 0, st, M, s_ref,
                      reinterpret_cast<const double2*>(A0), reinterpret_cast<const double2*>(CM),
-                     TX, TC, reinterpret_cast<const double2*>(UhU), eps_h, eb, Lw, Yw,
+                     reinterpret_cast<const double2*>(TXk), reinterpret_cast<const double2*>(TXu),
+                     reinterpret_cast<const double2*>(TCz),
+                     reinterpret_cast<const double2*>(UhU), eps_h, eb, Lw, Yw,
                      reinterpret_cast<double2*>(Dp));
   return hipGetLastError();
 }

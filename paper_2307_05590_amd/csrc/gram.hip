@@ -2,7 +2,8 @@
 //   gram:   P = A^H B over N rows (split-N partials + fixed-order reduction)
 //   rotate: C = A V  (tall x small)
 //   rcgemm: T = S Z  (small real x complex)
-// Complex products use four real MFMAs (re.re, im.im, re.im, im.re).
+// Complex products use four real MFMAs (re.re, im.im, re.im, im.re).  The
+// same four give A^H conj(B) too, so a pass can return both.
 //
 // Operand layout of the 16x16x4 f64 MFMA for lane l (0..63):
 //   a: A[l % 16][l / 16]   b: B[l / 16][l % 16]
@@ -79,13 +80,13 @@ static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
   return g;
 }
 
-template <int RI, int RJ, bool G3>
-__global__ __launch_bounds__(G3 ? 768 : 1024) void k_gram_chunk(const double2* __restrict__ A, int64_t lda,
-                                                     const double2* __restrict__ B, int64_t ldb,
-                                                     int64_t N, int m, int n, int64_t rows,
-                                                     int herm1, int nb1, int nb2,
-                                                     double2* __restrict__ part1,
-                                                     double2* __restrict__ part2) {
+template <int RI, int RJ, bool G3, bool CJ>
+__global__ __launch_bounds__(G3 ? 768 : (CJ ? 512 : 1024)) void k_gram_chunk(
+    const double2* __restrict__ A, int64_t lda, const double2* __restrict__ B, int64_t ldb,
+    int64_t N, int m, int n, int64_t rows, int herm1, int nb1, int nb2,
+    double2* __restrict__ part1, double2* __restrict__ part2, double2* __restrict__ part1c,
+    double2* __restrict__ part2c) {
+  static_assert(!(G3 && CJ), "one product form at a time");
   const int lane = __lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int TI = (m + 15) / 16, TJ = (n + 15) / 16;
@@ -117,15 +118,20 @@ __global__ __launch_bounds__(G3 ? 768 : 1024) void k_gram_chunk(const double2* _
     const double2* Bs = self ? A : B;
     const int64_t ldbs = self ? lda : ldb;
     // G3: three real products per complex one (P1 = ar br, P2 = ai bi,
-    // P3 = (ar - ai)(br + bi); re = P1 + P2, im = P3 - P1 + P2)
-    double4_t accr[RI][RJ], acci[RI][RJ], acc3[G3 ? RI : 1][G3 ? RJ : 1];
+    // P3 = (ar - ai)(br + bi); re = P1 + P2, im = P3 - P1 + P2).
+    // CJ: the four real products kept apart (ar br, ai bi, ar bi, ai br), which
+    // give both A^H B and A^H conj(B) from the same MFMAs.
+    constexpr int R3 = (G3 || CJ) ? RI : 1, C3 = (G3 || CJ) ? RJ : 1;
+    constexpr int R4 = CJ ? RI : 1, C4 = CJ ? RJ : 1;
+    double4_t accr[RI][RJ], acci[RI][RJ], acc3[R3][C3], acc4[R4][C4];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
 #pragma unroll
       for (int q = 0; q < RJ; ++q) {
         accr[r][q] = double4_t{0, 0, 0, 0};
         acci[r][q] = double4_t{0, 0, 0, 0};
-        if (G3) acc3[G3 ? r : 0][G3 ? q : 0] = double4_t{0, 0, 0, 0};
+        if (G3 || CJ) acc3[r % R3][q % C3] = double4_t{0, 0, 0, 0};
+        if (CJ) acc4[r % R4][q % C4] = double4_t{0, 0, 0, 0};
       }
     for (int64_t k0 = r0; k0 < r1; k0 += 4) {
       const int64_t row = k0 + (lane >> 4);
@@ -149,8 +155,12 @@ __global__ __launch_bounds__(G3 ? 768 : 1024) void k_gram_chunk(const double2* _
           if (G3) {
             accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);  // P1
             acci[r][q] = mfma(fa[r].y, fb[q].y, acci[r][q]);  // P2
-            acc3[G3 ? r : 0][G3 ? q : 0] =
-                mfma(fa[r].x - fa[r].y, fb[q].x + fb[q].y, acc3[G3 ? r : 0][G3 ? q : 0]);
+            acc3[r % R3][q % C3] = mfma(fa[r].x - fa[r].y, fb[q].x + fb[q].y, acc3[r % R3][q % C3]);
+          } else if (CJ) {
+            accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);
+            acci[r][q] = mfma(fa[r].y, fb[q].y, acci[r][q]);
+            acc3[r % R3][q % C3] = mfma(fa[r].x, fb[q].y, acc3[r % R3][q % C3]);
+            acc4[r % R4][q % C4] = mfma(fa[r].y, fb[q].x, acc4[r % R4][q % C4]);
           } else {
             // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
             accr[r][q] = mfma(fa[r].x, fb[q].x, accr[r][q]);
@@ -165,12 +175,39 @@ __global__ __launch_bounds__(G3 ? 768 : 1024) void k_gram_chunk(const double2* _
       for (int r = 0; r < RI; ++r)
 #pragma unroll
         for (int q = 0; q < RJ; ++q) {
-          const double4_t p1 = accr[r][q], p2 = acci[r][q], p3 = acc3[G3 ? r : 0][G3 ? q : 0];
+          const double4_t p1 = accr[r][q], p2 = acci[r][q], p3 = acc3[r % R3][q % C3];
           accr[r][q] = p1 + p2;
           acci[r][q] = (p3 - p1) + p2;
         }
     }
-    double2* P = second ? part2 + (size_t)blockIdx.x * m * m : part1 + (size_t)blockIdx.x * m * n;
+    const size_t poff = second ? (size_t)blockIdx.x * m * m : (size_t)blockIdx.x * m * n;
+    if (CJ) {  // A^H conj(B): re = ar br - ai bi, im = -(ar bi + ai br)
+      double2* Q = (second ? part2c : part1c) + poff;
+#pragma unroll
+      for (int r = 0; r < RI; ++r)
+#pragma unroll
+        for (int q = 0; q < RJ; ++q) {
+          const int I = bi * RI + r, J = bj * RJ + q;
+          if (I >= TI || J >= tj) continue;
+          const int col = J * 16 + cl;
+          const double4_t qr = accr[r][q] - acci[r][q];
+          const double4_t qi = -(acc3[r % R3][q % C3] + acc4[r % R4][q % C4]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rowo = I * 16 + (lane >> 4) + 4 * v;
+            if (rowo < m && col < ncol) Q[(size_t)rowo * ncol + col] = make_double2(qr[v], qi[v]);
+          }
+        }
+#pragma unroll
+      for (int r = 0; r < RI; ++r)
+#pragma unroll
+        for (int q = 0; q < RJ; ++q) {  // A^H B: re = ar br + ai bi, im = ar bi - ai br
+          const double4_t p1 = accr[r][q], p2 = acci[r][q];
+          accr[r][q] = p1 + p2;
+          acci[r][q] = acc3[r % R3][q % C3] - acc4[r % R4][q % C4];
+        }
+    }
+    double2* P = (second ? part2 : part1) + poff;
 #pragma unroll
     for (int r = 0; r < RI; ++r)
 #pragma unroll
@@ -208,12 +245,14 @@ __global__ void k_sum_partials1(const double2* __restrict__ part, int nparts, in
   mid[(size_t)sl * mn + idx] = s;
 }
 
+// mirror: 0 every tile computed; 1 Hermitian (tiles below the diagonal are
+// the conjugate of the computed (j, i) entry); 2 complex symmetric (its plain
+// transpose)
 __global__ void k_sum_partials2(const double2* __restrict__ mid, int mn,
                                 double2* __restrict__ P, int n, int64_t ldp, int herm) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mn) return;
   const int i = idx / n, j = idx % n;
-  // mirrored tile of a Hermitian product: conj of the computed (j, i) entry
   const bool mirror = herm && (j / 16) < (i / 16);
   const int src = mirror ? j * n + i : idx;
   double2 s = make_double2(0.0, 0.0);
@@ -222,7 +261,7 @@ __global__ void k_sum_partials2(const double2* __restrict__ mid, int mn,
     s.x += v.x;
     s.y += v.y;
   }
-  P[i * ldp + j] = mirror ? make_double2(s.x, -s.y) : s;
+  P[i * ldp + j] = (mirror && herm == 1) ? make_double2(s.x, -s.y) : s;
 }
 
 size_t gram_ws_size(int64_t N, int m, int n) {
@@ -232,58 +271,103 @@ size_t gram_ws_size(int64_t N, int m, int n) {
   return ((size_t)g.chunks * (mn + mm) + kSumSlices * (mn > mm ? mn : mm)) * sizeof(double2);
 }
 
+size_t gram2c_ws_size(int64_t N, int m, int n) {
+  // the dual form and its conjugate-B companions
+  const GramPlan g = gram_plan(N, m, n, false, true);
+  const size_t mn = (size_t)m * n, mm = (size_t)m * m;
+  return ((size_t)g.chunks * (mn + mm) * 2 + kSumSlices * (mn > mm ? mn : mm)) * sizeof(double2);
+}
+
 static hipError_t gram_reduce(const double2* part, int64_t chunks, int m, int n, double* P,
-                              int64_t ldp, bool herm, double2* mid, hipStream_t st) {
+                              int64_t ldp, int herm, double2* mid, hipStream_t st) {
   const int mn = m * n;
   hipLaunchKernelGGL(k_sum_partials1, dim3((mn + 255) / 256, kSumSlices), dim3(256), 0, st, part,
                      (int)chunks, mn, mid);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_partials2, dim3((mn + 255) / 256), dim3(256), 0, st, mid, mn,
-                     reinterpret_cast<double2*>(P), n, ldp, herm ? 1 : 0);
+                     reinterpret_cast<double2*>(P), n, ldp, herm);
   return hipGetLastError();
 }
 
-hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
-                        int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
-                        void* ws, hipStream_t st) {
+// P1 = A^H B, optionally P2 = A^H A (dual), and with Q1 the companions
+// Q1 = A^H conj(B), Q2 = A^H conj(A) from the same MFMAs
+static hipError_t gram_run(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                           int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                           double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
+                           hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const bool herm1 = (A == B && lda == ldb && m == n);
   const bool dual = P2 != nullptr;
+  const bool cj = Q1 != nullptr;
   const GramPlan g = gram_plan(N, m, n, herm1, dual);
   double2* part1 = reinterpret_cast<double2*>(ws);
   double2* part2 = part1 + (size_t)g.chunks * m * n;
-  double2* mid = part2 + (dual ? (size_t)g.chunks * m * m : 0);
+  double2* part1c = part2 + (dual ? (size_t)g.chunks * m * m : 0);
+  double2* part2c = part1c + (cj ? (size_t)g.chunks * m * n : 0);
+  double2* mid = part2c + (cj && dual ? (size_t)g.chunks * m * m : 0);
   if (g.chunks > 0) {
     const dim3 grid((unsigned)g.chunks), block(64 * g.waves);
     const double2* Ac = reinterpret_cast<const double2*>(A);
     const double2* Bc = reinterpret_cast<const double2*>(B);
     // the 2 x 2 blocks (the large Hermitian Grams) use three real products
-    // per complex one, on 12 waves (their accumulators need 128 registers)
+    // per complex one, on 12 waves (their accumulators need 128 registers);
+    // the conjugate companions keep four accumulators, on at most 8 waves
     const dim3 grid3((unsigned)g.chunks), block3(64 * (g.waves < 12 ? g.waves : 12));
-#define MPT_GC3(RI, RJ)                                                                   \
-  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, true>), grid3, block3, 0, st, Ac, lda, Bc, ldb, N, \
-                     m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
-#define MPT_GC(RI, RJ)                                                                      \
-  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false>), grid, block, 0, st, Ac, lda, Bc, ldb, N, \
-                     m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2)
-    if (g.RI == 2) MPT_GC3(2, 2);
-    else if (g.RJ == 3) MPT_GC(1, 3);
-    else if (g.RJ == 2) MPT_GC(1, 2);
-    else MPT_GC(1, 1);
+    const dim3 blockc(64 * (g.waves < 8 ? g.waves : 8));
+#define MPT_GC3(RI, RJ)                                                                      \
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, true, false>), grid3, block3, 0, st, Ac, lda, Bc, ldb, \
+                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+#define MPT_GC(RI, RJ)                                                                        \
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false, false>), grid, block, 0, st, Ac, lda, Bc, ldb, \
+                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+#define MPT_GCC(RI, RJ)                                                                       \
+  hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false, true>), grid, blockc, 0, st, Ac, lda, Bc, ldb, \
+                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+    if (cj) {
+      if (g.RI == 2) MPT_GCC(2, 2);
+      else if (g.RJ == 3) MPT_GCC(1, 3);
+      else if (g.RJ == 2) MPT_GCC(1, 2);
+      else MPT_GCC(1, 1);
+    } else {
+      if (g.RI == 2) MPT_GC3(2, 2);
+      else if (g.RJ == 3) MPT_GC(1, 3);
+      else if (g.RJ == 2) MPT_GC(1, 2);
+      else MPT_GC(1, 1);
+    }
 #undef MPT_GC
 #undef MPT_GC3
+#undef MPT_GCC
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else {
     hipError_t e = hipMemsetAsync(part1, 0, (size_t)m * n * sizeof(double2), st);
     if (e == hipSuccess && dual) e = hipMemsetAsync(part2, 0, (size_t)m * m * sizeof(double2), st);
+    if (e == hipSuccess && cj) e = hipMemsetAsync(part1c, 0, (size_t)m * n * sizeof(double2), st);
+    if (e == hipSuccess && cj && dual)
+      e = hipMemsetAsync(part2c, 0, (size_t)m * m * sizeof(double2), st);
     if (e != hipSuccess) return e;
   }
   const int64_t ch = g.chunks > 0 ? g.chunks : 1;
-  hipError_t e = gram_reduce(part1, ch, m, n, P1, ldp1, herm1, mid, st);
+  hipError_t e = gram_reduce(part1, ch, m, n, P1, ldp1, herm1 ? 1 : 0, mid, st);
+  if (e == hipSuccess && cj) e = gram_reduce(part1c, ch, m, n, Q1, ldq1, herm1 ? 2 : 0, mid, st);
   if (e != hipSuccess || !dual) return e;
-  return gram_reduce(part2, ch, m, m, P2, ldp2, true, mid, st);
+  e = gram_reduce(part2, ch, m, m, P2, ldp2, 1, mid, st);
+  if (e == hipSuccess && cj && Q2) e = gram_reduce(part2c, ch, m, m, Q2, ldq2, 2, mid, st);
+  return e;
+}
+
+hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                        int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                        void* ws, hipStream_t st) {
+  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, nullptr, 0, nullptr, 0, ws, st);
+}
+
+hipError_t gram2c_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                         int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
+                         hipStream_t st) {
+  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, Q1, ldq1, Q2, ldq2, ws, st);
 }
 
 hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,

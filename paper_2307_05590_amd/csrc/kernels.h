@@ -64,12 +64,19 @@ hipError_t spmm_launch(const mpt_csr& K, const double* U, int64_t ldU, int M, do
 //   P (m x n) = A^H B over N rows, A: N x m (lda), B: N x n (ldb), complex.
 //   Split-N partials in ws then a fixed-order reduction.
 size_t gram_ws_size(int64_t N, int m, int n);
+size_t gram2c_ws_size(int64_t N, int m, int n);  // for gram2c_launch
 hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                        int m, int n, double* P, int64_t ldp, void* ws, hipStream_t st);
 //   P1 = A^H B (m x n) and P2 = A^H A (m x m) in one pass over the rows
 hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                         int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
                         void* ws, hipStream_t st);
+//   the same, and from the same MFMAs Q1 = A^H conj(B) (m x n; complex
+//   symmetric when A == B) and, with P2, Q2 = A^H conj(A) (may be null)
+hipError_t gram2c_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
+                         int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
+                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
+                         hipStream_t st);
 //   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv).
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
                          int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st);
@@ -79,14 +86,16 @@ hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n,
                              void* ws, hipStream_t st);
 
 // cert.hip : certificate data per reference shift (Lemma 4.1):
-//   G (n_ref x (2M+3)^2) and D' (n_ref x M x M) from Y = K U, U, the scaled
-//   conductor rows Zc = sqrt(c) [w | U] (n_c x (M+3)), the conductor block's
-//   eigenpairs (Vt rows, lam), the shifts, and the assembled A0, C_M, U^H U.
-size_t cert_ws_size(int64_t N, int M, int64_t nc, int n_ref);
-hipError_t cert_launch(const double* Y, int64_t ldY, const double* U, int64_t ldU, int64_t N,
-                       int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
+//   G (n_ref x (2M+3)^2) and D' (n_ref x M x M) from the scaled conductor
+//   rows Zc = sqrt(c) [w | U] (n_c x (M+3)), the conductor block's eigenpairs
+//   (Vt rows, lam), the shifts, the assembled A0, C_M, U^H U, and the
+//   conjugation products U^H conj(K U), U^H conj(U) (M x M) and
+//   Zc^H conj(Zc) ((M+3) x (M+3)).
+size_t cert_ws_size(int M, int64_t nc, int n_ref);
+hipError_t cert_launch(int M, const double* Zc, int64_t nc, const double* Vt, const double* lam,
                        int n_ref, const double* s_ref, const double* A0, const double* CM,
-                       const double* UhU, double eps_h, const int32_t* dirs, double* G,
+                       const double* UhU, const double* TXk, const double* TXu,
+                       const double* TCz, double eps_h, const int32_t* dirs, double* G,
                        double* Dp, void* ws, hipStream_t st);
 
 // eig.hip : Hermitian eigen-decomposition of a small n x n matrix (n <= 192)
