@@ -116,17 +116,6 @@ __global__ void k_pod_tail_mix(const double2* __restrict__ V0, int m, int nt,
   }
 }
 
-// C[:, c0:c1] = 0 for the N rows of a row-major matrix (leading dimension ldc)
-__global__ void k_zero_cols(double2* __restrict__ C, int64_t ldc, int64_t N, int c0, int c1) {
-  const int w = c1 - c0;
-  const int64_t tot = N * w;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / w;
-    C[r * ldc + c0 + (int)(e - r * w)] = make_double2(0.0, 0.0);
-  }
-}
-
 // Columns of the rotated snapshots that enter the Jacobi: squared norm >=
 // floor * the largest (the others lie under the numerical rank floor and
 // no truncation keeps them).  Compacts their Gram into Gc (n' x n', in
@@ -505,22 +494,15 @@ extern "C" mpt_status mpt_pod_basis(mpt_handle h, const double* D, int64_t ldD, 
                      std::max(tol_sigma, kRankFloor), Mc, sigma,
                      reinterpret_cast<double2*>(W), Mdev);
   HIP_OK(hipGetLastError());
-  // M to the host, then U = Q1 W on the M kept columns; columns M..M_cap-1
-  // cleared
+  // M to the host, then U = Q1 W on the M kept columns, columns M..M_cap-1
+  // cleared in the same pass
   HIP_OK(hipMemcpyAsync(h->host_M, Mdev, sizeof(int), hipMemcpyDeviceToHost, st));
   int hinfo[4] = {0, 0, 0, 0};
   HIP_OK(hipMemcpyAsync(hinfo, info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   const int M = *h->host_M;
   if (hinfo[0] < 0 || hinfo[1] < 0) return fail(h, MPT_E_NOTPD, "Jacobi did not converge");
-  if (M > 0) HIP_OK(rotate_launch(Q1, nq, N, nq, W, Mc, M, U, ldU, st));
-  if (M_cap > M) {
-    const int64_t tot = N * (M_cap - M);
-    const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_zero_cols, dim3(blocks), dim3(256), 0, st, reinterpret_cast<double2*>(U),
-                       ldU, N, M, M_cap);
-    HIP_OK(hipGetLastError());
-  }
+  HIP_OK(rotate_launch(Q1, nq, N, nq, W, Mc, M, U, ldU, st, M_cap));
   *M_out = M;
   return MPT_OK;
 }
@@ -609,10 +591,10 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
   double* TXu = reinterpret_cast<double*>(wsb + off[11]);
   double* TCz = reinterpret_cast<double*>(wsb + off[12]);
 
-  // Y = K U; K_M = U^H Y, U^H U and, from the same products, U^H conj(Y),
-  // U^H conj(U) (the conjugation defect's T_X)
+  // Y = K U; K_M = U^H Y (Hermitian: K is real symmetric), U^H U and, from
+  // the same products, U^H conj(Y), U^H conj(U) (the conjugation defect's T_X)
   HIP_OK(spmm_launch(*K, U, ldU, M, Yb, ldY, st));
-  HIP_OK(gram2c_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, TXk, M, TXu, M, gws, st));
+  HIP_OK(gram2c_launch(U, ldU, Yb, ldY, N, M, M, KMt, M, UhU, M, TXk, M, TXu, M, true, gws, st));
   // conductor rows: Zc = sqrt(c) [w | U], P = Zc^H Zc (C_M, g, E) and Zc^H conj(Zc)
   {
     const int64_t tot = n_c * L;
@@ -621,7 +603,8 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
                        reinterpret_cast<double2*>(Zc));
     HIP_OK(hipGetLastError());
   }
-  HIP_OK(gram2c_launch(Zc, L, Zc, L, n_c, L, L, P, L, nullptr, 0, TCz, L, nullptr, 0, gws, st));
+  HIP_OK(gram2c_launch(Zc, L, Zc, L, n_c, L, L, P, L, nullptr, 0, TCz, L, nullptr, 0, false, gws,
+                       st));
   // static tensor: o^H K o
   const double2* Nop = nullptr;
   if (o) {

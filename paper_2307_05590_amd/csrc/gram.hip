@@ -83,7 +83,7 @@ static GramPlan gram_plan(int64_t N, int m, int n, bool herm1, bool dual) {
 template <int RI, int RJ, bool G3, bool CJ>
 __global__ __launch_bounds__(G3 ? 768 : (CJ ? 512 : 1024)) void k_gram_chunk(
     const double2* __restrict__ A, int64_t lda, const double2* __restrict__ B, int64_t ldb,
-    int64_t N, int m, int n, int64_t rows, int herm1, int nb1, int nb2,
+    int64_t N, int m, int n, int64_t rows, int flags1, int nb1, int nb2,
     double2* __restrict__ part1, double2* __restrict__ part2, double2* __restrict__ part1c,
     double2* __restrict__ part2c) {
   static_assert(!(G3 && CJ), "one product form at a time");
@@ -96,11 +96,13 @@ __global__ __launch_bounds__(G3 ? 768 : (CJ ? 512 : 1024)) void k_gram_chunk(
   const double2 z2 = make_double2(0.0, 0.0);
   for (int bk = wave; bk < nb1 + nb2; bk += nw) {
     const bool second = bk >= nb1;  // wave-uniform
-    const bool self = second || herm1;
+    // flags1: bit 0 the first product is Hermitian (blocks below the diagonal
+    // skipped), bit 1 its B is A
+    const bool self = second || (flags1 & 2);
     const int ncol = second ? m : n;
     const int tj = second ? TI : TJ;
     int bi, bj;
-    gram_block_of(second ? bk - nb1 : bk, TI, tj, RI, RJ, second || herm1, bi, bj);
+    gram_block_of(second ? bk - nb1 : bk, TI, tj, RI, RJ, second || (flags1 & 1), bi, bj);
     int ca[RI], cb[RJ];
     bool va[RI], vb[RJ];
 #pragma unroll
@@ -294,10 +296,12 @@ static hipError_t gram_reduce(const double2* part, int64_t chunks, int m, int n,
 // Q1 = A^H conj(B), Q2 = A^H conj(A) from the same MFMAs
 static hipError_t gram_run(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                            int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
-                           double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
-                           hipStream_t st) {
+                           double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, bool herm_ab,
+                           void* ws, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const bool herm1 = (A == B && lda == ldb && m == n);
+  const bool same = (A == B && lda == ldb && m == n);
+  const bool herm1 = same || (herm_ab && m == n);
+  const int flags1 = (herm1 ? 1 : 0) | (same ? 2 : 0);
   const bool dual = P2 != nullptr;
   const bool cj = Q1 != nullptr;
   const GramPlan g = gram_plan(N, m, n, herm1, dual);
@@ -317,13 +321,13 @@ static hipError_t gram_run(const double* A, int64_t lda, const double* B, int64_
     const dim3 blockc(64 * (g.waves < 8 ? g.waves : 8));
 #define MPT_GC3(RI, RJ)                                                                      \
   hipLaunchKernelGGL((k_gram_chunk<RI, RJ, true, false>), grid3, block3, 0, st, Ac, lda, Bc, ldb, \
-                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+                     N, m, n, g.rows, flags1, g.nb1, g.nb2, part1, part2, part1c, part2c)
 #define MPT_GC(RI, RJ)                                                                        \
   hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false, false>), grid, block, 0, st, Ac, lda, Bc, ldb, \
-                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+                     N, m, n, g.rows, flags1, g.nb1, g.nb2, part1, part2, part1c, part2c)
 #define MPT_GCC(RI, RJ)                                                                       \
   hipLaunchKernelGGL((k_gram_chunk<RI, RJ, false, true>), grid, blockc, 0, st, Ac, lda, Bc, ldb, \
-                     N, m, n, g.rows, herm1 ? 1 : 0, g.nb1, g.nb2, part1, part2, part1c, part2c)
+                     N, m, n, g.rows, flags1, g.nb1, g.nb2, part1, part2, part1c, part2c)
     if (cj) {
       if (g.RI == 2) MPT_GCC(2, 2);
       else if (g.RJ == 3) MPT_GCC(1, 3);
@@ -360,14 +364,16 @@ static hipError_t gram_run(const double* A, int64_t lda, const double* B, int64_
 hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                         int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
                         void* ws, hipStream_t st) {
-  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, nullptr, 0, nullptr, 0, ws, st);
+  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, nullptr, 0, nullptr, 0, false, ws,
+                  st);
 }
 
 hipError_t gram2c_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                          int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
-                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
-                         hipStream_t st) {
-  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, Q1, ldq1, Q2, ldq2, ws, st);
+                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, bool herm_ab,
+                         void* ws, hipStream_t st) {
+  return gram_run(A, lda, B, ldb, N, m, n, P1, ldp1, P2, ldp2, Q1, ldq1, Q2, ldq2, herm_ab, ws,
+                  st);
 }
 
 hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
@@ -383,9 +389,10 @@ template <int RT, int CT>
 __global__ __launch_bounds__(256) void k_rotate(const double2* __restrict__ A, int64_t lda,
                                                 int64_t N, int m, const double2* __restrict__ V,
                                                 int64_t ldv, int n, double2* __restrict__ C,
-                                                int64_t ldc) {
+                                                int64_t ldc, int nw) {
+  // nw >= n: columns n .. nw-1 of C are written as zeros
   const int lane = __lane_id();
-  const int TJ = (n + 15) / 16, CG = (TJ + CT - 1) / CT;
+  const int TJ = (nw + 15) / 16, CG = (TJ + CT - 1) / CT;
   const int64_t task = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t RB = (N + 16 * RT - 1) / (16 * RT);
   if (task >= RB * CG) return;
@@ -418,8 +425,9 @@ __global__ __launch_bounds__(256) void k_rotate(const double2* __restrict__ A, i
     }
   };
   double2 a[RT], v[CT];
-  load(0, a, v);
-  for (int k0 = 0; k0 < m; k0 += 4) {
+  const bool live = cg * CT * 16 < n;  // wave-uniform: this column group holds columns of V
+  if (live) load(0, a, v);
+  for (int k0 = 0; live && k0 < m; k0 += 4) {
     double2 na[RT], nv[CT];
     load(k0 + 4, na, nv);  // next step's fragments in flight during the MFMAs
 #pragma unroll
@@ -444,21 +452,22 @@ __global__ __launch_bounds__(256) void k_rotate(const double2* __restrict__ A, i
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t row = rb * 16 * RT + r * 16 + kl + 4 * q;
-        if (row < N && col < n) C[row * ldc + col] = make_double2(accr[r][c][q], acci[r][c][q]);
+        if (row < N && col < nw) C[row * ldc + col] = make_double2(accr[r][c][q], acci[r][c][q]);
       }
     }
 }
 
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
-                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st) {
-  if (N <= 0 || n <= 0) return hipSuccess;
+                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st, int n_zero) {
+  const int nw = n_zero > n ? n_zero : n;
+  if (N <= 0 || nw <= 0) return hipSuccess;
   constexpr int RT = 2, CT = 3;
-  const int TJ = (n + 15) / 16, CG = (TJ + CT - 1) / CT;
+  const int TJ = (nw + 15) / 16, CG = (TJ + CT - 1) / CT;
   const int64_t tasks = ((N + 16 * RT - 1) / (16 * RT)) * CG;
   hipLaunchKernelGGL((k_rotate<RT, CT>), dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(A), lda, N, m,
                      reinterpret_cast<const double2*>(V), ldv, n, reinterpret_cast<double2*>(C),
-                     ldc);
+                     ldc, nw);
   return hipGetLastError();
 }
 

@@ -71,15 +71,19 @@ hipError_t gram_launch(const double* A, int64_t lda, const double* B, int64_t ld
 hipError_t gram2_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                         int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
                         void* ws, hipStream_t st);
-//   the same, and from the same MFMAs Q1 = A^H conj(B) (m x n; complex
-//   symmetric when A == B) and, with P2, Q2 = A^H conj(A) (may be null)
+//   the same, and from the same MFMAs Q1 = A^H conj(B) (m x n) and, with P2,
+//   Q2 = A^H conj(A) (may be null).  herm_ab: A^H B is Hermitian and A^H
+//   conj(B) complex symmetric by construction (B = S A, S real symmetric), so
+//   only the tiles on and above the diagonal are computed; implied when A == B
 hipError_t gram2c_launch(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t N,
                          int m, int n, double* P1, int64_t ldp1, double* P2, int64_t ldp2,
-                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, void* ws,
-                         hipStream_t st);
-//   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv).
+                         double* Q1, int64_t ldq1, double* Q2, int64_t ldq2, bool herm_ab,
+                         void* ws, hipStream_t st);
+//   C (N x n) = A (N x m) * V (m x n), complex, V small (row-major, ldv);
+//   columns n .. n_zero-1 of C (when n_zero > n) are set to zero in the same pass.
 hipError_t rotate_launch(const double* A, int64_t lda, int64_t N, int m, const double* V,
-                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st);
+                         int64_t ldv, int n, double* C, int64_t ldc, hipStream_t st,
+                         int n_zero = 0);
 //   T (r x n) = S (r x r, real) * Z (r x n, complex); ws of rcgemm_ws_size
 size_t rcgemm_ws_size(int64_t r, int n);
 hipError_t real_complex_gemm(const double* S, int64_t r, const double* Z, int n, double* T,
