@@ -255,16 +255,61 @@ __global__ void k_gather_cond(const int32_t* __restrict__ cond, int64_t nc,
   }
 }
 
-// real N x 3 -> complex N x 3
-__global__ void k_real_to_complex(const double* __restrict__ x, int64_t cnt,
-                                  double2* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) y[i] = make_double2(x[i], 0.0);
+// o^T K o (3 x 3, real; o is N x 3 row-major) for the static tensor N0: one
+// row per thread, (K o)_r in registers, the nine products summed per
+// workgroup (wave sums, then the waves in order) into part[block][9]
+constexpr int kOkoThreads = 256;
+__global__ __launch_bounds__(kOkoThreads) void k_oko_partial(int64_t N,
+                                                             const int32_t* __restrict__ rowptr,
+                                                             const int32_t* __restrict__ colind,
+                                                             const double* __restrict__ val,
+                                                             const double* __restrict__ o,
+                                                             double* __restrict__ part) {
+  __shared__ double sh[kOkoThreads / 64][9];
+  const int64_t r = (int64_t)blockIdx.x * kOkoThreads + threadIdx.x;
+  double y[3] = {0.0, 0.0, 0.0}, orow[3] = {0.0, 0.0, 0.0};
+  if (r < N) {
+    const int b = rowptr[r], e = rowptr[r + 1];
+#pragma unroll 4
+    for (int k = b; k < e; ++k) {
+      const double v = val[k];
+      const int64_t c = colind[k];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) y[j] = fma(v, o[3 * c + j], y[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) orow[i] = o[3 * r + i];
+  }
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double s = wave_sum(orow[i] * y[j]);
+      if (lane == 0) sh[wave][3 * i + j] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kOkoThreads / 64; ++w) s += sh[w][threadIdx.x];
+    part[(size_t)blockIdx.x * 9 + threadIdx.x] = s;
+  }
+}
+
+// No[e] = sum of the partials of entry e (wave e, fixed order), imaginary part 0
+__global__ __launch_bounds__(576) void k_oko_sum(const double* __restrict__ part, int nb,
+                                                 double2* __restrict__ No) {
+  const int lane = __lane_id(), e = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int p = lane; p < nb; p += 64) s += part[(size_t)p * 9 + e];
+  s = wave_sum(s);
+  if (lane == 0) No[e] = make_double2(s, 0.0);
 }
 
 // assemble K_M, A0, C_M, g, E, N0 from the small contractions
 //   KMt (M x M = U^H K U), UhU (M x M), P ((M+3)^2 = Zc^H Zc: C_M, g and E),
-//   No (3 x 3 complex = o^H K o, or NULL)
+//   No (3 x 3, = o^T K o in the real parts, or NULL)
 __global__ void k_assemble(int M, double eps_h, const double2* __restrict__ KMt,
                            const double2* __restrict__ UhU, const double2* __restrict__ P,
                            const double2* __restrict__ No, const double* __restrict__ vol,
@@ -516,8 +561,8 @@ static void proj_layout(int64_t N, int M, int64_t nc, int n_ref, size_t* off) {
   off[1] = o; o = align256(o + (size_t)M * M * 16);         // UhU
   off[2] = o; o = align256(o + (size_t)nc * L * 16);        // Zc
   off[3] = o; o = align256(o + (size_t)L * L * 16);         // P = Zc^H Zc
-  off[4] = o; o = align256(o + (size_t)N * 3 * 16);         // Oc (o as complex)
-  off[5] = o; o = align256(o + (size_t)N * 3 * 16);         // KO
+  off[4] = o; o = align256(o + (size_t)((N + 255) / 256) * 9 * 8);  // o^T K o partials
+  off[5] = o;
   off[6] = o; o = align256(o + 9 * 16);                     // No
   off[7] = o; o = align256(o + (size_t)M * M * 16);         // U^H K U before symmetrising
   off[8] = o; o = align256(o + std::max(gram2c_ws_size(gN, L, L), gram2c_ws_size(gN, M, M)));
@@ -581,8 +626,7 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
   double* UhU = reinterpret_cast<double*>(wsb + off[1]);
   double* Zc = reinterpret_cast<double*>(wsb + off[2]);
   double* P = reinterpret_cast<double*>(wsb + off[3]);
-  double* Oc = reinterpret_cast<double*>(wsb + off[4]);
-  double* KO = reinterpret_cast<double*>(wsb + off[5]);
+  double* OkoPart = reinterpret_cast<double*>(wsb + off[4]);
   double* No = reinterpret_cast<double*>(wsb + off[6]);
   double* KMt = reinterpret_cast<double*>(wsb + off[7]);
   void* gws = wsb + off[8];
@@ -605,15 +649,16 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
   }
   HIP_OK(gram2c_launch(Zc, L, Zc, L, n_c, L, L, P, L, nullptr, 0, TCz, L, nullptr, 0, false, gws,
                        st));
-  // static tensor: o^H K o
+  // static tensor: o^T K o (o real)
   const double2* Nop = nullptr;
   if (o) {
-    const int64_t cnt = N * 3;
-    hipLaunchKernelGGL(k_real_to_complex, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, o,
-                       cnt, reinterpret_cast<double2*>(Oc));
+    const int64_t nb = (N + kOkoThreads - 1) / kOkoThreads;
+    hipLaunchKernelGGL(k_oko_partial, dim3((unsigned)nb), dim3(kOkoThreads), 0, st, N, K->rowptr,
+                       K->colind, K->val, o, OkoPart);
     HIP_OK(hipGetLastError());
-    HIP_OK(spmm_launch(*K, Oc, 3, 3, KO, 3, st));
-    HIP_OK(gram_launch(Oc, 3, KO, 3, N, 3, 3, No, 3, gws, st));
+    hipLaunchKernelGGL(k_oko_sum, dim3(1), dim3(576), 0, st, OkoPart, (int)nb,
+                       reinterpret_cast<double2*>(No));
+    HIP_OK(hipGetLastError());
     Nop = reinterpret_cast<const double2*>(No);
   }
   hipLaunchKernelGGL(k_assemble, dim3(64), dim3(256), 0, st, M, eps_h,

@@ -17,8 +17,28 @@ __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t b
 }
 }  // namespace
 
+// number of k with omega[k] <= x (strict: < x) for ascending omega, by the
+// whole block: a coarse pass over every stride-th entry, then the one stride
+// that holds the boundary
+__device__ int64_t block_count_below(const double* __restrict__ omega, int64_t n, double x,
+                                     bool strict) {
+  const int64_t stride = (n + blockDim.x - 1) / blockDim.x;
+  const int64_t p = (int64_t)threadIdx.x * stride;
+  const bool c = p < n && (strict ? omega[p] < x : omega[p] <= x);
+  const int cnt = __syncthreads_count(c);
+  if (cnt == 0) return 0;
+  const int64_t base = (int64_t)(cnt - 1) * stride, end = min(n, base + stride);
+  int64_t tot = 0;
+  for (int64_t q0 = base + 1; q0 < end; q0 += blockDim.x) {
+    const int64_t q = q0 + threadIdx.x;
+    tot += __syncthreads_count(q < end && (strict ? omega[q] < x : omega[q] <= x));
+  }
+  return base + 1 + tot;
+}
+
 // one block per interval j: snap[j] < w < snap[j+1] (Algorithm 1's interval
-// without its left end, which is a snapshot already)
+// without its left end, which is a snapshot already); omega is ascending, so
+// the interval's frequencies are one contiguous range, found first
 __global__ __launch_bounds__(256) void k_interval_max(const double* __restrict__ omega, int64_t n,
                                                       const double* __restrict__ out,
                                                       const double* __restrict__ snap, int n_snap,
@@ -26,9 +46,11 @@ __global__ __launch_bounds__(256) void k_interval_max(const double* __restrict__
                                                       int64_t* __restrict__ arg) {
   const int j = blockIdx.x;
   const double lo = snap[j], hi = snap[j + 1];
+  const int64_t k0 = block_count_below(omega, n, lo, false);
+  const int64_t k1 = block_count_below(omega, n, hi, true);
   double bv = -INFINITY;
   int64_t bi = -1;
-  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const double w = omega[k];
     const bool in = (w > lo) && (w < hi);
     if (!in) continue;
