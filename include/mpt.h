@@ -431,6 +431,26 @@ typedef struct {
 size_t mpt_pencil_bytes(int M, int n_ref);
 mpt_status mpt_pencil_reduce(mpt_handle h, const mpt_rom* rom, void* buf, size_t bytes,
                              mpt_pencil* out);
+
+/* mpt_project followed by mpt_pencil_reduce in one call (joint basis only):
+ * the same outputs, bit for bit, as the two calls in a row (the rom matrices
+ * as mpt_project writes them, and the pencil in pbuf, pbytes >=
+ * mpt_pencil_bytes(M, n_ref), as mpt_pencil_reduce writes it; alpha_lb is the
+ * pencil's stability constant, > 0).  The reduction needs A0, C_M and g only,
+ * so it runs on a private stream of the handle, forked from and joined back
+ * into the handle's stream by events, beside the certificate data (G, D');
+ * the call stays asynchronous and stream-ordered for the caller.  Both
+ * buffers (ws and pbuf) must stay allocated until the stream has passed the
+ * call.  1 <= M <= 96, 1 <= n_ref <= 64; errors as for the two calls. */
+mpt_status mpt_project_pencil(mpt_handle h, const mpt_csr* K, const double* c, double eps_h,
+                              const double* w, const double* o, const double* vol, double alpha,
+                              const double* U, int64_t ldU, int M,
+                              const int32_t* cond, int64_t n_c, const double* Vt,
+                              const double* lam, int n_ref, const double* s_ref,
+                              double* KM, double* A0, double* CM, double* g, double* G,
+                              double* Dp, double* E, double* N0, double* Y, void* ws,
+                              size_t ws_bytes, void* pbuf, size_t pbytes, double alpha_lb,
+                              mpt_pencil* pen);
 mpt_status mpt_sweep_pencil(mpt_handle h, const mpt_pencil* pen, const double* omega,
                             int64_t n_omega, double* out, double* a_out, int32_t* status);
 

@@ -36,6 +36,10 @@ struct mpt_handle_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
   hipStream_t cap = nullptr;  // private stream used only to record graphs
+  // private stream and events of mpt_project_pencil (the reduction runs beside
+  // the certificate data)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // key of the plan (jobs, per-object arguments, work items) that the last
   // batched pencil call uploaded into its caller's buffer
   std::vector<int64_t> pkey;
@@ -395,6 +399,9 @@ extern "C" mpt_status mpt_destroy(mpt_handle h) {
   else hipDeviceSynchronize();
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->cap) hipStreamDestroy(h->cap);
+  if (h->side) hipStreamDestroy(h->side);
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
   if (h->host_M) hipHostFree(h->host_M);
   delete h;
   return MPT_OK;
@@ -603,7 +610,8 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
                                const int32_t* cond, int64_t n_c, const double* Vt,
                                const double* lam, int n_ref, const double* s_ref, double* KM,
                                double* A0, double* CM, double* g, double* G, double* Dp, double* E,
-                               double* N0, double* Y, void* ws, size_t ws_bytes) {
+                               double* N0, double* Y, void* ws, size_t ws_bytes,
+                               char* pbuf = nullptr) {
   if (!h) return MPT_E_ARG;
   ARG(K && K->rowptr && K->colind && K->val && c && w && vol && U && cond && Vt && lam && s_ref,
       "NULL input");
@@ -667,9 +675,22 @@ static mpt_status project_impl(mpt_handle h, const mpt_csr* K, const double* c, 
                      reinterpret_cast<double2*>(KM), reinterpret_cast<double2*>(A0),
                      reinterpret_cast<double2*>(CM), reinterpret_cast<double2*>(g), E, N0);
   HIP_OK(hipGetLastError());
+  // pencil form requested: its reduction needs A0, C_M and g only, so it runs
+  // on the private stream while this stream computes the certificate data
+  const mpt::PencilJob job{M,  n_ref, A0, CM, KM, G, Dp, s_ref, g, E, N0, pbuf};
+  if (pbuf) {
+    HIP_OK(hipEventRecord(h->ev_fork, st));
+    HIP_OK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    HIP_OK(mpt::pencil_core_launch(job, nullptr, 1, M, h->side));
+    HIP_OK(hipEventRecord(h->ev_join, h->side));
+  }
   // certificate data per reference shift: G_s and D'_s (Lemma 4.1)
   HIP_OK(cert_launch(M, Zc, n_c, Vt, lam, n_ref, s_ref, A0, CM, UhU, TXk, TXu, TCz, eps_h, dirs,
                      G, Dp, cws, st));
+  if (pbuf) {
+    HIP_OK(hipStreamWaitEvent(st, h->ev_join, 0));
+    HIP_OK(mpt::pencil_layout_launch(job, nullptr, 1, n_ref, st));
+  }
   return MPT_OK;
 }
 
@@ -682,6 +703,43 @@ extern "C" mpt_status mpt_project(mpt_handle h, const mpt_csr* K, const double* 
                                   double* E, double* N0, double* Y, void* ws, size_t ws_bytes) {
   return project_impl(h, K, c, eps_h, w, o, vol, alpha, U, ldU, M, nullptr, cond, n_c, Vt, lam,
                       n_ref, s_ref, KM, A0, CM, g, G, Dp, E, N0, Y, ws, ws_bytes);
+}
+
+extern "C" mpt_status mpt_project_pencil(
+    mpt_handle h, const mpt_csr* K, const double* c, double eps_h, const double* w,
+    const double* o, const double* vol, double alpha, const double* U, int64_t ldU, int M,
+    const int32_t* cond, int64_t n_c, const double* Vt, const double* lam, int n_ref,
+    const double* s_ref, double* KM, double* A0, double* CM, double* g, double* G, double* Dp,
+    double* E, double* N0, double* Y, void* ws, size_t ws_bytes, void* pbuf, size_t pbytes,
+    double alpha_lb, mpt_pencil* pen) {
+  if (!h) return MPT_E_ARG;
+  ARG(pbuf != nullptr && pen != nullptr, "NULL pencil buffer/out");
+  ARG(alpha_lb > 0.0, "alpha_lb must be positive");
+  ARG(M >= 1 && M <= 96, "the pencil form takes 1 <= M <= 96");
+  ARG(n_ref >= 1 && n_ref <= mpt::kPenMaxRef, "the pencil form takes 1 <= n_ref <= 64");
+  if (pbytes < mpt::pencil_total_bytes(M, n_ref))
+    return fail(h, MPT_E_NOMEM, "pencil buffer smaller than mpt_pencil_bytes");
+  HIP_OK(hipSetDevice(h->device));
+  if (!h->side) HIP_OK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  if (!h->ev_fork) HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  if (!h->ev_join) HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  mpt_status s = project_impl(h, K, c, eps_h, w, o, vol, alpha, U, ldU, M, nullptr, cond, n_c,
+                              Vt, lam, n_ref, s_ref, KM, A0, CM, g, G, Dp, E, N0, Y, ws,
+                              ws_bytes, static_cast<char*>(pbuf));
+  if (s != MPT_OK) return s;
+  const mpt::PencilLayout L = mpt::pencil_layout(M);
+  char* b = static_cast<char*>(pbuf);
+  pen->M = M;
+  pen->n_ref = n_ref;
+  pen->H = reinterpret_cast<const double*>(b + L.H);
+  pen->T = reinterpret_cast<const double*>(b + L.T);
+  pen->f = reinterpret_cast<const double*>(b + L.f);
+  pen->Z = reinterpret_cast<const double*>(b + L.Z);
+  pen->W = reinterpret_cast<const double*>(b + L.W);
+  pen->S = reinterpret_cast<const double*>(b + L.S);
+  pen->alpha = alpha;
+  pen->alpha_lb = alpha_lb;
+  return MPT_OK;
 }
 
 extern "C" mpt_status mpt_project_dirs(mpt_handle h, const mpt_csr* K, const double* c,

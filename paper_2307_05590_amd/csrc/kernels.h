@@ -202,6 +202,12 @@ PencilArgs pencil_args(const mpt_pencil& pen);
 // array (maxM bounds their M)
 hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
                                 int maxRef, hipStream_t st);
+// its two parts: the reduction (H, T, Q^H g, Z; reads A0, C_M, g only) and
+// the layout of the quadratic-form matrices (reads K_M, C_M, g, E, N0, G, D')
+hipError_t pencil_core_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
+                              hipStream_t st);
+hipError_t pencil_layout_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs,
+                                int maxRef, hipStream_t st);
 // items == nullptr: one object (P) over omega[0, n); else n_items work items
 // (object, first omega, count <= 16, -) of objects with segment width L
 hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,

@@ -609,8 +609,8 @@ static size_t z_lds(int M) {
   return (size_t)M * (M + 1) * sizeof(double2) + (M > kPenLdsM ? 0 : nrot * 3 * sizeof(double));
 }
 
-hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
-                                int maxRef, hipStream_t st) {
+hipError_t pencil_core_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
+                              hipStream_t st) {
   // LDS for the largest requirement among M <= maxM (not monotonic at kPenLdsM)
   const int Ml = maxM < kPenLdsM ? maxM : kPenLdsM;
   size_t lds1 = reduce_lds(Ml), lds2 = z_lds(Ml);
@@ -626,10 +626,20 @@ hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int
   if (e != hipSuccess) return e;
   // one thread per row of Z
   hipLaunchKernelGGL(k_pencil_z, dim3(n_jobs), dim3(maxM > 64 ? 128 : 64), lds2, st, one, jobs);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t pencil_layout_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs,
+                                int maxRef, hipStream_t st) {
   hipLaunchKernelGGL(k_pencil_layout, dim3(3 + 4 * maxRef, n_jobs), dim3(256), 0, st, one, jobs);
   return hipGetLastError();
+}
+
+hipError_t pencil_reduce_launch(const PencilJob& one, const PencilJob* jobs, int n_jobs, int maxM,
+                                int maxRef, hipStream_t st) {
+  hipError_t e = pencil_core_launch(one, jobs, n_jobs, maxM, st);
+  if (e != hipSuccess) return e;
+  return pencil_layout_launch(one, jobs, n_jobs, maxRef, st);
 }
 
 // ------------------------------------------------------------ the sweep

@@ -85,6 +85,8 @@ def lib():
             "mpt_sweep_adjoint_batched": ([P, P, P, I32, P, P, P, P, P, P, P, S], I32),
             "mpt_pencil_bytes": ([I32, I32], S),
             "mpt_pencil_reduce": ([P, P, P, S, P], I32),
+            "mpt_project_pencil": ([P, P, P, D, P, P, P, D, P, I64, I32, P, I64, P, P, I32, P,
+                                    P, P, P, P, P, P, P, P, P, P, S, P, S, D, P], I32),
             "mpt_sweep_pencil": ([P, P, P, I64, P, P, P], I32),
             "mpt_pencil_batched_bytes": ([P, I32, P], S),
             "mpt_tensors_fmm_ws_size": ([I64, I32], S),
@@ -397,6 +399,43 @@ def mpt_pencil_reduce(rom: Rom) -> Pencil:
     st = _Pencil()
     h._check(lib().mpt_pencil_reduce(h.h, C.byref(r), _ptr(buf), nb, C.byref(st)))
     return Pencil(buf, st, rom)
+
+
+def mpt_project_pencil(K: Csr, c, eps_h, w, o, vol, alpha, U, cond, Vt, lam, s_ref,
+                       alpha_lb=ALPHA_LB):
+    """a2 and the pencil reduction in one call (the reduction runs beside the
+    certificate data on a private stream) -> (Rom, Pencil), equal to
+    mpt_project followed by mpt_pencil_reduce."""
+    h = handle(U.device)
+    _dev_check(c, w, o, vol, cond, Vt, lam, s_ref)
+    _dev_check_rows(U)
+    N, M = U.shape
+    nc = cond.numel()
+    nr = s_ref.numel()
+    dev = U.device
+    cd, rd = torch.complex128, torch.float64
+    KM = torch.empty((M, M), dtype=cd, device=dev)
+    A0 = torch.empty_like(KM)
+    CM = torch.empty_like(KM)
+    g = torch.empty((3, M), dtype=cd, device=dev)
+    G = torch.empty((nr, 2 * M + 3, 2 * M + 3), dtype=cd, device=dev)
+    Dp = torch.empty((nr, M, M), dtype=cd, device=dev)
+    E = torch.empty((3, 3), dtype=rd, device=dev)
+    N0 = torch.empty((3, 3), dtype=rd, device=dev)
+    ws = torch.empty(lib().mpt_project_ws_size(N, M, nc, nr), dtype=torch.uint8, device=dev)
+    nb = lib().mpt_pencil_bytes(M, nr)
+    if nb == 0:
+        raise MptError(f"the pencil form takes 1 <= M <= 96 and n_ref <= 64 (M = {M}, n_ref = {nr})")
+    buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    st = _Pencil()
+    k = K.struct()
+    h._check(lib().mpt_project_pencil(
+        h.h, C.byref(k), _ptr(c), float(eps_h), _ptr(w), _ptr(o), _ptr(vol), float(alpha), _ptr(U),
+        _ld(U), M, _ptr(cond), nc, _ptr(Vt), _ptr(lam), nr, _ptr(s_ref), _ptr(KM), _ptr(A0),
+        _ptr(CM), _ptr(g), _ptr(G), _ptr(Dp), _ptr(E), _ptr(N0), None, _ptr(ws), ws.numel(),
+        _ptr(buf), nb, float(alpha_lb), C.byref(st)))
+    rom = Rom(M, KM, A0, CM, g, G, Dp, s_ref, E, N0, float(alpha), float(alpha_lb))
+    return rom, Pencil(buf, st, rom)
 
 
 def mpt_sweep_pencil(pen: Pencil, omega: torch.Tensor, want_a: bool = False):

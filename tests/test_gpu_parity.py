@@ -227,6 +227,40 @@ def test_pencil_empty_bad_args_singular_deterministic(mpt):
 
 
 # ------------------------------------------- full matrix method on q = U a
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("magnetic10", 12), ("ellipsoid16", 70)])
+def test_project_pencil_equals_two_calls(mpt, case, M):
+    """mpt_project_pencil (the reduction forked beside the certificate data)
+    gives exactly mpt_project followed by mpt_pencil_reduce: every rom
+    matrix, the pencil's H, T, f, Z and the sweep outputs (which read the
+    rest of the pencil), bit for bit."""
+    c = getattr(_cases, case)()
+    if M <= c.D.shape[1]:
+        U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    else:  # beyond the snapshots: a random orthonormal basis (the M > 64 reduction)
+        rng = np.random.default_rng(M)
+        N = c.D.shape[0]
+        U = np.linalg.qr(rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M)))[0]
+    ops = c.ops
+    args = (mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
+            _dev(c.w, torch.float64), _dev(c.o, torch.float64), _dev(ops.vol, torch.float64),
+            ops.alpha, _dev(U, torch.complex128), _dev(ops.cond_idx, torch.int32),
+            _dev(c.Vt, torch.float64), _dev(c.lam, torch.float64), _dev(c.s_ref, torch.float64))
+    w = _dev(np.logspace(1, 6, 333), torch.float64)
+    for rep in range(2):  # the second call reuses the handle's private stream and events
+        rom1 = mpt.mpt_project(*args)
+        pen1 = mpt.mpt_pencil_reduce(rom1)
+        rom2, pen2 = mpt.mpt_project_pencil(*args)
+        torch.cuda.synchronize()
+        for name in ("KM", "A0", "CM", "g", "G", "Dp", "E", "N0"):
+            assert torch.equal(getattr(rom1, name), getattr(rom2, name)), name
+        for a, b in zip(pen1.parts(), pen2.parts()):
+            assert torch.equal(a, b)
+        o1, s1 = mpt.mpt_sweep_pencil(pen1, w)
+        o2, s2 = mpt.mpt_sweep_pencil(pen2, w)
+        assert torch.equal(o1, o2) and torch.equal(s1, s2)
+    print(f"{case} M={M}: fused projection + reduction identical", flush=True)
+
+
 @pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("ellipsoid16", 48), ("magnetic10", 12)])
 def test_fmm_matches_oracle_and_reduced_sweep(mpt, case, M):
     """GPU FMM vs the oracle's FMM on the same reduced solutions, and vs the
@@ -417,6 +451,40 @@ def test_spmm_row_blocks_ragged_and_rejected(mpt):
     for bad in (7, -1):
         with pytest.raises(mpt.MptError):
             mpt.mpt_spmm(mpt.Csr.from_scipy(A, row_blocks=bad), Ud)
+
+
+@pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("magnetic10", 12), ("ellipsoid16", 70)])
+def test_project_pencil_equals_two_calls(mpt, case, M):
+    """mpt_project_pencil (the reduction forked beside the certificate data)
+    gives exactly mpt_project followed by mpt_pencil_reduce: every rom
+    matrix, the pencil's H, T, f, Z and the sweep outputs (which read the
+    rest of the pencil), bit for bit."""
+    c = getattr(_cases, case)()
+    if M <= c.D.shape[1]:
+        U = np.linalg.svd(c.D, full_matrices=False)[0][:, :M]
+    else:  # beyond the snapshots: a random orthonormal basis (the M > 64 reduction)
+        rng = np.random.default_rng(M)
+        N = c.D.shape[0]
+        U = np.linalg.qr(rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M)))[0]
+    ops = c.ops
+    args = (mpt.Csr.from_scipy(ops.K), _dev(ops.c, torch.float64), ops.eps_h,
+            _dev(c.w, torch.float64), _dev(c.o, torch.float64), _dev(ops.vol, torch.float64),
+            ops.alpha, _dev(U, torch.complex128), _dev(ops.cond_idx, torch.int32),
+            _dev(c.Vt, torch.float64), _dev(c.lam, torch.float64), _dev(c.s_ref, torch.float64))
+    w = _dev(np.logspace(1, 6, 333), torch.float64)
+    for rep in range(2):  # the second call reuses the handle's private stream and events
+        rom1 = mpt.mpt_project(*args)
+        pen1 = mpt.mpt_pencil_reduce(rom1)
+        rom2, pen2 = mpt.mpt_project_pencil(*args)
+        torch.cuda.synchronize()
+        for name in ("KM", "A0", "CM", "g", "G", "Dp", "E", "N0"):
+            assert torch.equal(getattr(rom1, name), getattr(rom2, name)), name
+        for a, b in zip(pen1.parts(), pen2.parts()):
+            assert torch.equal(a, b)
+        o1, s1 = mpt.mpt_sweep_pencil(pen1, w)
+        o2, s2 = mpt.mpt_sweep_pencil(pen2, w)
+        assert torch.equal(o1, o2) and torch.equal(s1, s2)
+    print(f"{case} M={M}: fused projection + reduction identical", flush=True)
 
 
 @pytest.mark.parametrize("case,M", [("ellipsoid16", 10), ("ellipsoid16", 48), ("magnetic10", 12)])
