@@ -76,12 +76,16 @@ def log(msg):
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_ellipsoid48.md")
+COUNTERS_SHELL = os.path.join(ROOT, "profiles", "counters_shell64_ellipsoid48.md")
 KERNEL_SOURCES = {
     "sweep": ["paper_2307_05590_amd/csrc/sweep_impl.h", "paper_2307_05590_amd/csrc/sweep.hip",
               "paper_2307_05590_amd/csrc/device_util.h"],
     "spmm": ["paper_2307_05590_amd/csrc/spmm.hip", "paper_2307_05590_amd/csrc/device_util.h"],
     "sweep_pencil": ["paper_2307_05590_amd/csrc/pencil.hip",
                      "paper_2307_05590_amd/csrc/device_util.h"],
+    "pencil_stage": ["paper_2307_05590_amd/csrc/pencil.hip",
+                     "paper_2307_05590_amd/csrc/device_util.h"],
+    "spmm64": ["paper_2307_05590_amd/csrc/spmm.hip", "paper_2307_05590_amd/csrc/device_util.h"],
 }
 
 
@@ -94,13 +98,13 @@ def source_digest(kind):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, path=COUNTERS_FILE):
     """HBM bytes per launch of the kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each scaled by what
     the counter reads for a plain 1 GiB copy), or None when the summary is
     missing or the kernel's sources changed since the counters were taken."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             text = f.read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
@@ -899,7 +903,8 @@ def bench_adaptive(args):
                                 "(the reduction timed on its own)" if pencil else kern["kernel"]),
                      "bound": "mfma", "achieved": round(stage_tf, 3), "peak": FP64_MFMA_PEAK_TF,
                      "unit": "TFLOP/s", "frac": round(stage_tf / FP64_MFMA_PEAK_TF, 4),
-                     "traffic": None, "flops_per_unit": round(F),
+                     "traffic": measured_traffic("pencil_stage", COUNTERS_SHELL) if pencil else None,
+                     "flops_per_unit": round(F),
                      "flops_basis": "F(M) = 8/3 M^3 + 76 M^2 + 96 (M+1.5)^2 per omega",
                      "units_per_launch": int(n_omega), "launch_ms": round(sweep_ms, 4)},
         "stage_rooflines": {
@@ -911,7 +916,8 @@ def bench_adaptive(args):
             "spmm": {"kernel": "k_spmm (Y = K U)", "bound": "hbm", "achieved": round(spmm_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(spmm_gbs / HBM_PEAK_GBS, 4),
                      "launch_ms": round(spmm_ms, 4),
-                     "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M)}},
+                     "bytes_per_launch": spmm_bytes(ops.N, ops.K.nnz, M),
+                     "traffic": measured_traffic("spmm64", COUNTERS_SHELL)}},
         "cpu_baseline": cpu,
     }
     return line

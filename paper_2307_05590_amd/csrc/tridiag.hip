@@ -2,7 +2,8 @@
 // accuracy ~ eps ||A||, for the first pass of the POD basis, where the
 // eigenvectors only have to rotate the snapshot Gram close to diagonal:
 //   1. Householder reduction to tridiagonal form, H_k = I - g_k u_k u_k^H
-//      (one workgroup, packed lower triangle in LDS);
+//      (one workgroup, packed lower triangle in LDS; above the LDS budget the
+//      first steps run on a copy in global memory);
 //   2. a diagonal unitary that makes the off-diagonal real;
 //   3. all eigenvalues of the real tridiagonal by multisection on Sturm
 //      counts (every eigenvalue's interval tested at P points per step);
@@ -27,110 +28,142 @@ __device__ __forceinline__ double2 lget(const double2* A, int i, int j) {
 }
 
 // 1. + 2.: d (n), e (n-1, >= 0), phases ph (n), reflectors Hv (row k holds
-// u_k in columns k+1..n-1) and their scalars g (n-2)
-template <bool SHARED>
+// u_k in columns k+1..n-1) and their scalars g (n-2).
+// The packed lower triangle (A[lpos(i - base, j - base)], rows and columns
+// >= base held) lives in LDS when it fits; otherwise the first k0 steps work
+// on a copy in global memory, and at step k0 the trailing triangle (rows and
+// columns >= k0, which then fits) moves into LDS for the remaining steps.
+struct HetrdShared {
+  double2 u[kTriMaxN], p[kTriMaxN], beta[kTriMaxN];
+  double g;
+};
+
+// step k on the triangle A (rows and columns >= base stored)
+__device__ __forceinline__ void hetrd_step(double2* A, int base, int k, int n, HetrdShared& sh,
+                                           double2* __restrict__ Hv, double* __restrict__ gam,
+                                           double* __restrict__ dout) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = __lane_id(), wave = tid >> 6;
+  auto at = [&](int i, int j) -> double2& { return A[lpos(i - base, j - base)]; };  // i >= j
+  const int L = n - k - 1;  // trailing block rows/cols o .. n-1
+  const int o = k + 1;
+  if (wave == 0) {
+    double s = 0.0;
+    for (int i = lane; i < L; i += 64) {
+      const double2 x = at(o + i, k);
+      s += x.x * x.x + x.y * x.y;
+    }
+    s = wave_sum(s);
+    const double alpha = sqrt(s);
+    const double2 x0 = at(o, k);
+    const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+    const bool refl = alpha > 1e-300;
+    double2 th = make_double2(1.0, 0.0);
+    if (ax0 > 0.0) th = make_double2(x0.x / ax0, x0.y / ax0);
+    const double g = refl ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+    for (int i = lane; i < L; i += 64) {
+      double2 x = at(o + i, k);
+      if (i == 0) x = make_double2(x.x + th.x * alpha, x.y + th.y * alpha);
+      if (!refl) x = make_double2(0.0, 0.0);
+      sh.u[i] = x;
+      Hv[(size_t)k * n + o + i] = x;
+    }
+    if (lane == 0) {
+      sh.g = g;
+      gam[k] = g;
+      sh.beta[k] = refl ? make_double2(-th.x * alpha, -th.y * alpha) : x0;
+      dout[k] = at(k, k).x;
+    }
+  }
+  __syncthreads();
+  const double g = sh.g;
+  if (g == 0.0) return;  // uniform: column already reduced
+  // p = g A22 u, eight threads per row
+  const int s8 = tid & 7;
+  for (int i = tid >> 3; i < L; i += nt >> 3) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = s8; j < L; j += 8) {
+      const double2 a = j <= i ? at(o + i, o + j) : cconj(at(o + j, o + i));
+      acc = cfma(acc, a, sh.u[j]);
+    }
+    // sum over the 8 lanes of the row group (DPP inside a half-row)
+    acc.x += dpp_d<kDppXor1>(acc.x, 0.0);
+    acc.y += dpp_d<kDppXor1>(acc.y, 0.0);
+    acc.x += dpp_d<kDppXor2>(acc.x, 0.0);
+    acc.y += dpp_d<kDppXor2>(acc.y, 0.0);
+    acc.x += dpp_d<kDppHalfMirror>(acc.x, 0.0);
+    acc.y += dpp_d<kDppHalfMirror>(acc.y, 0.0);
+    if (s8 == 0) sh.p[i] = make_double2(g * acc.x, g * acc.y);
+  }
+  __syncthreads();
+  // K = g/2 Re(u^H p) (every wave computes it), w = p - K u,
+  // A22 <- A22 - u w^H - w u^H on the lower triangle: thread (r, c) of a
+  // 32 x 32 grid takes rows r + 32 a and, in each, columns c + 32 b <= row
+  double kk = 0.0;
+  for (int i = lane; i < L; i += 64) kk += cmulc(sh.u[i], sh.p[i]).x;
+  kk = 0.5 * g * wave_sum(kk);
+  const int r0 = tid >> 5, c0 = tid & 31;
+  for (int i = r0; i < L; i += nt >> 5) {
+    const double2 ui = sh.u[i], pi = sh.p[i];
+    const double2 wi = make_double2(pi.x - kk * ui.x, pi.y - kk * ui.y);
+    for (int j = c0; j <= i; j += 32) {
+      const double2 uj = sh.u[j], pj = sh.p[j];
+      const double2 wj = make_double2(pj.x - kk * uj.x, pj.y - kk * uj.y);
+      double2& ar = at(o + i, o + j);
+      double2 a = ar;
+      a = cfms(a, ui, cconj(wj));
+      a = cfms(a, wi, cconj(uj));
+      ar = a;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kTriThreads) void k_hetrd(const double2* __restrict__ Ag, int n,
-                                                       double2* __restrict__ Ap,
+                                                       int k0, double2* __restrict__ Ap,
                                                        double2* __restrict__ Hv,
                                                        double* __restrict__ gam,
                                                        double* __restrict__ dout,
                                                        double* __restrict__ eout,
                                                        double2* __restrict__ ph) {
   extern __shared__ double2 smem[];
-  __shared__ double2 u[kTriMaxN], p[kTriMaxN], beta[kTriMaxN];
-  __shared__ double g_sh;
-  double2* A = SHARED ? smem : Ap;
+  __shared__ HetrdShared sh;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = __lane_id(), wave = tid >> 6;
+  double2* A0 = k0 == 0 ? smem : Ap;
   for (int i = tid; i < n * n; i += nt) {
     const int r = i / n, c = i % n;
-    if (r >= c) A[lpos(r, c)] = Ag[i];
+    if (r >= c) A0[lpos(r, c)] = Ag[i];
   }
   __syncthreads();
-  for (int k = 0; k + 2 < n; ++k) {
-    const int L = n - k - 1;  // trailing block rows/cols o .. n-1
-    const int o = k + 1;
-    if (wave == 0) {
-      double s = 0.0;
-      for (int i = lane; i < L; i += 64) {
-        const double2 x = A[lpos(o + i, k)];
-        s += x.x * x.x + x.y * x.y;
-      }
-      s = wave_sum(s);
-      const double alpha = sqrt(s);
-      const double2 x0 = A[lpos(o, k)];
-      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
-      const bool refl = alpha > 1e-300;
-      double2 th = make_double2(1.0, 0.0);
-      if (ax0 > 0.0) th = make_double2(x0.x / ax0, x0.y / ax0);
-      const double g = refl ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
-      for (int i = lane; i < L; i += 64) {
-        double2 x = A[lpos(o + i, k)];
-        if (i == 0) x = make_double2(x.x + th.x * alpha, x.y + th.y * alpha);
-        if (!refl) x = make_double2(0.0, 0.0);
-        u[i] = x;
-        Hv[(size_t)k * n + o + i] = x;
-      }
-      if (lane == 0) {
-        g_sh = g;
-        gam[k] = g;
-        beta[k] = refl ? make_double2(-th.x * alpha, -th.y * alpha) : x0;
-        dout[k] = A[lpos(k, k)].x;
-      }
-    }
-    __syncthreads();
-    const double g = g_sh;
-    if (g == 0.0) continue;  // uniform: column already reduced
-    // p = g A22 u, eight threads per row
-    const int s8 = tid & 7;
-    for (int i = tid >> 3; i < L; i += nt >> 3) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int j = s8; j < L; j += 8) acc = cfma(acc, lget(A, o + i, o + j), u[j]);
-      // sum over the 8 lanes of the row group (DPP inside a half-row)
-      acc.x += dpp_d<kDppXor1>(acc.x, 0.0);
-      acc.y += dpp_d<kDppXor1>(acc.y, 0.0);
-      acc.x += dpp_d<kDppXor2>(acc.x, 0.0);
-      acc.y += dpp_d<kDppXor2>(acc.y, 0.0);
-      acc.x += dpp_d<kDppHalfMirror>(acc.x, 0.0);
-      acc.y += dpp_d<kDppHalfMirror>(acc.y, 0.0);
-      if (s8 == 0) p[i] = make_double2(g * acc.x, g * acc.y);
-    }
-    __syncthreads();
-    // K = g/2 Re(u^H p) (every wave computes it), w = p - K u,
-    // A22 <- A22 - u w^H - w u^H on the lower triangle
-    double kk = 0.0;
-    for (int i = lane; i < L; i += 64) kk += cmulc(u[i], p[i]).x;
-    kk = 0.5 * g * wave_sum(kk);
-    const int nl = L * (L + 1) / 2;
-    for (int e = tid; e < nl; e += nt) {
+  int k = 0;
+  for (; k < k0 && k + 2 < n; ++k) hetrd_step(Ap, 0, k, n, sh, Hv, gam, dout);
+  if (k0 > 0) {  // the trailing triangle, rows and columns >= k0, into LDS
+    const int m0 = n - k0, cnt = m0 * (m0 + 1) / 2;
+    for (int e = tid; e < cnt; e += nt) {
       int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
       while ((i + 1) * (i + 2) / 2 <= e) ++i;
       while (i * (i + 1) / 2 > e) --i;
       const int j = e - i * (i + 1) / 2;
-      const double2 ui = u[i], uj = u[j], pi = p[i], pj = p[j];
-      const double2 wi = make_double2(pi.x - kk * ui.x, pi.y - kk * ui.y);
-      const double2 wj = make_double2(pj.x - kk * uj.x, pj.y - kk * uj.y);
-      double2 a = A[lpos(o + i, o + j)];
-      a = cfms(a, ui, cconj(wj));
-      a = cfms(a, wi, cconj(uj));
-      A[lpos(o + i, o + j)] = a;
+      smem[e] = Ap[lpos(k0 + i, k0 + j)];
     }
     __syncthreads();
   }
+  for (; k + 2 < n; ++k) hetrd_step(smem, k0, k, n, sh, Hv, gam, dout);
   if (tid == 0) {
+    auto at = [&](int i, int j) { return smem[lpos(i - k0, j - k0)]; };
     if (n >= 2) {
-      dout[n - 2] = A[lpos(n - 2, n - 2)].x;
-      beta[n - 2] = A[lpos(n - 1, n - 2)];
+      dout[n - 2] = at(n - 2, n - 2).x;
+      sh.beta[n - 2] = at(n - 1, n - 2);
     }
-    dout[n - 1] = A[lpos(n - 1, n - 1)].x;
+    dout[n - 1] = at(n - 1, n - 1).x;
     double2 f = make_double2(1.0, 0.0);
     ph[0] = f;
-    for (int k = 0; k + 1 < n; ++k) {
-      const double2 b = beta[k];
+    for (int kk = 0; kk + 1 < n; ++kk) {
+      const double2 b = sh.beta[kk];
       const double ab = sqrt(b.x * b.x + b.y * b.y);
-      eout[k] = ab;
+      eout[kk] = ab;
       if (ab > 0.0) f = cmul(f, make_double2(b.x / ab, b.y / ab));
-      ph[k + 1] = f;
+      ph[kk + 1] = f;
     }
   }
 }
@@ -474,13 +507,13 @@ hipError_t tridiag_eig_launch(const double* A, int n, double* V, double* lam, vo
   double2* ph = reinterpret_cast<double2*>(w + L.ph);
   double* Z = reinterpret_cast<double*>(w + L.z);
   const double2* Ag = reinterpret_cast<const double2*>(A);
-  const size_t lds_a = (size_t)n * (n + 1) / 2 * sizeof(double2);
-  if (lds_a <= kTriLdsBudget)
-    hipLaunchKernelGGL((k_hetrd<true>), dim3(1), dim3(kTriThreads), lds_a, st, Ag, n, Ap, Hv, gam,
-                       d, e, ph);
-  else
-    hipLaunchKernelGGL((k_hetrd<false>), dim3(1), dim3(kTriThreads), 0, st, Ag, n, Ap, Hv, gam, d,
-                       e, ph);
+  // k0: the first step whose trailing triangle (rows and columns >= k0) fits
+  // the LDS budget (0: the whole matrix fits)
+  int k0 = 0;
+  while ((size_t)(n - k0) * (n - k0 + 1) / 2 * sizeof(double2) > kTriLdsBudget) ++k0;
+  const size_t lds_a = (size_t)(n - k0) * (n - k0 + 1) / 2 * sizeof(double2);
+  hipLaunchKernelGGL(k_hetrd, dim3(1), dim3(kTriThreads), lds_a, st, Ag, n, k0, Ap, Hv, gam, d, e,
+                     ph);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int nb = (n + kTriWaves - 1) / kTriWaves;
