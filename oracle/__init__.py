@@ -1,7 +1,7 @@
 """Plain FP64 CPU oracle for the MPT reduced-order hot path.
 
 TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test-suite, the smoke check in
-the repository's graft entry point and the CPU baseline leg of the benchmark may
+__graft_entry__.py and the CPU baseline leg of the benchmark may
 import or call anything here.  It shares no code with the GPU library and does
 not import it.
 
