@@ -682,7 +682,7 @@ __device__ __forceinline__ int pair_of(int i, int j) {
 
 
 template <int L, int R>
-__global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
+__global__ __launch_bounds__(256, 3) void k_sweep_pencil(PencilArgs one,
                                                       const PencilArgs* __restrict__ objs,
                                                       const int4* __restrict__ items,
                                                       const double* __restrict__ omega, int64_t n,
@@ -704,11 +704,10 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
     cnt = (int)(n - b0 < kPenBatch ? n - b0 : kPenBatch);
   }
   const int M = P.M, Kp = P.Kp, NTs = P.NTs, NTr = P.NTr;
-  const int tpb0 = P.Mp / 16;
   double2* sY = lds;                                                  // [3][Kp][16]
   double2* sEt = sY + 3 * Kp * kPenBatch;                             // [3][12][16]
-  double* sPart = reinterpret_cast<double*>(sEt + 36 * kPenBatch);    // [5 tpb][6][16]
-  int* sStat = reinterpret_cast<int*>(sPart + (size_t)5 * tpb0 * 6 * kPenBatch);
+  double* sPart = reinterpret_cast<double*>(sEt + 36 * kPenBatch);    // [5][6][16]
+  int* sStat = reinterpret_cast<int*>(sPart + (size_t)5 * 6 * kPenBatch);
   int* sRef = sStat + kPenBatch;   // reference shift of each frequency
   int* sList = sRef + kPenBatch;   // the distinct shifts of the batch, ascending
   int* sNList = sList + kPenBatch;
@@ -947,84 +946,92 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
   }
 
   // ---- 2b. MFMA products with the stacked matrices, contracted at once.
-  // Jobs: the NTs shared tiles, then NTr tiles for each shift of the batch;
-  // a shift's results are kept only for the frequencies that use it. --------
+  // Jobs: one per quadratic-form block (K_M, C_M; then Gxx, H, D' for each
+  // shift of the batch), which takes the block's row tiles in order and sums
+  // their contractions in registers, and one per remaining tile (g; B and F
+  // for each shift); a shift's results are kept only for the frequencies
+  // that use it. --------
   const int nlist = *sNList;
-  const int njobs = NTs + nlist * NTr;
+  const int njobs = 3 + 4 * nlist;
   for (int job = wave; job < njobs; job += 4) {
-    int rt, blk0, kr = -1;  // W tile, first quadratic-form block of its part
-    bool last;
-    if (job < NTs) {
-      rt = job;
-      last = job == NTs - 1;
-      blk0 = 0;
+    int rt0, blk, kr = -1;  // first W tile; quadratic-form block, or -1 for a single tile
+    if (job < 3) {
+      blk = job < 2 ? job : -1;
+      rt0 = job < 2 ? job * tpb : NTs - 1;
     } else {
-      const int u = (job - NTs) / NTr, t = (job - NTs) % NTr;
+      const int u = (job - 3) / 4, q = (job - 3) % 4;
       kr = sList[u];
-      rt = NTs + kr * NTr + t;
-      last = t == NTr - 1;
-      blk0 = 2 * tpb;  // Gxx, H, D' after K_M, C_M
+      blk = q < 3 ? 2 + q : -1;
+      rt0 = NTs + kr * NTr + q * tpb;
     }
-    const int tloc = job < NTs ? job : (job - NTs) % NTr;  // tile within its part
     const int col = wl & 15;
     const bool keep = kr < 0 || (col < cnt && sRef[col] == kr);
-    double4_t ar[3], ai[3];
+    const int ntile = blk >= 0 ? tpb : 1;
+    double acc[6];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      ar[j] = double4_t{0, 0, 0, 0};
-      ai[j] = double4_t{0, 0, 0, 0};
-    }
-    const double2* Wt = P.W + (size_t)rt * KB * 64 + wl;
-    for (int kk = 0; kk < KB; ++kk) {
-      const double2 w = Wt[(size_t)kk * 64];
+    for (int p = 0; p < 6; ++p) acc[p] = 0.0;
+    for (int tt = 0; tt < ntile; ++tt) {
+      double4_t ar[3], ai[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const double2 yv = sY[(j * Kp + kk * 4 + (wl >> 4)) * kPenBatch + (wl & 15)];
-        ar[j] = mfma(w.x, yv.x, ar[j]);
-        ar[j] = mfma(-w.y, yv.y, ar[j]);
-        ai[j] = mfma(w.x, yv.y, ai[j]);
-        ai[j] = mfma(w.y, yv.x, ai[j]);
+        ar[j] = double4_t{0, 0, 0, 0};
+        ai[j] = double4_t{0, 0, 0, 0};
       }
-    }
-    if (!last) {
-      // Re y_i^H (P y_j) for the six pairs i <= j, rows of this tile
-      const int row0 = (tloc % tpb) * 16;
-      double part[6];
+      const double2* Wt = P.W + (size_t)(rt0 + tt) * KB * 64 + wl;
+      for (int kk = 0; kk < KB; ++kk) {
+        const double2 w = Wt[(size_t)kk * 64];
 #pragma unroll
-      for (int p = 0; p < 6; ++p) part[p] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+          const double2 yv = sY[(j * Kp + kk * 4 + (wl >> 4)) * kPenBatch + (wl & 15)];
+          ar[j] = mfma(w.x, yv.x, ar[j]);
+          ar[j] = mfma(-w.y, yv.y, ar[j]);
+          ai[j] = mfma(w.x, yv.y, ai[j]);
+          ai[j] = mfma(w.y, yv.x, ai[j]);
+        }
+      }
+      if (blk >= 0) {
+        // Re y_i^H (P y_j) for the six pairs i <= j, rows of this tile
+        const int row0 = tt * 16;
+        double part[6];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + (wl >> 4) + 4 * v;
-        if (row < M) {
-          double2 yi[3];
+        for (int p = 0; p < 6; ++p) part[p] = 0.0;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) yi[i] = sY[(i * Kp + row) * kPenBatch + (wl & 15)];
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + (wl >> 4) + 4 * v;
+          if (row < M) {
+            double2 yi[3];
 #pragma unroll
-          for (int p = 0; p < 6; ++p) {
-            const int i = kPairI[p], j = kPairJ[p];
-            part[p] = fma(yi[i].x, ar[j][v], part[p]);
-            part[p] = fma(yi[i].y, ai[j][v], part[p]);
+            for (int i = 0; i < 3; ++i) yi[i] = sY[(i * Kp + row) * kPenBatch + (wl & 15)];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+              const int i = kPairI[p], j = kPairJ[p];
+              part[p] = fma(yi[i].x, ar[j][v], part[p]);
+              part[p] = fma(yi[i].y, ai[j][v], part[p]);
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+          double s = part[p] + other16(part[p], wl);
+          s = s + other32(s, wl);
+          acc[p] += s;
+        }
+      } else if (keep) {
+        const int rb = kr < 0 ? 0 : 6;  // rows of sEt: shared tile, then the shift's
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int row = (wl >> 4) + 4 * v;
+          if (row < 6) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              sEt[(j * 12 + rb + row) * kPenBatch + (wl & 15)] = make_double2(ar[j][v], ai[j][v]);
           }
         }
       }
-      const int sb = blk0 + tloc;  // slot block: blk * tpb + tile
+    }
+    if (blk >= 0 && wl < 16 && keep) {
 #pragma unroll
-      for (int p = 0; p < 6; ++p) {
-        double s = part[p] + other16(part[p], wl);
-        s = s + other32(s, wl);
-        if (wl < 16 && keep) sPart[(sb * 6 + p) * kPenBatch + wl] = s;
-      }
-    } else if (keep) {
-      const int rb = kr < 0 ? 0 : 6;  // rows of sEt: shared tile, then the shift's
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int row = (wl >> 4) + 4 * v;
-        if (row < 6) {
-#pragma unroll
-          for (int j = 0; j < 3; ++j)
-            sEt[(j * 12 + rb + row) * kPenBatch + (wl & 15)] = make_double2(ar[j][v], ai[j][v]);
-        }
-      }
+      for (int p = 0; p < 6; ++p) sPart[(blk * 6 + p) * kPenBatch + wl] = acc[p];
     }
   }
   __syncthreads();
@@ -1038,11 +1045,7 @@ __global__ __launch_bounds__(256) void k_sweep_pencil(PencilArgs one,
 #pragma unroll
     for (int blk = 0; blk < 5; ++blk)
 #pragma unroll
-      for (int p = 0; p < 6; ++p) {
-        double s = 0.0;
-        for (int tb = 0; tb < tpb; ++tb) s += sPart[((blk * tpb + tb) * 6 + p) * kPenBatch + w];
-        Q[blk][p] = s;
-      }
+      for (int p = 0; p < 6; ++p) Q[blk][p] = sPart[(blk * 6 + p) * kPenBatch + w];
     auto GA = [&](int i, int j) { return sEt[(j * 12 + i) * kPenBatch + w]; };      // g_i^H a_j
     auto BA = [&](int i, int j) { return sEt[(j * 12 + 6 + i) * kPenBatch + w]; };  // (B a_j)_i
     auto FA = [&](int i, int j) { return sEt[(j * 12 + 9 + i) * kPenBatch + w]; };  // (F a_j)_i
@@ -1107,16 +1110,16 @@ PencilArgs pencil_args(const mpt_pencil& pen) {
   return P;
 }
 
-// Kp: rows of the solutions; tpb: 16-row tiles per M x M block
-static size_t sweep_lds(int Kp, int tpb) {
+// Kp: rows of the solutions
+static size_t sweep_lds(int Kp) {
   return ((size_t)3 * Kp * kPenBatch + 36 * kPenBatch) * sizeof(double2) +
-         (size_t)5 * tpb * 6 * kPenBatch * sizeof(double) + (3 * kPenBatch + 1) * sizeof(int);
+         (size_t)5 * 6 * kPenBatch * sizeof(double) + (3 * kPenBatch + 1) * sizeof(int);
 }
 
 hipError_t pencil_sweep_launch(const PencilArgs& P, const double* omega, int64_t n, double* out,
                                double* a_out, int32_t* status, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sweep_lds(P.Kp, P.Mp / 16);
+  const size_t lds = sweep_lds(P.Kp);
   const dim3 grid((unsigned)((n + kPenBatch - 1) / kPenBatch)), block(256);
   const PencilArgs* no = nullptr;
   const int4* ni = nullptr;
@@ -1140,7 +1143,7 @@ hipError_t pencil_sweep_items_launch(int L, const PencilArgs* objs, const int4* 
                                      int32_t* status, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   // LDS for the largest object of the bucket: Kp <= bucket, tiles <= bucket / 16
-  const size_t lds = sweep_lds(L, L / 16);
+  const size_t lds = sweep_lds(L);
   const dim3 grid((unsigned)n_items), block(256);
   PencilArgs none{};
   double* no_a = nullptr;
