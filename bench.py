@@ -86,6 +86,8 @@ KERNEL_SOURCES = {
     "pencil_stage": ["paper_2307_05590_amd/csrc/pencil.hip",
                      "paper_2307_05590_amd/csrc/device_util.h"],
     "spmm64": ["paper_2307_05590_amd/csrc/spmm.hip", "paper_2307_05590_amd/csrc/device_util.h"],
+    "sweep_e48": ["paper_2307_05590_amd/csrc/sweep_impl.h", "paper_2307_05590_amd/csrc/sweep.hip",
+                  "paper_2307_05590_amd/csrc/device_util.h"],
 }
 
 
@@ -352,7 +354,8 @@ def bench_plain(args):
         roofline = {"kernel": "sweep (k_sweep: reduced LU + solves + tensors + certificates)",
                     "bound": "alu", "achieved": round(sweep_tf, 3), "peak": FP64_VALU_PEAK_TF,
                     "unit": "TFLOP/s", "frac": round(sweep_tf / FP64_VALU_PEAK_TF, 4),
-                    "traffic": measured_traffic("sweep"),
+                    # counters of the 48^3 step (k_sweep<32, false> at M = 31)
+                    "traffic": measured_traffic("sweep_e48", COUNTERS_SHELL) if M <= 32 else None,
                     "flops_per_unit": fpu, "units_per_launch": n_omega,
                     "launch_ms": round(ms["sweep"], 4)}
 
