@@ -82,10 +82,10 @@ __device__ __forceinline__ void hetrd_step(double2* A, int base, int k, int n, H
   const int s8 = tid & 7;
   for (int i = tid >> 3; i < L; i += nt >> 3) {
     double2 acc = make_double2(0.0, 0.0);
-    for (int j = s8; j < L; j += 8) {
-      const double2 a = j <= i ? at(o + i, o + j) : cconj(at(o + j, o + i));
-      acc = cfma(acc, a, sh.u[j]);
-    }
+    // the stored row part (j <= i, contiguous), then the mirrored column part
+    int j = s8;
+    for (; j <= i; j += 8) acc = cfma(acc, at(o + i, o + j), sh.u[j]);
+    for (; j < L; j += 8) acc = cfma(acc, cconj(at(o + j, o + i)), sh.u[j]);
     // sum over the 8 lanes of the row group (DPP inside a half-row)
     acc.x += dpp_d<kDppXor1>(acc.x, 0.0);
     acc.y += dpp_d<kDppXor1>(acc.y, 0.0);
